@@ -1,0 +1,264 @@
+/*
+ * sj.h -- C ABI of libsj, an MI355X (gfx950) implementation of the per-tick
+ * spatial join of moving-object positions against rectangular range queries
+ * described in Lettich, Orlando, Silvestri, Jensen, "Manycore processing of
+ * repeated range queries over massive moving objects observations".
+ *
+ * Problem (Section "Problem setting and statement"): objects o_0..o_{N-1}
+ * send position updates and issue range queries; time is cut into ticks and
+ * at the end of each tick every query issued during the tick is answered on
+ * the last known positions of all objects (Definition 1: an object is in the
+ * result of a query iff its point lies in the closed query rectangle).
+ *
+ * Method (Sections "Index Creation and Indexing in QUAD", "Filtering",
+ * "Bitmap decoding", "Optimizations"): the space is partitioned by a
+ * point-region quadtree whose leaves hold at most th objects; each query is
+ * split into one subquery per leaf it touches, classified covering (the
+ * leaf lies inside the query: its objects are reported without tests) or
+ * intersecting (its objects are tested); results are produced lock-free by a
+ * count pass, an exclusive scan and a write pass.
+ *
+ * Conventions
+ *  - Every pointer named d_* is a device pointer (HBM of the GPU the scene
+ *    was created on); everything else is host memory.
+ *  - All calls are asynchronous on the scene's stream unless stated; input
+ *    buffers must stay valid and unmodified until the stream has passed the
+ *    call.  Calls on one scene must not overlap; distinct scenes are
+ *    independent (and may share a stream).
+ *  - The library allocates no device memory: the caller provides one device
+ *    workspace of sj_workspace_bytes(cfg) bytes (256-byte aligned) at
+ *    creation and owns it; the scene borrows it until sj_scene_destroy.
+ *  - Return values: SJ_OK (0) or a negative SJ_E* code.  Errors found on the
+ *    device (bad ids or coordinates, capacity overflow) are latched in the
+ *    scene and returned by the next call that synchronises
+ *    (sj_fetch_results, sj_stats); sj_last_error gives a message.
+ */
+#ifndef SJ_H
+#define SJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sj_scene sj_scene;
+
+enum sj_status {
+  SJ_OK = 0,
+  SJ_EINVAL = -1,    /* bad argument: null/misaligned pointer, size above the
+                        configured capacity, object id >= capacity_objects */
+  SJ_ENOSPACE = -2,  /* workspace smaller than sj_workspace_bytes(cfg) */
+  SJ_EOVERFLOW = -3, /* a tick produced more subqueries, covering entries or
+                        result ids than configured; nothing partial was
+                        reported for that tick; grow the capacities and run
+                        the tick again (run_tick does not change positions) */
+  SJ_EDATA = -4,     /* non-finite coordinate, or a query with x^a > x^b or
+                        y^a > y^b; such entries are ignored */
+  SJ_EDEVICE = -5,   /* a HIP runtime call failed */
+  SJ_ESTATE = -6     /* call out of order (e.g. fetch before any run_tick) */
+};
+
+/* Configuration flags (sj_config.flags). */
+enum sj_flags {
+  SJ_COVERING = 1u << 0, /* covering-subquery optimisation (Section
+                            "Optimizations"); off = every subquery is tested;
+                            results are identical either way */
+  SJ_REORDER = 1u << 1,  /* task scheduling optimisation: leaves processed
+                            heaviest first, weight = intersecting subqueries x
+                            objects (Section "Optimizations") */
+  SJ_PROFILE = 1u << 2   /* record per-phase device times (sj_phase_times) */
+};
+
+/* Quadtree reuse across ticks (the paper builds the partitioning on the
+ * first tick and builds it again when the distribution changes
+ * significantly). */
+enum sj_rebuild {
+  SJ_REBUILD_AUTO = 0,   /* rebuild on the first tick, after sj_build_index,
+                            every rebuild_period ticks, when a leaf below
+                            l_max held more than 2*th objects on the previous
+                            tick, or when more than 1% of the objects lie
+                            outside the index frame */
+  SJ_REBUILD_ALWAYS = 1, /* rebuild on every tick */
+  SJ_REBUILD_NEVER = 2   /* rebuild only on the first tick and after
+                            sj_build_index */
+};
+
+typedef struct sj_config {
+  uint32_t capacity_objects;    /* N: object ids are 0..N-1 */
+  uint32_t capacity_queries;    /* largest nq of one sj_run_tick */
+  uint64_t capacity_subqueries; /* intersecting subqueries per tick
+                                   (0: 32 * capacity_queries) */
+  uint64_t capacity_covering;   /* covering subqueries per tick
+                                   (0: 32 * capacity_queries) */
+  uint64_t capacity_results;    /* result ids of intersecting subqueries per
+                                   tick (0: 64 * capacity_queries) */
+  uint32_t th_quad;             /* leaf split threshold: a quadrant with more
+                                   than th_quad objects is split (0: 64) */
+  uint32_t th_min;              /* smallest threshold the scene will be built
+                                   with; sizes the leaf table (0: th_quad) */
+  uint32_t l_max;               /* deepest quadtree level, 1..16 (0: 16) */
+  uint32_t flags;               /* sj_flags (SJ_COVERING | SJ_REORDER is the
+                                   paper's configuration) */
+  uint32_t rebuild_policy;      /* sj_rebuild */
+  uint32_t rebuild_period;      /* SJ_REBUILD_AUTO period in ticks (0: 32) */
+} sj_config;
+
+/* Compressed results of the last tick (Sections "Bitmap decoding" and
+ * "Optimizations"): for query k (input order of the tick),
+ *   intersecting part: d_isect_id[d_isect_off[k] .. d_isect_off[k+1])
+ *   covering part: for every c in [d_cov_off[k], d_cov_off[k+1]), leaf
+ *     L = d_cov_leaf[c] contributes all objects
+ *     d_sorted_id[d_leaf_beg[L] .. d_leaf_beg[L+1]).
+ * Order inside a query is unspecified (leaves in Morton order, ids in leaf
+ * order); lists of distinct leaves are disjoint, so the result set is their
+ * concatenation.  A query superseded by a later query of the same object in
+ * the tick, or one rejected as invalid, has an empty result.  Pointers are
+ * device views into the workspace, valid until the next call on the scene. */
+typedef struct sj_results {
+  uint32_t nq;
+  uint32_t n_leaves;
+  uint64_t n_isect_ids;       /* = d_isect_off[nq] */
+  uint64_t n_cov_entries;     /* = d_cov_off[nq] */
+  uint64_t total_pairs;       /* sum over queries of |res(q)| */
+  const uint64_t *d_isect_off; /* [nq + 1] */
+  const uint32_t *d_isect_id;
+  const uint32_t *d_cov_off;   /* [nq + 1] */
+  const uint32_t *d_cov_leaf;
+  const uint32_t *d_leaf_beg;  /* [n_leaves + 1] */
+  const uint32_t *d_sorted_id; /* [n_present] object ids in Morton order */
+} sj_results;
+
+/* Counters of the last tick (read back by sj_stats, which synchronises). */
+typedef struct sj_tick_stats {
+  uint32_t n_present;     /* objects with a position */
+  uint32_t n_leaves;      /* quadtree leaves (including empty ones) */
+  uint32_t n_nodes;       /* internal quadtree nodes */
+  uint32_t l_deep;        /* deepest level holding a leaf */
+  uint32_t th;            /* threshold of the current quadtree */
+  uint32_t rebuilt;       /* 1 if the quadtree was built on this tick */
+  uint32_t n_tasks;       /* leaves with at least one intersecting subquery */
+  uint32_t max_leaf;      /* largest object count of a leaf above l_max */
+  uint64_t n_isect;       /* intersecting subqueries */
+  uint64_t n_cov;         /* covering subqueries */
+  uint64_t n_isect_ids;   /* result ids written by the join */
+  uint64_t cov_pairs;     /* pairs reported through covering leaves */
+  uint64_t tests;         /* containment tests: sum over leaves of
+                             |intersecting subqueries| * |objects| */
+  uint32_t error_bits;    /* latched device error flags of this tick */
+  uint32_t tick;          /* ticks run so far */
+} sj_tick_stats;
+
+/* Phases timed when SJ_PROFILE is set (device time in milliseconds of the
+ * last tick, from events on the scene's stream). */
+enum sj_phase {
+  SJ_PH_UPDATES = 0, /* sj_apply_updates since the previous tick */
+  SJ_PH_INDEX,       /* MBR, Morton codes, radix sort, gather */
+  SJ_PH_BUILD,       /* quadtree construction (0 on ticks that reuse it) */
+  SJ_PH_LEAVES,      /* object ranges of the leaves */
+  SJ_PH_SPLIT,       /* query splitting: count, scans, write */
+  SJ_PH_SCHEDULE,    /* task list (and heaviest-first order) */
+  SJ_PH_JOIN_COUNT,  /* join count pass */
+  SJ_PH_JOIN_SCAN,   /* result offsets */
+  SJ_PH_JOIN_WRITE,  /* join write pass */
+  SJ_PH_COUNT
+};
+
+/* Bytes of device workspace needed by a scene with this configuration. */
+size_t sj_workspace_bytes(const sj_config *cfg);
+
+/* Creates a scene on the current HIP device.  d_workspace: caller-owned
+ * device buffer of at least sj_workspace_bytes(cfg) bytes, 256-byte aligned.
+ * stream: stream all work of the scene is ordered on.  Initialises the
+ * workspace (asynchronously); no object has a position yet. */
+int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes,
+                    hipStream_t stream, sj_scene **out);
+
+/* Releases host-side state (events); the workspace is the caller's. */
+int sj_scene_destroy(sj_scene *scene);
+
+/* Position updates (tick batching): m updates (d_id[k], d_x[k], d_y[k]);
+ * within the tick the last update of an object wins (later call, then later
+ * index).  An object never updated has no position and is in no result.
+ * Updates with id >= capacity_objects (SJ_EINVAL) or a non-finite
+ * coordinate (SJ_EDATA) are ignored and latched. */
+int sj_apply_updates(sj_scene *scene, const uint32_t *d_id, const float *d_x,
+                     const float *d_y, uint32_t m);
+
+/* Marks the quadtree for construction on the next sj_run_tick with split
+ * threshold th (0: keep the current one); th must be >= th_min.  Results
+ * do not depend on the threshold. */
+int sj_build_index(sj_scene *scene, uint32_t th);
+
+/* Closes the tick and answers nq range queries (timeslice semantics: on the
+ * positions after every earlier sj_apply_updates).  Query k is issued by
+ * object d_qid[k]; its rectangle has lower-left corner (d_xa[k], d_ya[k])
+ * and upper-right corner (d_xb[k], d_yb[k]) and may extend beyond the
+ * objects' MBR.  If an object issues several queries in one tick the last
+ * one is answered.  nq <= capacity_queries. */
+int sj_run_tick(sj_scene *scene, const uint32_t *d_qid, const float *d_xa,
+                const float *d_ya, const float *d_xb, const float *d_yb,
+                uint32_t nq);
+
+/* Synchronises the stream and returns views of the compressed results of
+ * the last tick, or the latched error of the tick. */
+int sj_fetch_results(sj_scene *scene, sj_results *out);
+
+/* Expanded results: per-query CSR, covering leaves expanded.  With
+ * d_ids == NULL only *n_pairs is set (the size the caller must provide).
+ * Otherwise writes d_off[nq + 1] and d_ids[total_pairs] (ids of query k in
+ * d_ids[d_off[k] .. d_off[k+1]), unspecified order) if ids_cap suffices,
+ * else returns SJ_EINVAL.  Synchronises. */
+int sj_expand_results(sj_scene *scene, uint64_t *d_off, uint32_t *d_ids,
+                      uint64_t ids_cap, uint64_t *n_pairs);
+
+/* Per-query result size and order-independent pair-set hash
+ * H(q) = sum over id in res(q) of mix64((qid << 32) | id) mod 2^64, mix64
+ * being the SplitMix64 output function; written to d_count[nq],
+ * d_hash[nq].  Asynchronous. */
+int sj_result_hashes(sj_scene *scene, uint64_t *d_count, uint64_t *d_hash);
+
+/* Asynchronously copies counters of the last tick to d_out[8] (device
+ * memory, u64): [0] total pairs, [1] result ids of intersecting subqueries,
+ * [2] pairs reported through covering leaves, [3] intersecting subqueries,
+ * [4] covering subqueries, [5] containment tests, [6] tasks (leaves joined),
+ * [7] latched error bits.  Lets a caller collect per-tick totals without
+ * synchronising. */
+int sj_tick_counters(sj_scene *scene, uint64_t *d_out);
+
+/* Counters of the last tick; synchronises; returns the latched error. */
+int sj_stats(sj_scene *scene, sj_tick_stats *out);
+
+/* Device times of the phases of the last tick (SJ_PROFILE), n <=
+ * SJ_PH_COUNT floats.  Synchronises. */
+int sj_phase_times(sj_scene *scene, float *ms, int n);
+
+/* Internal arrays for tests and tools (device views, valid until the next
+ * call): sorted Morton codes and ids of present objects, leaf table in
+ * Morton order (start code at the finest level, level), and the current
+ * frame. */
+typedef struct sj_index_view {
+  uint32_t n_present, n_leaves, l_deep;
+  float x0, y0;
+  int32_t e;                 /* frame side is 2^e */
+  const uint32_t *d_codes;   /* [n_present] */
+  const uint32_t *d_ids;     /* [n_present] */
+  const uint32_t *d_leaf_start; /* [n_leaves] */
+  const uint32_t *d_leaf_level; /* [n_leaves] */
+  const uint32_t *d_leaf_beg;   /* [n_leaves + 1] */
+  const float *d_px, *d_py;     /* positions by id (NaN: no position) */
+} sj_index_view;
+
+int sj_index_view_get(sj_scene *scene, sj_index_view *out);
+
+/* Message for the last error of the scene (or of creation when NULL). */
+const char *sj_last_error(const sj_scene *scene);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SJ_H */

@@ -1,0 +1,298 @@
+"""ctypes binding of libsj (include/sj.h).  Argument marshalling only: every
+step of the join runs in the library's HIP kernels.  PyTorch provides the
+device memory (the scene's workspace, result buffers) and the stream.
+
+The library must have been built (``paper_1411_3212_amd/build.py``); loading
+fails loudly otherwise -- there is no other implementation behind this API.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, Structure, byref, c_char_p, c_float, c_int, c_int32, c_size_t, \
+    c_uint32, c_uint64, c_void_p
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
+
+SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SJ_COVERING, SJ_REORDER, SJ_PROFILE = 1, 2, 4
+REBUILD = {"auto": 0, "always": 1, "never": 2}
+PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
+          "join_write"]
+_NAMES = {0: "SJ_OK", -1: "SJ_EINVAL", -2: "SJ_ENOSPACE", -3: "SJ_EOVERFLOW", -4: "SJ_EDATA",
+          -5: "SJ_EDEVICE", -6: "SJ_ESTATE"}
+
+
+class SjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SjConfig(Structure):
+    _fields_ = [("capacity_objects", c_uint32), ("capacity_queries", c_uint32),
+                ("capacity_subqueries", c_uint64), ("capacity_covering", c_uint64),
+                ("capacity_results", c_uint64), ("th_quad", c_uint32), ("th_min", c_uint32),
+                ("l_max", c_uint32), ("flags", c_uint32), ("rebuild_policy", c_uint32),
+                ("rebuild_period", c_uint32)]
+
+
+class SjResults(Structure):
+    _fields_ = [("nq", c_uint32), ("n_leaves", c_uint32), ("n_isect_ids", c_uint64),
+                ("n_cov_entries", c_uint64), ("total_pairs", c_uint64),
+                ("d_isect_off", c_void_p), ("d_isect_id", c_void_p), ("d_cov_off", c_void_p),
+                ("d_cov_leaf", c_void_p), ("d_leaf_beg", c_void_p), ("d_sorted_id", c_void_p)]
+
+
+class SjTickStats(Structure):
+    _fields_ = [("n_present", c_uint32), ("n_leaves", c_uint32), ("n_nodes", c_uint32),
+                ("l_deep", c_uint32), ("th", c_uint32), ("rebuilt", c_uint32),
+                ("n_tasks", c_uint32), ("max_leaf", c_uint32), ("n_isect", c_uint64),
+                ("n_cov", c_uint64), ("n_isect_ids", c_uint64), ("cov_pairs", c_uint64),
+                ("tests", c_uint64), ("error_bits", c_uint32), ("tick", c_uint32)]
+
+
+class SjIndexView(Structure):
+    _fields_ = [("n_present", c_uint32), ("n_leaves", c_uint32), ("l_deep", c_uint32),
+                ("x0", c_float), ("y0", c_float), ("e", c_int32),
+                ("d_codes", c_void_p), ("d_ids", c_void_p), ("d_leaf_start", c_void_p),
+                ("d_leaf_level", c_void_p), ("d_leaf_beg", c_void_p), ("d_px", c_void_p),
+                ("d_py", c_void_p)]
+
+
+EXPORTS = {
+    "sj_workspace_bytes": (c_size_t, [POINTER(SjConfig)]),
+    "sj_scene_create": (c_int, [POINTER(SjConfig), c_void_p, c_size_t, c_void_p,
+                                POINTER(c_void_p)]),
+    "sj_scene_destroy": (c_int, [c_void_p]),
+    "sj_apply_updates": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint32]),
+    "sj_build_index": (c_int, [c_void_p, c_uint32]),
+    "sj_run_tick": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_uint32]),
+    "sj_fetch_results": (c_int, [c_void_p, POINTER(SjResults)]),
+    "sj_expand_results": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(c_uint64)]),
+    "sj_result_hashes": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "sj_tick_counters": (c_int, [c_void_p, c_void_p]),
+    "sj_stats": (c_int, [c_void_p, POINTER(SjTickStats)]),
+    "sj_phase_times": (c_int, [c_void_p, POINTER(c_float), c_int]),
+    "sj_index_view_get": (c_int, [c_void_p, POINTER(SjIndexView)]),
+    "sj_last_error": (c_char_p, [c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libsj.so and declares its exports; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise ImportError(f"libsj is not built ({LIB_PATH} missing): run "
+                          "paper_1411_3212_amd/build.py or __graft_entry__.build()")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, handle=None):
+    if rc != SJ_OK:
+        msg = load().sj_last_error(handle)
+        raise SjError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Results:
+    """Compressed results of a tick as torch views into the workspace."""
+
+    def __init__(self, scene: "Scene", r: SjResults):
+        import torch
+        self.nq = int(r.nq)
+        self.n_leaves = int(r.n_leaves)
+        self.n_isect_ids = int(r.n_isect_ids)
+        self.n_cov_entries = int(r.n_cov_entries)
+        self.total_pairs = int(r.total_pairs)
+        v = scene._view
+        self.isect_off = v(r.d_isect_off, self.nq + 1, torch.int64)
+        self.isect_id = v(r.d_isect_id, self.n_isect_ids, torch.int32)
+        self.cov_off = v(r.d_cov_off, self.nq + 1, torch.int32)
+        self.cov_leaf = v(r.d_cov_leaf, self.n_cov_entries, torch.int32)
+        self.leaf_beg = v(r.d_leaf_beg, self.n_leaves + 1, torch.int32)
+        n_present = int(self.leaf_beg[-1].item()) if self.n_leaves else 0
+        self.sorted_id = v(r.d_sorted_id, n_present, torch.int32)
+
+    def to_lists(self):
+        """Per-query result lists (ascending ids), computed on the host from
+        the compressed form (for tests and small cases)."""
+        io = self.isect_off.cpu().numpy()
+        ii = self.isect_id.cpu().numpy().view(np.uint32)
+        co = self.cov_off.cpu().numpy().view(np.uint32)
+        cl = self.cov_leaf.cpu().numpy().view(np.uint32)
+        lb = self.leaf_beg.cpu().numpy().view(np.uint32)
+        sid = self.sorted_id.cpu().numpy().view(np.uint32)
+        out = []
+        for k in range(self.nq):
+            parts = [ii[io[k]:io[k + 1]]]
+            for c in cl[co[k]:co[k + 1]]:
+                parts.append(sid[lb[c]:lb[c + 1]])
+            out.append(np.sort(np.concatenate(parts)).tolist() if parts else [])
+        return out
+
+
+class Scene:
+    """One moving-object set joined against range queries tick after tick.
+
+    Inputs are torch CUDA tensors (uint32/int32 ids, float32 coordinates).
+    """
+
+    def __init__(self, capacity_objects: int, capacity_queries: int, *, th: int = 64,
+                 th_min: int = 0, l_max: int = 16, covering: bool = True, reorder: bool = True,
+                 rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
+                 capacity_covering: int = 0, capacity_results: int = 0, profile: bool = False,
+                 device=None, stream=None):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device if device is not None else "cuda")
+        flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
+                (SJ_PROFILE if profile else 0)
+        self.cfg = SjConfig(capacity_objects, capacity_queries, capacity_subqueries,
+                            capacity_covering, capacity_results, th, th_min, l_max, flags,
+                            REBUILD[rebuild], rebuild_period)
+        nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
+        if nbytes == 0:
+            raise SjError(SJ_EINVAL, "invalid configuration")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        rc = self._lib.sj_scene_create(byref(self.cfg), _ptr(self.ws), nbytes,
+                                       c_void_p(self.stream.cuda_stream), byref(h))
+        _check(rc, None)
+        self.handle = h
+        self._keep = []
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.ws.numel())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.sj_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _view(self, ptr, count, dtype):
+        import torch
+        item = torch.empty((), dtype=dtype).element_size()
+        if count == 0 or not ptr:
+            return torch.empty(0, dtype=dtype, device=self.device)
+        off = int(ptr) - self.ws.data_ptr()
+        assert 0 <= off and off + count * item <= self.ws.numel(), "view outside the workspace"
+        return self.ws[off:off + count * item].view(dtype)
+
+    @staticmethod
+    def _dev(t, dtype, n=None):
+        assert t.is_cuda and t.is_contiguous() and t.dtype == dtype, (t.dtype, dtype)
+        if n is not None:
+            assert t.numel() == n
+        return t
+
+    def apply_updates(self, ids, x, y):
+        import torch
+        m = ids.numel()
+        ids = self._dev(ids, ids.dtype if ids.dtype in (torch.int32, torch.uint32) else torch.int32)
+        self._dev(x, torch.float32, m)
+        self._dev(y, torch.float32, m)
+        _check(self._lib.sj_apply_updates(self.handle, _ptr(ids), _ptr(x), _ptr(y), m), self.handle)
+        self._keep = [ids, x, y]
+
+    def build_index(self, th: int = 0):
+        _check(self._lib.sj_build_index(self.handle, th), self.handle)
+
+    def run_tick(self, qid, xa, ya, xb, yb):
+        import torch
+        nq = qid.numel()
+        qid = self._dev(qid, qid.dtype if qid.dtype in (torch.int32, torch.uint32) else torch.int32)
+        for t in (xa, ya, xb, yb):
+            self._dev(t, torch.float32, nq)
+        _check(self._lib.sj_run_tick(self.handle, _ptr(qid), _ptr(xa), _ptr(ya), _ptr(xb),
+                                     _ptr(yb), nq), self.handle)
+        self._keep = [qid, xa, ya, xb, yb]
+
+    def fetch(self) -> Results:
+        r = SjResults()
+        _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
+        return Results(self, r)
+
+    def expand(self):
+        """(off[nq+1] int64, ids int32) with covering leaves expanded."""
+        import torch
+        n = c_uint64()
+        _check(self._lib.sj_expand_results(self.handle, None, None, 0, byref(n)), self.handle)
+        r = SjResults()
+        _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
+        off = torch.empty(int(r.nq) + 1, dtype=torch.int64, device=self.device)
+        ids = torch.empty(max(int(n.value), 1), dtype=torch.int32, device=self.device)
+        _check(self._lib.sj_expand_results(self.handle, _ptr(off), _ptr(ids), ids.numel(),
+                                           byref(n)), self.handle)
+        return off, ids[:int(n.value)]
+
+    def hashes(self):
+        """Per-query (count, pair-set hash) as int64 tensors (hash bits are
+        the unsigned 64-bit value)."""
+        import torch
+        r = SjResults()
+        _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
+        cnt = torch.empty(max(int(r.nq), 1), dtype=torch.int64, device=self.device)
+        h = torch.empty(max(int(r.nq), 1), dtype=torch.int64, device=self.device)
+        _check(self._lib.sj_result_hashes(self.handle, _ptr(cnt), _ptr(h)), self.handle)
+        return cnt[:r.nq], h[:r.nq]
+
+    def counters_into(self, out):
+        """Enqueues a copy of the last tick's 8 counters into ``out`` (an
+        int64 CUDA tensor of 8 elements, or a view of a larger one)."""
+        import torch
+        assert out.is_cuda and out.dtype == torch.int64 and out.numel() >= 8
+        _check(self._lib.sj_tick_counters(self.handle, _ptr(out)), self.handle)
+
+    def stats(self, check: bool = True) -> dict:
+        s = SjTickStats()
+        rc = self._lib.sj_stats(self.handle, byref(s))
+        if check:
+            _check(rc, self.handle)
+        d = {k: int(getattr(s, k)) for k, _ in SjTickStats._fields_}
+        d["status"] = rc
+        return d
+
+    def phase_times(self) -> dict:
+        buf = (c_float * len(PHASES))()
+        _check(self._lib.sj_phase_times(self.handle, buf, len(PHASES)), self.handle)
+        return {k: float(buf[i]) for i, k in enumerate(PHASES)}
+
+    def index_view(self) -> dict:
+        import torch
+        v = SjIndexView()
+        _check(self._lib.sj_index_view_get(self.handle, byref(v)), self.handle)
+        n, L = int(v.n_present), int(v.n_leaves)
+        return dict(n_present=n, n_leaves=L, l_deep=int(v.l_deep), x0=float(v.x0),
+                    y0=float(v.y0), e=int(v.e),
+                    codes=self._view(v.d_codes, n, torch.int32),
+                    ids=self._view(v.d_ids, n, torch.int32),
+                    leaf_start=self._view(v.d_leaf_start, L, torch.int32),
+                    leaf_level=self._view(v.d_leaf_level, L, torch.int32),
+                    leaf_beg=self._view(v.d_leaf_beg, L + 1, torch.int32),
+                    px=self._view(v.d_px, self.cfg.capacity_objects, torch.float32),
+                    py=self._view(v.d_py, self.cfg.capacity_objects, torch.float32))

@@ -1,0 +1,486 @@
+// C ABI of libsj (declared in include/sj.h): scene lifecycle, workspace
+// layout, and the host side of the tick pipeline.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sj.h"
+#include "sj_device.h"
+#include "sj_kernels.h"
+
+using sj::Bufs;
+using sj::Ctl;
+
+struct sj_scene {
+  sj_config cfg;
+  Bufs B;
+  uint8_t *ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  int device;
+  uint32_t th, l_max, period;
+  uint32_t last_nq;
+  const uint32_t *last_qid;
+  bool ticked;
+  bool prof;
+  bool upd_open;  // an update event interval is open since the last tick
+  hipEvent_t ev[SJ_PH_COUNT + 2];
+  hipEvent_t ev_u0, ev_u1;
+  Ctl host_ctl;
+  char err[256];
+};
+
+static char g_create_err[256] = "";
+
+namespace {
+
+struct Derived {
+  uint32_t N, Q, th, th_min, l_max, period;
+  uint64_t S, C, R;
+  uint32_t LCAP, NCAP, FCAP;
+};
+
+int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
+  if (!cfg) {
+    snprintf(msg, msz, "null config");
+    return SJ_EINVAL;
+  }
+  d->N = cfg->capacity_objects;
+  d->Q = cfg->capacity_queries;
+  if (d->N == 0 || d->N > 0x7fffffffu) {
+    snprintf(msg, msz, "capacity_objects must be in 1..2^31-1");
+    return SJ_EINVAL;
+  }
+  if (d->Q == 0 || d->Q > 0x7fffffffu) {
+    snprintf(msg, msz, "capacity_queries must be in 1..2^31-1");
+    return SJ_EINVAL;
+  }
+  d->S = cfg->capacity_subqueries ? cfg->capacity_subqueries : 32ull * d->Q;
+  d->C = cfg->capacity_covering ? cfg->capacity_covering : 32ull * d->Q;
+  d->R = cfg->capacity_results ? cfg->capacity_results : 256ull * d->Q;
+  if (d->S >= 0xffffffffull || d->C >= 0xffffffffull) {
+    snprintf(msg, msz, "subquery and covering capacities must be below 2^32-1");
+    return SJ_EINVAL;
+  }
+  d->th = cfg->th_quad ? cfg->th_quad : 64u;
+  d->th_min = cfg->th_min ? cfg->th_min : d->th;
+  if (d->th_min > d->th) {
+    snprintf(msg, msz, "th_min must not exceed th_quad");
+    return SJ_EINVAL;
+  }
+  d->l_max = cfg->l_max ? cfg->l_max : 16u;
+  if (d->l_max > 16u) {
+    snprintf(msg, msz, "l_max must be in 1..16");
+    return SJ_EINVAL;
+  }
+  d->period = cfg->rebuild_period ? cfg->rebuild_period : 32u;
+  if (cfg->rebuild_policy > SJ_REBUILD_NEVER) {
+    snprintf(msg, msz, "unknown rebuild policy");
+    return SJ_EINVAL;
+  }
+  // Split nodes at level l are disjoint and hold more than th_min objects
+  // each, and there are at most 4^l of them: bound the tree by that.
+  const uint64_t per = (uint64_t)d->N / ((uint64_t)d->th_min + 1u);
+  uint64_t splits = 1, fmax = 1, p4 = 1;
+  for (uint32_t l = 1; l < d->l_max; ++l) {
+    p4 *= 4u;
+    const uint64_t c = p4 < per ? p4 : per;
+    splits += c;
+    if (c > fmax) fmax = c;
+  }
+  const uint64_t leaves = 3u * splits + 1u;
+  if (leaves >= 0x7fffffffull) {
+    snprintf(msg, msz, "quadtree bound too large: raise th_min");
+    return SJ_EINVAL;
+  }
+  d->LCAP = (uint32_t)leaves;
+  d->NCAP = (uint32_t)splits;
+  d->FCAP = (uint32_t)fmax;
+  return SJ_OK;
+}
+
+struct Carver {
+  uint8_t *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(uint64_t count) {
+    off = (off + 255u) & ~(size_t)255u;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += (size_t)count * sizeof(T);
+    return p;
+  }
+};
+
+size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
+  Carver c{base};
+  Bufs b{};
+  const uint64_t N = d.N, Q = d.Q, L = d.LCAP;
+  b.ctl = c.take<Ctl>(1);
+  b.px = c.take<float>(N);
+  b.py = c.take<float>(N);
+  b.ustamp = c.take<uint64_t>(N);
+  b.qstamp = c.take<uint64_t>(N);
+  b.keyA = c.take<uint32_t>(N);
+  b.valA = c.take<uint32_t>(N);
+  b.keyB = c.take<uint32_t>(N);
+  b.valB = c.take<uint32_t>(N);
+  b.sxy = c.take<float2>(N);
+  b.blk = c.take<uint32_t>(sj::kChunkBlocks);
+  b.part = c.take<uint64_t>(sj::kChunkBlocks);
+  b.hist = c.take<uint32_t>(256u * sj::kChunkBlocks);
+  b.tot = c.take<uint32_t>(256);
+  b.n32 = c.take<uint32_t>(4);
+  b.front[0] = c.take<uint4>(d.FCAP);
+  b.front[1] = c.take<uint4>(d.FCAP);
+  b.lstart = c.take<uint32_t>(L);
+  b.llevel = c.take<uint32_t>(L);
+  b.lstart2 = c.take<uint32_t>(L);
+  b.llevel2 = c.take<uint32_t>(L);
+  b.nopen = c.take<uint32_t>(L);
+  b.node_off = c.take<uint32_t>(L + 1);
+  b.nodes = c.take<uint4>(d.NCAP);
+  b.leaf_beg = c.take<uint32_t>(L + 1);
+  b.leaf_nsq = c.take<uint32_t>(L);
+  b.leaf_sqoff = c.take<uint32_t>(L + 1);
+  b.tflag = c.take<uint32_t>(L);
+  b.toff = c.take<uint32_t>(L + 1);
+  b.tasks = c.take<uint32_t>(L);
+  b.tkey = c.take<uint32_t>(L);
+  b.tasks2 = c.take<uint32_t>(L);
+  b.tkey2 = c.take<uint32_t>(L);
+  b.qrect = c.take<float4>(Q);
+  b.q_ni = c.take<uint32_t>(Q);
+  b.q_nc = c.take<uint32_t>(Q);
+  b.q_ioff = c.take<uint32_t>(Q + 1);
+  b.q_coff = c.take<uint32_t>(Q + 1);
+  b.q_roff = c.take<uint64_t>(Q + 1);
+  b.sq_q = c.take<uint32_t>(d.S);
+  b.sq_s = c.take<uint32_t>(d.S);
+  b.sq_cnt = c.take<uint32_t>(d.S);
+  b.res_off = c.take<uint64_t>(d.S + 1);
+  b.cov_leaf = c.take<uint32_t>(d.C);
+  b.res_ids = c.take<uint32_t>(d.R);
+  b.N = d.N;
+  b.Q = d.Q;
+  b.LCAP = d.LCAP;
+  b.NCAP = d.NCAP;
+  b.FCAP = d.FCAP;
+  b.S = d.S;
+  b.C = d.C;
+  b.R = d.R;
+  if (B) *B = b;
+  return (c.off + 255u) & ~(size_t)255u;
+}
+
+int fail(sj_scene *s, int code, const char *what) {
+  if (s) snprintf(s->err, sizeof s->err, "%s", what);
+  return code;
+}
+
+int hip_fail(sj_scene *s, hipError_t e, const char *where) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  return fail(s, SJ_EDEVICE, buf);
+}
+
+int status_of(sj_scene *s, uint32_t bits) {
+  if (bits & sj::kErrOverflow) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "capacity exceeded (flags 0x%x): subqueries %llu covering %llu "
+             "result ids %llu", bits, (unsigned long long)s->host_ctl.n_isect,
+             (unsigned long long)s->host_ctl.n_cov, (unsigned long long)s->host_ctl.n_res);
+    return fail(s, SJ_EOVERFLOW, buf);
+  }
+  if (bits & (sj::kErrUpdId | sj::kErrQueryId))
+    return fail(s, SJ_EINVAL, "object id >= capacity_objects in an update or a query");
+  if (bits & (sj::kErrUpdCoord | sj::kErrQueryRect))
+    return fail(s, SJ_EDATA, "non-finite coordinate or inverted query rectangle (ignored)");
+  return SJ_OK;
+}
+
+int sync_ctl(sj_scene *s) {
+  hipError_t e = hipMemcpyAsync(&s->host_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+                                s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+  return SJ_OK;
+}
+
+void record(sj_scene *s, int i) {
+  if (s->prof) (void)hipEventRecord(s->ev[i], s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sj_workspace_bytes(const sj_config *cfg) {
+  Derived d;
+  char msg[256];
+  if (derive(cfg, &d, msg, sizeof msg) != SJ_OK) return 0;
+  return carve(d, nullptr, nullptr);
+}
+
+int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hipStream_t stream,
+                    sj_scene **out) {
+  if (!out) return SJ_EINVAL;
+  *out = nullptr;
+  Derived d;
+  int rc = derive(cfg, &d, g_create_err, sizeof g_create_err);
+  if (rc != SJ_OK) return rc;
+  const size_t need = carve(d, nullptr, nullptr);
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u)) {
+    snprintf(g_create_err, sizeof g_create_err, "workspace must be a 256-byte aligned device pointer");
+    return SJ_EINVAL;
+  }
+  if (ws_bytes < need) {
+    snprintf(g_create_err, sizeof g_create_err, "workspace has %zu bytes, needs %zu", ws_bytes,
+             need);
+    return SJ_ENOSPACE;
+  }
+  sj_scene *s = new (std::nothrow) sj_scene();
+  if (!s) return SJ_EINVAL;
+  s->cfg = *cfg;
+  s->ws = (uint8_t *)d_workspace;
+  s->ws_bytes = ws_bytes;
+  s->stream = stream;
+  s->th = d.th;
+  s->l_max = d.l_max;
+  s->period = d.period;
+  s->prof = (cfg->flags & SJ_PROFILE) != 0;
+  (void)hipGetDevice(&s->device);
+  carve(d, s->ws, &s->B);
+  if (s->prof) {
+    bool ok = true;
+    for (auto &ev : s->ev) ok = ok && hipEventCreate(&ev) == hipSuccess;
+    ok = ok && hipEventCreate(&s->ev_u0) == hipSuccess;
+    ok = ok && hipEventCreate(&s->ev_u1) == hipSuccess;
+    if (!ok) {
+      snprintf(g_create_err, sizeof g_create_err, "hipEventCreate failed");
+      delete s;
+      return SJ_EDEVICE;
+    }
+  }
+  sj::launch_ctl_init(s->B.ctl, d.th, stream);
+  sj::launch_fill_u32((uint32_t *)s->B.px, d.N, 0x7fc00000u, stream);  // NaN: no position
+  sj::launch_fill_u32((uint32_t *)s->B.py, d.N, 0x7fc00000u, stream);
+  sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
+  sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    snprintf(g_create_err, sizeof g_create_err, "kernel launch: %s", hipGetErrorString(e));
+    delete s;
+    return SJ_EDEVICE;
+  }
+  *out = s;
+  return SJ_OK;
+}
+
+int sj_scene_destroy(sj_scene *s) {
+  if (!s) return SJ_EINVAL;
+  if (s->prof) {
+    for (auto &e : s->ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(s->ev_u0);
+    (void)hipEventDestroy(s->ev_u1);
+  }
+  delete s;
+  return SJ_OK;
+}
+
+int sj_apply_updates(sj_scene *s, const uint32_t *d_id, const float *d_x, const float *d_y,
+                     uint32_t m) {
+  if (!s) return SJ_EINVAL;
+  if (m == 0) return SJ_OK;
+  if (!d_id || !d_x || !d_y || ((uintptr_t)d_id & 3u) || ((uintptr_t)d_x & 3u) ||
+      ((uintptr_t)d_y & 3u))
+    return fail(s, SJ_EINVAL, "apply_updates: null or misaligned pointer");
+  if (s->prof && !s->upd_open) {
+    (void)hipEventRecord(s->ev_u0, s->stream);
+    s->upd_open = true;
+  }
+  sj::launch_updates(s->B, d_id, d_x, d_y, m, s->stream);
+  if (s->prof) (void)hipEventRecord(s->ev_u1, s->stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "apply_updates launch");
+}
+
+int sj_build_index(sj_scene *s, uint32_t th) {
+  if (!s) return SJ_EINVAL;
+  const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
+  if (th && th < th_min) return fail(s, SJ_EINVAL, "build_index: th below th_min");
+  sj::launch_request_build(s->B.ctl, th, s->stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "build_index launch");
+}
+
+int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
+                const float *d_xb, const float *d_yb, uint32_t nq) {
+  if (!s) return SJ_EINVAL;
+  if (nq > s->B.Q) return fail(s, SJ_EINVAL, "run_tick: nq above capacity_queries");
+  if (nq && (!d_qid || !d_xa || !d_ya || !d_xb || !d_yb || ((uintptr_t)d_qid & 3u) ||
+             ((uintptr_t)d_xa & 3u) || ((uintptr_t)d_ya & 3u) || ((uintptr_t)d_xb & 3u) ||
+             ((uintptr_t)d_yb & 3u)))
+    return fail(s, SJ_EINVAL, "run_tick: null or misaligned pointer");
+  const hipStream_t st = s->stream;
+  const uint32_t flags = s->cfg.flags;
+  record(s, 0);
+  sj::launch_index(s->B, s->cfg.rebuild_policy, s->period, st);
+  record(s, 1);
+  sj::launch_build(s->B, s->l_max, st);
+  record(s, 2);
+  sj::launch_leaves(s->B, s->l_max, st);
+  record(s, 3);
+  sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  record(s, 4);
+  sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, st);
+  record(s, 5);
+  sj::launch_join_count(s->B, st);
+  record(s, 6);
+  sj::launch_join_scan(s->B, s->B.R, st);
+  record(s, 7);
+  sj::launch_join_write(s->B, st);
+  record(s, 8);
+  sj::launch_finish(s->B, nq, st);
+  record(s, 9);
+  s->last_nq = nq;
+  s->last_qid = d_qid;
+  s->ticked = true;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "run_tick launch");
+}
+
+int sj_tick_counters(sj_scene *s, uint64_t *d_out) {
+  if (!s || !d_out || ((uintptr_t)d_out & 7u)) return SJ_EINVAL;
+  sj::launch_counters(s->B, d_out, s->stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "tick_counters launch");
+}
+
+int sj_stats(sj_scene *s, sj_tick_stats *out) {
+  if (!s || !out) return SJ_EINVAL;
+  int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  const Ctl &c = s->host_ctl;
+  memset(out, 0, sizeof *out);
+  out->n_present = c.n_present;
+  out->n_leaves = c.n_leaves;
+  out->n_nodes = (c.n_leaves > 0) ? (c.n_leaves - 1) / 3 : 0;
+  out->l_deep = c.l_deep;
+  out->th = c.th_cur;
+  out->rebuilt = c.rebuild;
+  out->n_tasks = c.n_tasks;
+  out->max_leaf = c.max_leaf;
+  out->n_isect = c.n_isect;
+  out->n_cov = c.n_cov;
+  out->n_isect_ids = c.n_res;
+  out->cov_pairs = c.cov_pairs;
+  out->tests = c.tests;
+  out->error_bits = c.err;
+  out->tick = c.tick;
+  return s->ticked ? status_of(s, c.err) : SJ_OK;
+}
+
+int sj_fetch_results(sj_scene *s, sj_results *out) {
+  if (!s || !out) return SJ_EINVAL;
+  if (!s->ticked) return fail(s, SJ_ESTATE, "fetch_results before run_tick");
+  int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  const Ctl &c = s->host_ctl;
+  memset(out, 0, sizeof *out);
+  const bool ok = c.go_join != 0;
+  out->nq = s->last_nq;
+  out->n_leaves = c.n_leaves;
+  out->n_isect_ids = ok ? c.n_res : 0;
+  out->n_cov_entries = ok ? c.n_cov : 0;
+  out->total_pairs = ok ? c.n_res + c.cov_pairs : 0;
+  out->d_isect_off = s->B.q_roff;
+  out->d_isect_id = s->B.res_ids;
+  out->d_cov_off = s->B.q_coff;
+  out->d_cov_leaf = s->B.cov_leaf;
+  out->d_leaf_beg = s->B.leaf_beg;
+  out->d_sorted_id = s->B.valA;
+  return status_of(s, c.err);
+}
+
+int sj_result_hashes(sj_scene *s, uint64_t *d_count, uint64_t *d_hash) {
+  if (!s || !d_count || !d_hash) return SJ_EINVAL;
+  if (!s->ticked) return fail(s, SJ_ESTATE, "result_hashes before run_tick");
+  sj::launch_hash(s->B, s->last_nq, s->last_qid, d_count, d_hash, s->stream);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "result_hashes launch");
+}
+
+int sj_expand_results(sj_scene *s, uint64_t *d_off, uint32_t *d_ids, uint64_t ids_cap,
+                      uint64_t *n_pairs) {
+  if (!s) return SJ_EINVAL;
+  if (!s->ticked) return fail(s, SJ_ESTATE, "expand_results before run_tick");
+  int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  const Ctl &c = s->host_ctl;
+  const uint64_t total = c.go_join ? c.n_res + c.cov_pairs : 0;
+  if (n_pairs) *n_pairs = total;
+  rc = status_of(s, c.err);
+  if (rc == SJ_EOVERFLOW) return rc;
+  if (!d_ids) return SJ_OK;
+  if (!d_off || ids_cap < total) return fail(s, SJ_EINVAL, "expand_results: buffer too small");
+  sj::launch_expand_count(s->B, s->last_nq, d_off, s->stream);
+  sj::launch_expand(s->B, s->last_nq, d_off, d_ids, s->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "expand_results launch");
+  e = hipStreamSynchronize(s->stream);
+  return e == hipSuccess ? rc : hip_fail(s, e, "expand_results sync");
+}
+
+int sj_phase_times(sj_scene *s, float *ms, int n) {
+  if (!s || !ms || n < 0) return SJ_EINVAL;
+  if (!s->prof) return fail(s, SJ_ESTATE, "scene created without SJ_PROFILE");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "phase_times sync");
+  float t[SJ_PH_COUNT] = {0};
+  if (s->upd_open) (void)hipEventElapsedTime(&t[SJ_PH_UPDATES], s->ev_u0, s->ev_u1);
+  // events 0..9 bracket: index, build, leaves, split, schedule, join count,
+  // join scan, join write, finish (counted with the join scan)
+  float d[9];
+  for (int i = 0; i < 9; ++i) (void)hipEventElapsedTime(&d[i], s->ev[i], s->ev[i + 1]);
+  t[SJ_PH_INDEX] = d[0];
+  t[SJ_PH_BUILD] = d[1];
+  t[SJ_PH_LEAVES] = d[2];
+  t[SJ_PH_SPLIT] = d[3];
+  t[SJ_PH_SCHEDULE] = d[4];
+  t[SJ_PH_JOIN_COUNT] = d[5];
+  t[SJ_PH_JOIN_SCAN] = d[6] + d[8];
+  t[SJ_PH_JOIN_WRITE] = d[7];
+  for (int i = 0; i < n && i < SJ_PH_COUNT; ++i) ms[i] = t[i];
+  s->upd_open = false;
+  return SJ_OK;
+}
+
+int sj_index_view_get(sj_scene *s, sj_index_view *out) {
+  if (!s || !out) return SJ_EINVAL;
+  int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  const Ctl &c = s->host_ctl;
+  memset(out, 0, sizeof *out);
+  out->n_present = c.n_present;
+  out->n_leaves = c.n_leaves;
+  out->l_deep = c.l_deep;
+  out->x0 = c.x0;
+  out->y0 = c.y0;
+  out->e = c.e;
+  out->d_codes = s->B.keyA;
+  out->d_ids = s->B.valA;
+  out->d_leaf_start = s->B.lstart;
+  out->d_leaf_level = s->B.llevel;
+  out->d_leaf_beg = s->B.leaf_beg;
+  out->d_px = s->B.px;
+  out->d_py = s->B.py;
+  return SJ_OK;
+}
+
+const char *sj_last_error(const sj_scene *s) { return s ? s->err : g_create_err; }
+
+}  // extern "C"

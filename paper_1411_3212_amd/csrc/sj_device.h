@@ -1,0 +1,196 @@
+// Device-side definitions shared by the kernels of libsj (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sj {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;               // threads per block of most kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kChunkBlocks = 1024;        // blocks of chunked scans / sorts
+constexpr int kFine = 16;                 // bits per axis of the finest grid
+constexpr uint32_t kLeafBit = 0x80000000u; // child reference: leaf index
+constexpr int kSortItems = 8;             // keys per thread per sort tile
+constexpr int kSortTile = kBlock * kSortItems;
+
+// Error bits latched on the device.
+enum : uint32_t {
+  kErrUpdId = 1u << 0,
+  kErrUpdCoord = 1u << 1,
+  kErrQueryId = 1u << 2,
+  kErrQueryRect = 1u << 3,
+  kErrOvfSubq = 1u << 4,
+  kErrOvfCov = 1u << 5,
+  kErrOvfRes = 1u << 6,
+  kErrOvfTree = 1u << 7,
+};
+constexpr uint32_t kErrOverflow = kErrOvfSubq | kErrOvfCov | kErrOvfRes | kErrOvfTree;
+
+// Scene control block in device memory.  Kernels read the per-tick sizes
+// from here, so that the launch sequence of a tick does not depend on
+// values produced on the device (and can be captured in a graph).
+struct Ctl {
+  // index frame: square of side 2^e anchored at (x0, y0)
+  float x0, y0;
+  int32_t e;
+  float scale;           // 2^(16 - e)
+  uint32_t built;
+  uint32_t th_cur;       // threshold of the current quadtree
+  uint32_t th_next;      // threshold requested for the next build (0: keep)
+  uint32_t force;        // build requested by the host
+  uint32_t rebuild;      // the current tick builds the quadtree
+  uint32_t since_build;  // ticks since the last build
+  uint32_t tick;
+  uint32_t n_present;
+  uint32_t n_outside;    // present objects outside the frame
+  uint32_t mbr[4];       // order-preserving encodings: min x, min y, max x, max y
+  uint32_t n_leaves, n_nodes, l_deep;
+  uint32_t fcount[kFine + 2]; // frontier sizes per level of the build
+  uint32_t n_tasks;
+  uint32_t max_leaf, prev_max_leaf;
+  uint32_t err_upd;      // errors of updates since the last tick
+  uint32_t err;          // errors of the current tick (includes err_upd)
+  uint32_t go_split;     // subquery/covering capacities respected
+  uint32_t go_join;      // result capacity respected
+  uint32_t pad0;
+  uint64_t n_isect, n_cov, n_res, cov_pairs, tests;
+  uint64_t upd_seq, qry_seq;
+};
+
+__device__ __forceinline__ uint32_t fenc(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fdec(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Finest-level cell index of a coordinate: one binary32 subtraction, an
+// exact multiplication by a power of two, truncation, clamping.  Monotone,
+// and the same function for objects and query corners.
+__device__ __forceinline__ uint32_t cell_of(float v, float v0, float scale) {
+  float d = __fsub_rn(v, v0);
+  float t = __fmul_rn(d, scale);
+  if (!(t >= 0.0f)) return 0u;
+  if (t >= 65536.0f) return 65535u;
+  return (uint32_t)t;
+}
+
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+  x &= 0xffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+__device__ __forceinline__ uint32_t morton2(uint32_t i, uint32_t j) {
+  return spread16(i) | (spread16(j) << 1);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of m below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int readlane_i(int v, int l) {
+  return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T y = __shfl_xor(x, o, kWave);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Exclusive scan over a block of NT threads; lds must hold NT/64 + 1
+// elements.  Returns the exclusive prefix; *total gets the block sum.
+template <typename T, int NT>
+__device__ __forceinline__ T block_excl_scan(T v, T *lds, T *total) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  T inc = wave_incl_scan(v);
+  if (lane == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T s = 0;
+    for (int i = 0; i < NW; ++i) {
+      T t = lds[i];
+      lds[i] = s;
+      s += t;
+    }
+    lds[NW] = s;
+  }
+  __syncthreads();
+  T r = inc - v + lds[w];
+  *total = lds[NW];
+  __syncthreads();
+  return r;
+}
+
+// Wave-aggregated append: each lane asks for `want` slots of a counter;
+// one atomic per wave.  Returns the lane's first slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, uint32_t want) {
+  uint32_t inc = wave_incl_scan(want);
+  uint32_t tot = (uint32_t)readlane_i((int)inc, kWave - 1);
+  uint32_t base = 0;
+  if (lane_id() == 0 && tot) base = atomicAdd(counter, tot);
+  base = (uint32_t)readlane_i((int)base, 0);
+  return base + inc - want;
+}
+
+__device__ __forceinline__ void flag_error(Ctl *ctl, uint32_t bits, bool cond) {
+  uint64_t m = ballot(cond);
+  if (m && lane_id() == (uint32_t)(__ffsll((unsigned long long)m) - 1)) atomicOr(&ctl->err, bits);
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t lo, uint32_t hi,
+                                                    uint32_t key) {
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace sj
