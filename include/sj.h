@@ -78,9 +78,9 @@ enum sj_flags {
  * significantly). */
 enum sj_rebuild {
   SJ_REBUILD_AUTO = 0,   /* rebuild on the first tick, after sj_build_index,
-                            every rebuild_period ticks, when a leaf below
-                            l_max held more than 2*th objects on the previous
-                            tick, or when more than 1% of the objects lie
+                            every rebuild_period ticks, and on the tick after
+                            one where a leaf below l_max held more than 2*th
+                            objects or more than 1% of the objects lay
                             outside the index frame */
   SJ_REBUILD_ALWAYS = 1, /* rebuild on every tick */
   SJ_REBUILD_NEVER = 2   /* rebuild only on the first tick and after
@@ -105,6 +105,9 @@ typedef struct sj_config {
                                    paper's configuration) */
   uint32_t rebuild_policy;      /* sj_rebuild */
   uint32_t rebuild_period;      /* SJ_REBUILD_AUTO period in ticks (0: 32) */
+  uint32_t split_slots;         /* subqueries per query remembered between the
+                                   count and write passes of query splitting;
+                                   queries with more are walked twice (0: 32) */
 } sj_config;
 
 /* Compressed results of the last tick (Sections "Bitmap decoding" and

@@ -36,7 +36,7 @@ class SjConfig(Structure):
                 ("capacity_subqueries", c_uint64), ("capacity_covering", c_uint64),
                 ("capacity_results", c_uint64), ("th_quad", c_uint32), ("th_min", c_uint32),
                 ("l_max", c_uint32), ("flags", c_uint32), ("rebuild_policy", c_uint32),
-                ("rebuild_period", c_uint32)]
+                ("rebuild_period", c_uint32), ("split_slots", c_uint32)]
 
 
 class SjResults(Structure):
@@ -157,8 +157,8 @@ class Scene:
     def __init__(self, capacity_objects: int, capacity_queries: int, *, th: int = 64,
                  th_min: int = 0, l_max: int = 16, covering: bool = True, reorder: bool = True,
                  rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
-                 capacity_covering: int = 0, capacity_results: int = 0, profile: bool = False,
-                 device=None, stream=None):
+                 capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
+                 profile: bool = False, device=None, stream=None):
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
@@ -166,7 +166,7 @@ class Scene:
                 (SJ_PROFILE if profile else 0)
         self.cfg = SjConfig(capacity_objects, capacity_queries, capacity_subqueries,
                             capacity_covering, capacity_results, th, th_min, l_max, flags,
-                            REBUILD[rebuild], rebuild_period)
+                            REBUILD[rebuild], rebuild_period, split_slots)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")

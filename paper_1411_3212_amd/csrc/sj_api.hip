@@ -26,6 +26,9 @@ struct sj_scene {
   const uint32_t *last_qid;
   bool ticked;
   bool prof;
+  bool known;          // host_ctl reflects the device state after the last tick
+  bool force_pending;  // sj_build_index since the last tick
+  uint64_t upd_pending;  // updates enqueued since the last tick
   bool upd_open;  // an update event interval is open since the last tick
   hipEvent_t ev[SJ_PH_COUNT + 2];
   hipEvent_t ev_u0, ev_u1;
@@ -38,7 +41,7 @@ static char g_create_err[256] = "";
 namespace {
 
 struct Derived {
-  uint32_t N, Q, th, th_min, l_max, period;
+  uint32_t N, Q, th, th_min, l_max, period, slots;
   uint64_t S, C, R;
   uint32_t LCAP, NCAP, FCAP;
 };
@@ -77,6 +80,11 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
     return SJ_EINVAL;
   }
   d->period = cfg->rebuild_period ? cfg->rebuild_period : 32u;
+  d->slots = cfg->split_slots ? cfg->split_slots : 32u;
+  if (d->slots > 4096u) {
+    snprintf(msg, msz, "split_slots must be at most 4096");
+    return SJ_EINVAL;
+  }
   if (cfg->rebuild_policy > SJ_REBUILD_NEVER) {
     snprintf(msg, msz, "unknown rebuild policy");
     return SJ_EINVAL;
@@ -129,10 +137,10 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.valB = c.take<uint32_t>(N);
   b.sxy = c.take<float2>(N);
   b.blk = c.take<uint32_t>(sj::kChunkBlocks);
-  b.part = c.take<uint64_t>(sj::kChunkBlocks);
+  b.red = c.take<uint64_t>((uint64_t)sj::kRedSlots * sj::kChunkBlocks);
+  b.part = c.take<uint64_t>((uint64_t)sj::kMaxScanJobs * sj::kChunkBlocks);
   b.hist = c.take<uint32_t>(256u * sj::kChunkBlocks);
   b.tot = c.take<uint32_t>(256);
-  b.n32 = c.take<uint32_t>(4);
   b.front[0] = c.take<uint4>(d.FCAP);
   b.front[1] = c.take<uint4>(d.FCAP);
   b.lstart = c.take<uint32_t>(L);
@@ -142,11 +150,10 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.nopen = c.take<uint32_t>(L);
   b.node_off = c.take<uint32_t>(L + 1);
   b.nodes = c.take<uint4>(d.NCAP);
+  b.table = c.take<uint32_t>(1u << 16);
   b.leaf_beg = c.take<uint32_t>(L + 1);
   b.leaf_nsq = c.take<uint32_t>(L);
   b.leaf_sqoff = c.take<uint32_t>(L + 1);
-  b.tflag = c.take<uint32_t>(L);
-  b.toff = c.take<uint32_t>(L + 1);
   b.tasks = c.take<uint32_t>(L);
   b.tkey = c.take<uint32_t>(L);
   b.tasks2 = c.take<uint32_t>(L);
@@ -157,6 +164,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.q_ioff = c.take<uint32_t>(Q + 1);
   b.q_coff = c.take<uint32_t>(Q + 1);
   b.q_roff = c.take<uint64_t>(Q + 1);
+  b.qlist = c.take<uint32_t>(Q * d.slots);
   b.sq_q = c.take<uint32_t>(d.S);
   b.sq_s = c.take<uint32_t>(d.S);
   b.sq_cnt = c.take<uint32_t>(d.S);
@@ -168,6 +176,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.LCAP = d.LCAP;
   b.NCAP = d.NCAP;
   b.FCAP = d.FCAP;
+  b.slots = d.slots;
   b.S = d.S;
   b.C = d.C;
   b.R = d.R;
@@ -207,6 +216,7 @@ int sync_ctl(sj_scene *s) {
   if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+  s->known = true;
   return SJ_OK;
 }
 
@@ -252,6 +262,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   s->l_max = d.l_max;
   s->period = d.period;
   s->prof = (cfg->flags & SJ_PROFILE) != 0;
+  s->known = true;  // host_ctl is zero: not built, the first tick builds
   (void)hipGetDevice(&s->device);
   carve(d, s->ws, &s->B);
   if (s->prof) {
@@ -302,7 +313,8 @@ int sj_apply_updates(sj_scene *s, const uint32_t *d_id, const float *d_x, const 
     (void)hipEventRecord(s->ev_u0, s->stream);
     s->upd_open = true;
   }
-  sj::launch_updates(s->B, d_id, d_x, d_y, m, s->stream);
+  sj::launch_updates(s->B, d_id, d_x, d_y, m, s->upd_pending, s->stream);
+  s->upd_pending += m;
   if (s->prof) (void)hipEventRecord(s->ev_u1, s->stream);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "apply_updates launch");
@@ -313,6 +325,7 @@ int sj_build_index(sj_scene *s, uint32_t th) {
   const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
   if (th && th < th_min) return fail(s, SJ_EINVAL, "build_index: th below th_min");
   sj::launch_request_build(s->B.ctl, th, s->stream);
+  s->force_pending = true;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "build_index launch");
 }
@@ -327,25 +340,38 @@ int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const flo
     return fail(s, SJ_EINVAL, "run_tick: null or misaligned pointer");
   const hipStream_t st = s->stream;
   const uint32_t flags = s->cfg.flags;
+  const uint32_t policy = s->cfg.rebuild_policy;
+  // Rebuild decision: when the host has seen the device state after the
+  // last tick it decides (and launches the build kernels only if needed);
+  // otherwise the device decides and the build kernels are launched gated.
+  uint32_t decision = 2u;
+  if (s->known) {
+    const Ctl &c = s->host_ctl;
+    const bool r = s->force_pending || !c.built || policy == SJ_REBUILD_ALWAYS ||
+                   (policy == SJ_REBUILD_AUTO && c.want_rebuild);
+    decision = r ? 1u : 0u;
+  }
   record(s, 0);
-  sj::launch_index(s->B, s->cfg.rebuild_policy, s->period, st);
+  sj::launch_index(s->B, decision, policy, s->upd_pending, d_qid, nq, st);
   record(s, 1);
-  sj::launch_build(s->B, s->l_max, st);
+  if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
   record(s, 2);
-  sj::launch_leaves(s->B, s->l_max, st);
+  sj::launch_leaves(s->B, st);
   record(s, 3);
   sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   record(s, 4);
-  sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, st);
+  const uint32_t *tasks = sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, st);
   record(s, 5);
-  sj::launch_join_count(s->B, st);
+  sj::launch_join_count(s->B, tasks, st);
   record(s, 6);
-  sj::launch_join_scan(s->B, s->B.R, st);
+  sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
   record(s, 7);
-  sj::launch_join_write(s->B, st);
+  sj::launch_join_write(s->B, tasks, nq, st);
   record(s, 8);
-  sj::launch_finish(s->B, nq, st);
   record(s, 9);
+  s->upd_pending = 0;
+  s->force_pending = false;
+  s->known = false;
   s->last_nq = nq;
   s->last_qid = d_qid;
   s->ticked = true;

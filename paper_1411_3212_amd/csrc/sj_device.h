@@ -35,28 +35,34 @@ struct Ctl {
   // index frame: square of side 2^e anchored at (x0, y0)
   float x0, y0;
   int32_t e;
-  float scale;           // 2^(16 - e)
+  float scale;            // 2^(16 - e)
   uint32_t built;
-  uint32_t th_cur;       // threshold of the current quadtree
-  uint32_t th_next;      // threshold requested for the next build (0: keep)
-  uint32_t force;        // build requested by the host
-  uint32_t rebuild;      // the current tick builds the quadtree
-  uint32_t since_build;  // ticks since the last build
+  uint32_t th_cur;        // threshold of the current quadtree
+  uint32_t th_next;       // threshold requested for the next build (0: keep)
+  uint32_t force;         // build requested by the host
+  uint32_t rebuild;       // the current tick builds the quadtree
+  uint32_t want_rebuild;  // automatic policy: build on the next tick
+  uint32_t since_build;   // ticks since the last build
   uint32_t tick;
   uint32_t n_present;
-  uint32_t n_outside;    // present objects outside the frame
-  uint32_t mbr[4];       // order-preserving encodings: min x, min y, max x, max y
-  uint32_t n_leaves, n_nodes, l_deep;
-  uint32_t fcount[kFine + 2]; // frontier sizes per level of the build
+  uint32_t n_outside;     // present objects outside the frame
+  uint32_t n_leaves, l_deep, tlev;
+  uint32_t fcount[kFine + 2];  // frontier sizes per level of the build
   uint32_t n_tasks;
-  uint32_t max_leaf, prev_max_leaf;
-  uint32_t err_upd;      // errors of updates since the last tick
-  uint32_t err;          // errors of the current tick (includes err_upd)
-  uint32_t go_split;     // subquery/covering capacities respected
-  uint32_t go_join;      // result capacity respected
-  uint32_t pad0;
+  uint32_t max_leaf;
+  uint32_t err_upd;       // errors of updates since the last tick
+  uint32_t err;           // errors of the current tick (includes err_upd)
+  uint32_t go_split;      // subquery/covering capacities respected
+  uint32_t go_join;       // result capacity respected
+  uint32_t n32[2];        // intersecting / covering subqueries as u32
   uint64_t n_isect, n_cov, n_res, cov_pairs, tests;
   uint64_t upd_seq, qry_seq;
+};
+
+// Slots of the per-block partial reductions (red[slot * kChunkBlocks + b]).
+enum : int {
+  kRedMinX = 0, kRedMinY, kRedMaxX, kRedMaxY, kRedOutside,
+  kRedCovPairs, kRedTests, kRedMaxLeaf, kRedTasks, kRedSlots
 };
 
 __device__ __forceinline__ uint32_t fenc(float f) {
@@ -191,6 +197,39 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t 
       hi = mid;
   }
   return lo;
+}
+
+// One array of a multi-array exclusive scan: in[0..n) -> out[0..n], out[n]
+// = total; out is u32 or u64.  Up to kMaxScanJobs arrays are scanned by one
+// launch of each scan kernel (blockIdx.y selects the array).
+constexpr int kMaxScanJobs = 3;
+struct ScanJob {
+  const uint32_t *in;
+  void *out;
+  const uint32_t *n_dev;  // element count in device memory, or
+  uint32_t n_host;        // this value when n_dev is null
+  uint32_t out64;
+};
+struct ScanJobs {
+  ScanJob j[kMaxScanJobs];
+};
+
+__device__ __forceinline__ uint32_t job_n(const ScanJob &j) { return j.n_dev ? *j.n_dev : j.n_host; }
+__device__ __forceinline__ void job_store(const ScanJob &j, uint64_t i, uint64_t v) {
+  if (j.out64)
+    ((uint64_t *)j.out)[i] = v;
+  else
+    ((uint32_t *)j.out)[i] = (uint32_t)v;
+}
+
+// In a block of kChunkBlocks threads: exclusive scan of the per-block
+// partials part[0..kChunkBlocks) in place; returns the total.
+__device__ __forceinline__ uint64_t scan_partials(uint64_t *part, uint64_t *lds) {
+  uint64_t total;
+  const uint64_t v = part[threadIdx.x];
+  const uint64_t ex = block_excl_scan<uint64_t, kChunkBlocks>(v, lds, &total);
+  part[threadIdx.x] = ex;
+  return total;
 }
 
 }  // namespace sj

@@ -4,22 +4,34 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sj_device.h"
+
 namespace sj {
 
-// Exclusive scan of in[0..n) (n = *n_dev, or n_host when n_dev is null)
-// into out[0..n]; out[n] and *total_out (if non-null) get the total.
-// part: kChunkBlocks u64 of scratch.  Skipped when *gate == 0.
-template <typename T>
-void scan_excl(const uint32_t *in, T *out, const uint32_t *n_dev, uint32_t n_host,
-               uint64_t *part, uint64_t *total_out, const uint32_t *gate, hipStream_t s);
+ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host);
+ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32_t n_host);
+
+// Exclusive scans of up to kMaxScanJobs arrays (out[n] = total).  The full
+// form runs reduce, a generic single-block top and down; callers with extra
+// per-tick bookkeeping launch their own top kernel between mscan_reduce and
+// mscan_down (the top must call scan_partials on part[q * kChunkBlocks]).
+// part: kMaxScanJobs * kChunkBlocks u64.  Skipped when *gate == 0.
+void mscan(const ScanJobs &jobs, int njobs, uint64_t *part, const uint32_t *gate,
+           uint64_t *total0, hipStream_t s);
+void mscan_reduce(const ScanJobs &jobs, int njobs, uint64_t *part, const uint32_t *gate,
+                  hipStream_t s);
+void mscan_down(const ScanJobs &jobs, int njobs, const uint64_t *part, const uint32_t *gate,
+                hipStream_t s);
 
 // Stable LSD radix sort of n = *n_dev (key, value) pairs over key bits
 // [bit_begin, bit_end) in steps of 8.  Passes alternate between (k0, v0)
-// and (k1, v1); with an even number of passes the result is in (k0, v0).
-// hist: 256 * kChunkBlocks u32, tot: 256 u32.  Skipped when *gate == 0.
-void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+// and (k1, v1); returns true if the result is in (k1, v1).  If gout is set,
+// the last pass also writes gout[i] = (gx[v], gy[v]) for every output value
+// v.  hist: 256 * kChunkBlocks u32, tot: 256 u32.  Skipped when *gate == 0.
+bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, const uint32_t *gate, uint32_t *hist, uint32_t *tot,
-                      int bit_begin, int bit_end, hipStream_t s);
+                      int bit_begin, int bit_end, hipStream_t s, const float *gx = nullptr,
+                      const float *gy = nullptr, float2 *gout = nullptr);
 
 inline unsigned grid_for(uint64_t n, unsigned cap = 2048) {
   uint64_t g = (n + 255) / 256;

@@ -12,7 +12,7 @@ struct Ctl;
 
 constexpr unsigned kJoinBlocks = 4096;  // 16384 waves for the join passes
 
-// Typed views of the caller's workspace (see layout() in sj_api.hip).
+// Typed views of the caller's workspace (carved by sj_api.hip).
 struct Bufs {
   Ctl *ctl;
   // objects (by id) and per-tick sorted arrays
@@ -21,26 +21,28 @@ struct Bufs {
   uint32_t *keyA, *valA, *keyB, *valB;  // sorted (code, id) end in A
   float2 *sxy;                          // positions in sorted order
   uint32_t *blk;                        // per-block present counts/offsets
-  uint64_t *part;                       // scan partials
+  uint64_t *red;                        // per-block partials (kRedSlots)
+  uint64_t *part;                       // scan partials (kMaxScanJobs)
   uint32_t *hist, *tot;                 // radix sort histograms
-  uint32_t *n32;                        // [0] intersecting, [1] covering (u32)
   // quadtree
   uint4 *front[2];
   uint32_t *lstart, *llevel, *lstart2, *llevel2;
   uint32_t *nopen, *node_off;
   uint4 *nodes;
+  uint32_t *table;                      // start table (4^8 entries)
   uint32_t *leaf_beg, *leaf_nsq, *leaf_sqoff;
   // schedule
-  uint32_t *tflag, *toff, *tasks, *tkey, *tasks2, *tkey2;
+  uint32_t *tasks, *tkey, *tasks2, *tkey2;
   // queries and subqueries
   float4 *qrect;
   uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;
   uint64_t *q_roff;
+  uint32_t *qlist;                      // visited leaves per query (slots each)
   uint32_t *sq_q, *sq_s, *sq_cnt;
   uint64_t *res_off;
   uint32_t *cov_leaf, *res_ids;
   // capacities
-  uint32_t N, Q, LCAP, NCAP, FCAP;
+  uint32_t N, Q, LCAP, NCAP, FCAP, slots;
   uint64_t S, C, R;
 };
 
@@ -49,18 +51,19 @@ void launch_request_build(Ctl *ctl, uint32_t th, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const float *y, uint32_t m,
-                    hipStream_t s);
-void launch_index(const Bufs &B, uint32_t policy, uint32_t period, hipStream_t s);
+                    uint64_t seq_off, hipStream_t s);
+void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
+                  const uint32_t *qid, uint32_t nq, hipStream_t s);
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s);
-void launch_leaves(const Bufs &B, uint32_t l_max, hipStream_t s);
+void launch_leaves(const Bufs &B, hipStream_t s);
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s);
-void launch_schedule(const Bufs &B, uint32_t reorder, hipStream_t s);
-void launch_join_count(const Bufs &B, hipStream_t s);
-void launch_join_scan(const Bufs &B, uint64_t cap_res, hipStream_t s);
-void launch_join_write(const Bufs &B, hipStream_t s);
-void launch_finish(const Bufs &B, uint32_t nq, hipStream_t s);
+const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, hipStream_t s);
+void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s);
+void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
+                      hipStream_t s);
+void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s);
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s);
 void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt, uint64_t *hash,
                  hipStream_t s);

@@ -2,24 +2,32 @@
 //
 // Pipeline of one tick (paper Section "Query processing pipeline"):
 //   updates      last-writer-wins scatter of (id, x, y) into positions by id
-//   index        MBR -> frame -> Morton codes -> LDS-staged radix sort ->
-//                sorted positions (index creation, Algorithm 1 first steps)
+//   index        MBR -> frame -> Morton codes -> LDS-staged radix sort whose
+//                last pass also gathers the positions in sorted order
+//                (index creation, first steps of Algorithm 1)
 //   build        level-wise PR-quadtree split under the threshold, leaves in
-//                Morton order, node table for query traversal (Algorithm 1)
+//                Morton order, node table and a start table at level
+//                min(l_deep, 8) (the paper's z_map, capped) for queries
+//                (Algorithm 1; only on ticks that build)
 //   leaves       object range of every leaf in the sorted order
-//   split        per query: leaves it touches, intersecting / covering;
-//                count -> exclusive scan -> write (query indexing)
-//   schedule     leaves with intersecting subqueries, heaviest first
-//                (task scheduling optimisation)
-//   join         per leaf, one wave per 64 objects: ballot of the closed
-//                containment test for every intersecting subquery; count
-//                pass -> exclusive scan -> write pass of object ids
-//                (filtering with bitmaps + decoding, Algorithm 2 and the
-//                decoding algorithm)
+//   split        per query: the leaves it touches, intersecting / covering;
+//                count -> exclusive scans -> write, subqueries grouped by
+//                leaf (query indexing and sorting of subqueries)
+//   schedule     leaves ordered by decreasing log2 of their weight
+//                |intersecting subqueries| x |objects| (task scheduling)
+//   join         one wave per leaf: ballot of the closed containment test
+//                per intersecting subquery; count -> scan -> write of ids
+//                (filtering with bitmaps + decoding)
+// Sums and maxima go through per-block partials reduced by the single-block
+// kernels of the pipeline (no same-address atomics from every block).
 #include "sj_device.h"
 #include "sj_kernels.h"
 
 namespace sj {
+
+constexpr uint32_t kTableLevel = 8;      // deepest level of the start table
+constexpr uint32_t kTableCells = 1u << (2 * kTableLevel);
+constexpr uint32_t kTableScanMax = 64;   // larger queries start at the root
 
 // ------------------------------------------------------------- utilities --
 
@@ -49,74 +57,64 @@ __global__ void k_request_build(Ctl *ctl, uint32_t th) {
   if (th) ctl->th_next = th;
 }
 
+__device__ __forceinline__ uint32_t compact16(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
+}
+
 // --------------------------------------------------------------- updates --
 // Tick batching: within a tick the most recent update of an object wins.
-// Every update gets a sequence number (monotone over the scene's life);
-// an atomic max per object keeps the latest, then only that one is written.
+// Update k of a call gets the sequence number upd_seq + seq_off + k + 1
+// (seq_off: updates of earlier calls in the same tick; upd_seq advances by
+// the tick's total when the tick runs); an atomic max per object keeps the
+// latest, then only that one is written.
 
 __global__ void __launch_bounds__(kBlock) k_upd_stamp(const uint32_t *id, const float *x,
                                                       const float *y, uint32_t m, uint32_t N,
-                                                      uint64_t *stamp, Ctl *ctl) {
-  const uint64_t seq = ctl->upd_seq;
-  const uint32_t stride = gridDim.x * kBlock;
+                                                      uint64_t seq_off, uint64_t *stamp,
+                                                      Ctl *ctl) {
+  const uint64_t seq = ctl->upd_seq + seq_off;
   const uint32_t mr = (m + kWave - 1) / kWave * kWave;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < mr; k += stride) {
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < mr; k += gridDim.x * kBlock) {
     bool bad_id = false, bad_xy = false;
     if (k < m) {
       const uint32_t o = id[k];
       const float xv = x[k], yv = y[k];
       bad_id = o >= N;
       bad_xy = !bad_id && !(isfinite(xv) && isfinite(yv));
-      if (!bad_id && !bad_xy) atomicMax((unsigned long long *)&stamp[o], (unsigned long long)(seq + k + 1));
+      if (!bad_id && !bad_xy)
+        atomicMax((unsigned long long *)&stamp[o], (unsigned long long)(seq + k + 1));
     }
-    if (ballot(bad_id | bad_xy)) {
-      uint64_t mi = ballot(bad_id), mx = ballot(bad_xy);
-      if (lane_id() == 0) atomicOr(&ctl->err_upd, (mi ? kErrUpdId : 0u) | (mx ? kErrUpdCoord : 0u));
-    }
+    const uint64_t mi = ballot(bad_id), mx = ballot(bad_xy);
+    if ((mi | mx) && lane_id() == 0)
+      atomicOr(&ctl->err_upd, (mi ? kErrUpdId : 0u) | (mx ? kErrUpdCoord : 0u));
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_upd_write(const uint32_t *id, const float *x,
                                                       const float *y, uint32_t m, uint32_t N,
-                                                      const uint64_t *stamp, const Ctl *ctl,
-                                                      float *px, float *py) {
-  const uint64_t seq = ctl->upd_seq;
+                                                      uint64_t seq_off, const uint64_t *stamp,
+                                                      const Ctl *ctl, float *px, float *py) {
+  const uint64_t seq = ctl->upd_seq + seq_off;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < m; k += gridDim.x * kBlock) {
     const uint32_t o = id[k];
-    if (o >= N) continue;
-    if (stamp[o] == seq + k + 1) {
+    if (o < N && stamp[o] == seq + k + 1) {
       px[o] = x[k];
       py[o] = y[k];
     }
   }
 }
 
-__global__ void k_upd_end(Ctl *ctl, uint32_t m) { ctl->upd_seq += m; }
-
 // ----------------------------------------------------------------- index --
 
-__global__ void k_tick_begin(Ctl *ctl) {
-  ctl->err = ctl->err_upd;
-  ctl->err_upd = 0;
-  ctl->mbr[0] = ctl->mbr[1] = 0xffffffffu;
-  ctl->mbr[2] = ctl->mbr[3] = 0u;
-  ctl->n_present = 0;
-  ctl->n_outside = 0;
-  ctl->rebuild = 0;
-  for (int l = 0; l < kFine + 2; ++l) ctl->fcount[l] = 0;
-  ctl->n_tasks = 0;
-  ctl->prev_max_leaf = ctl->max_leaf;
-  ctl->max_leaf = 0;
-  ctl->go_split = 0;
-  ctl->go_join = 0;
-  ctl->n_isect = ctl->n_cov = ctl->n_res = ctl->cov_pairs = ctl->tests = 0;
-}
-
-// MBR of the present objects (position not NaN), present count per block
-// of ids (for the order-preserving compaction) and the number of present
-// objects outside the current frame.
+// Per block of ids: present count (position not NaN), MBR and number of
+// present objects outside the current frame, as partials.
 __global__ void __launch_bounds__(kBlock) k_mbr(const float *px, const float *py, uint32_t N,
-                                                Ctl *ctl, uint32_t *blk) {
+                                                const Ctl *ctl, uint32_t *blk, uint64_t *red) {
   __shared__ float s_mnx[kWavesPerBlock], s_mny[kWavesPerBlock], s_mxx[kWavesPerBlock],
       s_mxy[kWavesPerBlock];
   __shared__ uint32_t s_cnt[kWavesPerBlock], s_out[kWavesPerBlock];
@@ -163,14 +161,13 @@ __global__ void __launch_bounds__(kBlock) k_mbr(const float *px, const float *py
       mxx = fmaxf(mxx, s_mxx[i]); mxy = fmaxf(mxy, s_mxy[i]);
       cnt += s_cnt[i]; out += s_out[i];
     }
-    blk[blockIdx.x] = cnt;
-    if (cnt) {
-      atomicMin(&ctl->mbr[0], fenc(mnx));
-      atomicMin(&ctl->mbr[1], fenc(mny));
-      atomicMax(&ctl->mbr[2], fenc(mxx));
-      atomicMax(&ctl->mbr[3], fenc(mxy));
-    }
-    if (out) atomicAdd(&ctl->n_outside, out);
+    const uint32_t b = blockIdx.x;
+    blk[b] = cnt;
+    red[kRedMinX * kChunkBlocks + b] = cnt ? fenc(mnx) : 0xffffffffu;
+    red[kRedMinY * kChunkBlocks + b] = cnt ? fenc(mny) : 0xffffffffu;
+    red[kRedMaxX * kChunkBlocks + b] = cnt ? fenc(mxx) : 0u;
+    red[kRedMaxY * kChunkBlocks + b] = cnt ? fenc(mxy) : 0u;
+    red[kRedOutside * kChunkBlocks + b] = out;
   }
 }
 
@@ -184,20 +181,67 @@ __device__ __forceinline__ int32_t frame_exp(float m) {
   return e < -100 ? -100 : e;
 }
 
-// Exclusive scan of the per-block present counts; rebuild decision; frame.
-__global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk,
-                                                         uint32_t policy, uint32_t period) {
-  __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
-  uint32_t total;
-  uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(blk[threadIdx.x], lds, &total);
-  blk[threadIdx.x] = ex;
-  if (threadIdx.x != 0) return;
-  ctl->n_present = total;
-  bool r = ctl->force || !ctl->built || policy == 1u;
-  if (!r && policy == 0u) {
-    r = ctl->since_build + 1 >= period || ctl->prev_max_leaf > 2u * ctl->th_cur ||
-        (uint64_t)ctl->n_outside * 100u > total;
+template <bool MAX>
+__device__ __forceinline__ uint32_t block_minmax_1024(uint32_t v, uint32_t *lds) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const uint32_t u = __shfl_xor(v, o, kWave);
+    v = MAX ? (u > v ? u : v) : (u < v ? u : v);
   }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) lds[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kChunkBlocks / kWave; ++i)
+      v = MAX ? (lds[i] > v ? lds[i] : v) : (lds[i] < v ? lds[i] : v);
+    lds[0] = v;
+  }
+  __syncthreads();
+  v = lds[0];
+  __syncthreads();
+  return v;
+}
+
+// Start of a tick (one block of 1024 threads): MBR from the partials,
+// offsets of the present objects per block, rebuild decision, frame, reset
+// of the tick's counters.  decision: 0 keep the quadtree, 1 build it, 2 let
+// the automatic policy decide (the host launches the build kernels for 1
+// and 2; they do nothing unless ctl->rebuild is set).
+__global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk,
+                                                         const uint64_t *red, uint4 *front0,
+                                                         uint32_t decision, uint32_t policy,
+                                                         uint64_t upd_total) {
+  __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
+  const int t = threadIdx.x;
+  const uint32_t mnx = block_minmax_1024<false>((uint32_t)red[kRedMinX * kChunkBlocks + t], lds);
+  const uint32_t mny = block_minmax_1024<false>((uint32_t)red[kRedMinY * kChunkBlocks + t], lds);
+  const uint32_t mxx = block_minmax_1024<true>((uint32_t)red[kRedMaxX * kChunkBlocks + t], lds);
+  const uint32_t mxy = block_minmax_1024<true>((uint32_t)red[kRedMaxY * kChunkBlocks + t], lds);
+  uint32_t outside;
+  block_excl_scan<uint32_t, kChunkBlocks>((uint32_t)red[kRedOutside * kChunkBlocks + t], lds,
+                                          &outside);
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(blk[t], lds, &total);
+  blk[t] = ex;
+  if (t != 0) return;
+  ctl->err = ctl->err_upd;
+  ctl->err_upd = 0;
+  ctl->upd_seq += upd_total;
+  ctl->n_present = total;
+  ctl->n_outside = outside;
+  ctl->go_split = 0;
+  ctl->go_join = 0;
+  ctl->n_isect = ctl->n_cov = ctl->n_res = ctl->cov_pairs = ctl->tests = 0;
+  ctl->n32[0] = ctl->n32[1] = 0;
+  ctl->n_tasks = 0;
+  ctl->max_leaf = 0;
+  bool r;
+  if (decision == 0u)
+    r = false;
+  else if (decision == 1u)
+    r = true;
+  else
+    r = ctl->force || !ctl->built || policy == 1u || (policy == 0u && ctl->want_rebuild);
   ctl->rebuild = r ? 1u : 0u;
   if (!r) {
     ctl->since_build += 1;
@@ -211,21 +255,29 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   float x0 = 0.0f, y0 = 0.0f;
   int32_t e = 0;
   if (total) {
-    x0 = fdec(ctl->mbr[0]);
-    y0 = fdec(ctl->mbr[1]);
-    const float w = __fsub_rn(fdec(ctl->mbr[2]), x0), h = __fsub_rn(fdec(ctl->mbr[3]), y0);
+    x0 = fdec(mnx);
+    y0 = fdec(mny);
+    const float w = __fsub_rn(fdec(mxx), x0), h = __fsub_rn(fdec(mxy), y0);
     e = frame_exp(w > h ? w : h);
   }
   ctl->x0 = x0;
   ctl->y0 = y0;
   ctl->e = e;
   ctl->scale = __uint_as_float((uint32_t)(127 + kFine - e) << 23);
+  for (int l = 0; l < kFine + 2; ++l) ctl->fcount[l] = 0;
+  ctl->fcount[0] = 1;
+  ctl->n_leaves = 0;
+  ctl->l_deep = 0;
+  front0[0] = make_uint4(0u, 0u, total, 0u);
 }
 
-// Morton codes of present objects, compacted in id order.
+// Morton codes of present objects, compacted in id order; then the
+// sequence stamps of the tick's queries (the latest query of an object is
+// the one answered).
 __global__ void __launch_bounds__(kBlock) k_morton(const float *px, const float *py, uint32_t N,
-                                                   const Ctl *ctl, const uint32_t *blk,
-                                                   uint32_t *keys, uint32_t *vals) {
+                                                   Ctl *ctl, const uint32_t *blk, uint32_t *keys,
+                                                   uint32_t *vals, const uint32_t *qid,
+                                                   uint32_t nq, uint64_t *qstamp) {
   __shared__ uint32_t lds[kWavesPerBlock + 1];
   const uint32_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
@@ -245,15 +297,16 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float *px, const float 
     }
     base += tot;
   }
-}
-
-__global__ void __launch_bounds__(kBlock) k_gather(const float *px, const float *py,
-                                                   const uint32_t *ids, const Ctl *ctl,
-                                                   float2 *sxy) {
-  const uint32_t n = ctl->n_present;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const uint32_t o = ids[i];
-    sxy[i] = make_float2(px[o], py[o]);
+  const uint64_t seq = ctl->qry_seq;
+  const uint32_t nr = (nq + kWave - 1) / kWave * kWave;
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nr; k += gridDim.x * kBlock) {
+    bool bad = false;
+    if (k < nq) {
+      const uint32_t o = qid[k];
+      bad = o >= N;
+      if (!bad) atomicMax((unsigned long long *)&qstamp[o], (unsigned long long)(seq + k + 1));
+    }
+    flag_error(ctl, kErrQueryId, bad);
   }
 }
 
@@ -263,14 +316,6 @@ __global__ void __launch_bounds__(kBlock) k_gather(const float *px, const float 
 // level-l children by binary search; a child with more than th objects
 // below l_max joins the next frontier, every other child (empty ones
 // included) becomes a leaf.
-
-__global__ void k_tree_init(Ctl *ctl, uint4 *front0) {
-  if (!ctl->rebuild) return;
-  front0[0] = make_uint4(0u, 0u, ctl->n_present, 0u);
-  ctl->fcount[0] = 1;
-  ctl->n_leaves = 0;
-  ctl->l_deep = 0;
-}
 
 __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uint32_t l_max,
                                                        const uint32_t *codes, const uint4 *fin,
@@ -308,8 +353,10 @@ __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uin
       for (uint32_t k = 0; k < 4; ++k) {
         const uint32_t cz = zp * 4u + k;
         if ((splitm >> k) & 1u) {
-          if (fb < fcap) fout[fb] = make_uint4(cz, bnd[k], bnd[k + 1], 0u);
-          else ovf = true;
+          if (fb < fcap)
+            fout[fb] = make_uint4(cz, bnd[k], bnd[k + 1], 0u);
+          else
+            ovf = true;
           ++fb;
         } else {
           if (lb < lcap) {
@@ -335,6 +382,7 @@ __global__ void k_tree_done(Ctl *ctl, uint32_t lcap) {
     ctl->n_leaves = lcap;
     ctl->err |= kErrOvfTree;
   }
+  ctl->tlev = ctl->l_deep < kTableLevel ? ctl->l_deep : kTableLevel;
 }
 
 __device__ __forceinline__ uint32_t open_level(uint32_t s) {
@@ -376,9 +424,31 @@ __global__ void __launch_bounds__(kBlock) k_nodes_build(Ctl *ctl, const uint32_t
         ref[c] = lu == k + 1 ? (kLeafBit | u) : node_off[u] + (k + 1 - open_level(cs));
       }
       if (bad) atomicOr(&ctl->err, kErrOvfTree);
-      if (idx < ncap) nodes[idx] = make_uint4(ref[0], ref[1], ref[2], ref[3]);
-      else atomicOr(&ctl->err, kErrOvfTree);
+      if (idx < ncap)
+        nodes[idx] = make_uint4(ref[0], ref[1], ref[2], ref[3]);
+      else
+        atomicOr(&ctl->err, kErrOvfTree);
     }
+  }
+}
+
+// Start table at level T = min(l_deep, 8): for every level-T cell, the leaf
+// that contains it (a leaf at level <= T) or the internal node at level T.
+__global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const uint4 *nodes,
+                                                        uint32_t *table) {
+  if (!ctl->rebuild || (ctl->err & kErrOvfTree)) return;
+  const uint32_t T = ctl->tlev;
+  const uint32_t ncell = 1u << (2 * T);
+  for (uint32_t z = blockIdx.x * kBlock + threadIdx.x; z < ncell; z += gridDim.x * kBlock) {
+    const uint32_t ci = compact16(z), cj = compact16(z >> 1);
+    uint32_t ref = 0;  // root
+    for (uint32_t k = 0; k < T; ++k) {
+      const uint32_t c = ((ci >> (T - k - 1)) & 1u) | (((cj >> (T - k - 1)) & 1u) << 1);
+      const uint4 rec = nodes[ref];
+      ref = c == 0 ? rec.x : c == 1 ? rec.y : c == 2 ? rec.z : rec.w;
+      if (ref & kLeafBit) break;
+    }
+    table[z] = ref;
   }
 }
 
@@ -395,36 +465,33 @@ __global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const ui
   if (blockIdx.x == 0 && threadIdx.x == 0) leaf_beg[n] = np;
 }
 
-__global__ void __launch_bounds__(kBlock) k_leaf_stats(Ctl *ctl, const uint32_t *leaf_beg,
-                                                       const uint32_t *llevel, uint32_t l_max) {
-  const uint32_t n = ctl->n_leaves;
-  const uint32_t nr = (n + kWave - 1) / kWave * kWave;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nr; t += gridDim.x * kBlock) {
-    uint32_t c = 0;
-    if (t < n && llevel[t] < l_max) c = leaf_beg[t + 1] - leaf_beg[t];
-    c = wave_max(c);
-    if (lane_id() == 0 && c) atomicMax(&ctl->max_leaf, c);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (ctl->err & kErrOvfTree)) ctl->built = 0;
-}
-
 // ----------------------------------------------------------------- split --
 // Query splitting (mapping function g): the corners are mapped through the
-// same cell function as the objects (clamped to the frame); a depth-first
-// walk of the node table visits every leaf whose finest-level cell range
-// overlaps the query's.  A leaf strictly inside the query's cell range on
-// both axes is covering; any other overlapping leaf is intersecting.
+// same cell function as the objects (clamped to the frame).  The query's
+// cells of the start table give either a leaf directly (kept once per leaf,
+// at the cell with minimal coordinates, as the paper does with z_map) or
+// an internal node below which a depth-first walk visits every leaf whose
+// finest-level cell range overlaps the query's.  A leaf strictly inside the
+// query's cell range on both axes is covering, any other is intersecting.
 // Leaves without objects are skipped (they are inactive).
 
 struct QBox {
   uint32_t i0, i1, j0, j1;
 };
 
+struct Tree {
+  const uint4 *nodes;
+  const uint32_t *table;
+  const uint32_t *lstart, *llevel;
+  uint32_t tlev;
+};
+
 template <typename Visit>
-__device__ __forceinline__ void walk_leaves(const uint4 *__restrict__ nodes, uint32_t *stack,
-                                            const QBox q, Visit &&visit) {
-  uint32_t node = 0, depth = 0, pi = 0, pj = 0, c = 0;
-  uint4 rec = nodes[0];
+__device__ __forceinline__ void walk_from(const uint4 *__restrict__ nodes, uint32_t *stack,
+                                          uint32_t node, uint32_t depth0, uint32_t pi,
+                                          uint32_t pj, const QBox q, Visit &visit) {
+  uint32_t depth = depth0, c = 0;
+  uint4 rec = nodes[node];
   while (true) {
     if (c < 4) {
       const uint32_t ref = c == 0 ? rec.x : c == 1 ? rec.y : c == 2 ? rec.z : rec.w;
@@ -443,10 +510,11 @@ __device__ __forceinline__ void walk_leaves(const uint4 *__restrict__ nodes, uin
         rec = nodes[node];
         continue;
       }
-      if (ov) visit(ref & ~kLeafBit, q.i0 < ilo && ihi < q.i1 && q.j0 < jlo && jhi < q.j1);
+      if (ov && (ref & kLeafBit))
+        visit(ref & ~kLeafBit, q.i0 < ilo && ihi < q.i1 && q.j0 < jlo && jhi < q.j1);
       ++c;
     } else {
-      if (depth == 0) break;
+      if (depth == depth0) break;
       --depth;
       c = ((pi & 1u) | ((pj & 1u) << 1)) + 1u;
       pi >>= 1;
@@ -457,18 +525,31 @@ __device__ __forceinline__ void walk_leaves(const uint4 *__restrict__ nodes, uin
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_q_stamp(const uint32_t *qid, uint32_t nq, uint32_t N,
-                                                    uint64_t *qstamp, Ctl *ctl) {
-  const uint64_t seq = ctl->qry_seq;
-  const uint32_t nr = (nq + kWave - 1) / kWave * kWave;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nr; k += gridDim.x * kBlock) {
-    bool bad = false;
-    if (k < nq) {
-      const uint32_t o = qid[k];
-      bad = o >= N;
-      if (!bad) atomicMax((unsigned long long *)&qstamp[o], (unsigned long long)(seq + k + 1));
+template <typename Visit>
+__device__ __forceinline__ void for_each_leaf(const Tree &tr, uint32_t *stack, const QBox q,
+                                              Visit &visit) {
+  const uint32_t T = tr.tlev, sh = (uint32_t)kFine - T;
+  const uint32_t ti0 = q.i0 >> sh, ti1 = q.i1 >> sh, tj0 = q.j0 >> sh, tj1 = q.j1 >> sh;
+  if ((ti1 - ti0 + 1) * (tj1 - tj0 + 1) > kTableScanMax) {
+    walk_from(tr.nodes, stack, 0u, 0u, 0u, 0u, q, visit);
+    return;
+  }
+  for (uint32_t cj = tj0; cj <= tj1; ++cj) {
+    for (uint32_t ci = ti0; ci <= ti1; ++ci) {
+      const uint32_t ref = tr.table[morton2(ci, cj)];
+      if (!(ref & kLeafBit)) {
+        walk_from(tr.nodes, stack, ref, T, ci, cj, q, visit);
+        continue;
+      }
+      const uint32_t leaf = ref & ~kLeafBit;
+      const uint32_t st = tr.lstart[leaf], l = tr.llevel[leaf];
+      const uint32_t li = compact16(st), lj = compact16(st >> 1);
+      const uint32_t li0 = li >> sh, lj0 = lj >> sh;
+      if (ci != (ti0 > li0 ? ti0 : li0) || cj != (tj0 > lj0 ? tj0 : lj0)) continue;
+      const uint32_t size = 1u << (kFine - l);
+      const uint32_t ihi = li + (size - 1u), jhi = lj + (size - 1u);
+      visit(leaf, q.i0 < li && ihi < q.i1 && q.j0 < lj && jhi < q.j1);
     }
-    flag_error(ctl, kErrQueryId, bad);
   }
 }
 
@@ -488,32 +569,41 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
   return true;
 }
 
+// Count pass: per query the numbers of intersecting and covering
+// subqueries, per leaf the number of intersecting subqueries; the visited
+// leaves are kept in the query's list slots for the write pass.
 __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const uint32_t *qid, const float *xa, const float *ya, const float *xb,
-    const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, const uint4 *nodes,
+    const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *leaf_nsq,
-    uint32_t covering) {
+    uint32_t *qlist, uint32_t slots, uint32_t covering) {
   __shared__ uint32_t stack[kFine * kBlock];
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
+  tr.tlev = ctl->tlev;
   const uint32_t nr = (nq + kWave - 1) / kWave * kWave;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nr; k += gridDim.x * kBlock) {
     bool bad_rect = false;
-    uint32_t ni = 0, nc = 0;
     if (k < nq) {
+      uint32_t ni = 0, nc = 0, nl = 0;
+      uint32_t *lst = qlist + (uint64_t)k * slots;
       const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
       qrect[k] = r;
       QBox q;
       if (query_box(ctl, k, qid[k], N, qstamp, seq, r, &q, &bad_rect) && tree_ok) {
-        walk_leaves(nodes, stack + threadIdx.x, q, [&](uint32_t leaf, bool cov) {
+        auto visit = [&](uint32_t leaf, bool cov) {
           if (leaf_beg[leaf + 1] == leaf_beg[leaf]) return;
-          if (cov && covering) {
+          const bool c = cov && covering;
+          if (c) {
             ++nc;
           } else {
             ++ni;
             atomicAdd(&leaf_nsq[leaf], 1u);
           }
-        });
+          if (nl < slots) lst[nl] = leaf | (c ? kLeafBit : 0u);
+          ++nl;
+        };
+        for_each_leaf(tr, stack + threadIdx.x, q, visit);
       }
       q_ni[k] = ni;
       q_nc[k] = nc;
@@ -522,76 +612,134 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
   }
 }
 
-// Capacities of the tick's subqueries.
-__global__ void k_split_check(Ctl *ctl, uint64_t cap_sq, uint64_t cap_cov, uint32_t *n32) {
+// Top of the split scans: totals, capacity checks.
+__global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs jobs,
+                                                            uint64_t *part, uint64_t cap_sq,
+                                                            uint64_t cap_cov) {
+  __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
+  uint64_t tot[3];
+  for (int q = 0; q < 3; ++q) {
+    tot[q] = scan_partials(part + q * kChunkBlocks, lds);
+    if (threadIdx.x == 0) job_store(jobs.j[q], job_n(jobs.j[q]), tot[q]);
+  }
+  if (threadIdx.x != 0) return;
   uint32_t err = 0;
-  if (ctl->n_isect > cap_sq) err |= kErrOvfSubq;
-  if (ctl->n_cov > cap_cov) err |= kErrOvfCov;
+  if (tot[0] > cap_sq) err |= kErrOvfSubq;
+  if (tot[1] > cap_cov) err |= kErrOvfCov;
   if (ctl->err & kErrOvfTree) err |= kErrOvfTree;
   ctl->err |= err;
+  ctl->n_isect = tot[0];
+  ctl->n_cov = tot[1];
   ctl->go_split = err ? 0u : 1u;
-  n32[0] = err ? 0u : (uint32_t)ctl->n_isect;
-  n32[1] = err ? 0u : (uint32_t)ctl->n_cov;
+  ctl->n32[0] = err ? 0u : (uint32_t)tot[0];
+  ctl->n32[1] = err ? 0u : (uint32_t)tot[1];
 }
 
+// Write pass: intersecting subqueries grouped by leaf (record: query,
+// slot of the subquery in query order), covering leaves per query.  The
+// order inside a leaf's group does not matter: a subquery's results go to
+// the offset of its query-order slot.
 __global__ void __launch_bounds__(kBlock) k_q_write(
-    Ctl *ctl, const uint32_t *qid, uint32_t nq, uint32_t N, const uint64_t *qstamp,
-    const uint4 *nodes, const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff,
-    const uint32_t *q_coff, const uint32_t *leaf_sqoff, uint32_t *leaf_nsq, uint32_t *sq_q,
-    uint32_t *sq_s, uint32_t *cov_leaf, uint32_t covering) {
-  if (!ctl->go_split) return;
+    Ctl *ctl, const uint32_t *qid, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
+    const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
+    const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, uint32_t slots,
+    const uint32_t *leaf_sqoff, uint32_t *leaf_nsq, uint32_t *sq_q, uint32_t *sq_s,
+    uint32_t *cov_leaf, uint32_t covering, uint64_t *red) {
   __shared__ uint32_t stack[kFine * kBlock];
-  const uint64_t seq = ctl->qry_seq;
+  __shared__ uint64_t lds[kWavesPerBlock];
   uint64_t covp = 0;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
-    QBox q;
-    bool bad_rect;
-    if (!query_box(ctl, k, qid[k], N, qstamp, seq, qrect[k], &q, &bad_rect)) continue;
-    uint32_t wi = q_ioff[k], wc = q_coff[k];
-    walk_leaves(nodes, stack + threadIdx.x, q, [&](uint32_t leaf, bool cov) {
-      const uint32_t cnt = leaf_beg[leaf + 1] - leaf_beg[leaf];
-      if (cnt == 0) return;
-      if (cov && covering) {
-        cov_leaf[wc++] = leaf;
-        covp += cnt;
+  if (ctl->go_split) {
+    const uint64_t seq = ctl->qry_seq;
+    tr.tlev = ctl->tlev;
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
+      const uint32_t n = q_ni[k] + q_nc[k];
+      if (n == 0) continue;
+      uint32_t wi = q_ioff[k], wc = q_coff[k];
+      auto emit = [&](uint32_t leaf, bool c) {
+        if (c) {
+          cov_leaf[wc++] = leaf;
+          covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
+        } else {
+          const uint32_t slot = leaf_sqoff[leaf] + atomicSub(&leaf_nsq[leaf], 1u) - 1u;
+          sq_q[slot] = k;
+          sq_s[slot] = wi++;
+        }
+      };
+      if (n <= slots) {
+        const uint32_t *lst = qlist + (uint64_t)k * slots;
+        for (uint32_t i = 0; i < n; ++i) {
+          const uint32_t e = lst[i];
+          emit(e & ~kLeafBit, (e & kLeafBit) != 0);
+        }
       } else {
-        const uint32_t slot = leaf_sqoff[leaf] + atomicSub(&leaf_nsq[leaf], 1u) - 1u;
-        sq_q[slot] = k;
-        sq_s[slot] = wi++;
+        QBox q;
+        bool bad_rect;
+        query_box(ctl, k, qid[k], N, qstamp, seq, qrect[k], &q, &bad_rect);
+        auto visit = [&](uint32_t leaf, bool cov) {
+          if (leaf_beg[leaf + 1] == leaf_beg[leaf]) return;
+          emit(leaf, cov && covering);
+        };
+        for_each_leaf(tr, stack + threadIdx.x, q, visit);
       }
-    });
+    }
   }
   covp = wave_sum(covp);
-  if (lane_id() == 0 && covp) atomicAdd((unsigned long long *)&ctl->cov_pairs, (unsigned long long)covp);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = covp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) t += lds[w];
+    red[kRedCovPairs * kChunkBlocks + blockIdx.x] = t;
+  }
 }
 
 // -------------------------------------------------------------- schedule --
-// Tasks = leaves with at least one intersecting subquery, in Morton order;
-// with reordering, heaviest first (weight = subqueries x objects), ties in
-// leaf order (the sort is stable).
-
-__global__ void __launch_bounds__(kBlock) k_task_flags(const Ctl *ctl, const uint32_t *leaf_sqoff,
-                                                       uint32_t *tflag) {
-  const uint32_t n = ctl->go_split ? ctl->n_leaves : 0u;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock)
-    tflag[t] = leaf_sqoff[t + 1] > leaf_sqoff[t] ? 1u : 0u;
-}
-
-__global__ void __launch_bounds__(kBlock) k_task_write(Ctl *ctl, const uint32_t *tflag,
-                                                       const uint32_t *toff,
-                                                       const uint32_t *leaf_beg,
-                                                       const uint32_t *leaf_sqoff,
-                                                       uint32_t *tasks, uint32_t *tkey) {
-  const uint32_t n = ctl->go_split ? ctl->n_leaves : 0u;
+// Task key of every leaf: 255 - bit length of its weight |intersecting
+// subqueries| x |objects| (ascending keys = heaviest first; weight 0 last);
+// a stable one-pass radix sort of the keys gives the order, ties in leaf
+// order.  Also the per-block partials of the containment-test count, the
+// largest leaf above l_max and the number of tasks.
+__global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint32_t *leaf_beg,
+                                                      const uint32_t *leaf_sqoff,
+                                                      const uint32_t *llevel, uint32_t l_max,
+                                                      uint32_t *tkey, uint32_t *tasks,
+                                                      uint64_t *red) {
+  __shared__ uint64_t s_tests[kWavesPerBlock];
+  __shared__ uint32_t s_max[kWavesPerBlock], s_tasks[kWavesPerBlock];
+  const uint32_t n = ctl->n_leaves;
+  const bool ok = ctl->go_split != 0;
+  uint64_t tests = 0;
+  uint32_t mx = 0, nt = 0;
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
-    if (!tflag[t]) continue;
-    const uint32_t pos = toff[t];
-    const uint64_t w =
-        (uint64_t)(leaf_sqoff[t + 1] - leaf_sqoff[t]) * (leaf_beg[t + 1] - leaf_beg[t]);
-    tasks[pos] = t;
-    tkey[pos] = 0xffffffffu - (uint32_t)(w < 0xffffffffull ? w : 0xffffffffull);
+    const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
+    const uint32_t nsq = ok ? leaf_sqoff[t + 1] - leaf_sqoff[t] : 0u;
+    const uint64_t w = (uint64_t)nsq * cnt;
+    tests += w;
+    nt += w != 0;
+    if (llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
+    tkey[t] = w == 0 ? 255u : 255u - (uint32_t)(64 - __clzll((long long)w));
+    tasks[t] = t;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_tasks = n ? toff[n] : 0u;
+  tests = wave_sum(tests);
+  nt = wave_sum(nt);
+  mx = wave_max(mx);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    s_tests[w] = tests;
+    s_max[w] = mx;
+    s_tasks[w] = nt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kWavesPerBlock; ++i) {
+      tests += s_tests[i];
+      nt += s_tasks[i];
+      mx = s_max[i] > mx ? s_max[i] : mx;
+    }
+    red[kRedTests * kChunkBlocks + blockIdx.x] = tests;
+    red[kRedMaxLeaf * kChunkBlocks + blockIdx.x] = mx;
+    red[kRedTasks * kChunkBlocks + blockIdx.x] = nt;
+  }
 }
 
 // ------------------------------------------------------------------ join --
@@ -603,22 +751,23 @@ __global__ void __launch_bounds__(kBlock) k_task_write(Ctl *ctl, const uint32_t 
 // set writes its object id at the subquery's offset plus the number of set
 // bits below it (coalesced, no atomics, no bitmap in memory).
 
-__global__ void __launch_bounds__(kBlock) k_join_count(Ctl *ctl, const uint32_t *tasks,
+__global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint32_t *tasks,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
                                                        const float4 *qrect, const float2 *sxy,
                                                        uint32_t *sq_cnt) {
   if (!ctl->go_split) return;
-  const uint32_t nt = ctl->n_tasks;
+  const uint32_t nt = ctl->n_leaves;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-  uint64_t tests = 0;
-  for (uint32_t t = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < nt; t += nwaves) {
+  const uint32_t w0 =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  for (uint32_t t = w0; t < nt; t += nwaves) {
     const uint32_t leaf = tasks[t];
-    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
-    tests += (uint64_t)(oe - ob) * (se - sb);
+    if (sb == se) continue;
+    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -641,35 +790,77 @@ __global__ void __launch_bounds__(kBlock) k_join_count(Ctl *ctl, const uint32_t 
       if (lane < nk) sq_cnt[slot] = cnt;
     }
   }
-  if (lane == 0 && tests) atomicAdd((unsigned long long *)&ctl->tests, (unsigned long long)tests);
 }
 
-__global__ void k_join_check(Ctl *ctl, uint64_t cap_res) {
-  if (!ctl->go_split) return;
-  if (ctl->n_res > cap_res) {
-    ctl->err |= kErrOvfRes;
-    ctl->go_join = 0;
-  } else {
-    ctl->go_join = 1;
+// Top of the result-offset scan: total result ids, reductions of the
+// tick's partials, result capacity check, and the automatic rebuild
+// decision for the next tick.
+__global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jobs, uint64_t *part,
+                                                           const uint64_t *red, uint64_t cap_res,
+                                                           uint32_t policy, uint32_t period) {
+  __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
+  __shared__ uint32_t ldm[kChunkBlocks / kWave + 1];
+  const bool ok = ctl->go_split != 0;
+  uint64_t total = 0;
+  if (ok) {
+    total = scan_partials(part, lds);
+    if (threadIdx.x == 0) job_store(jobs.j[0], job_n(jobs.j[0]), total);
   }
+  const int t = threadIdx.x;
+  uint64_t covp, tests, tasks;
+  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedCovPairs * kChunkBlocks + t], lds, &covp);
+  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedTests * kChunkBlocks + t], lds, &tests);
+  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedTasks * kChunkBlocks + t], lds, &tasks);
+  const uint32_t mx = block_minmax_1024<true>((uint32_t)red[kRedMaxLeaf * kChunkBlocks + t], ldm);
+  if (t != 0) return;
+  ctl->max_leaf = mx;
+  ctl->tests = tests;
+  ctl->n_tasks = (uint32_t)tasks;
+  if (ok) {
+    ctl->n_res = total;
+    ctl->cov_pairs = covp;
+    if (total > cap_res) {
+      ctl->err |= kErrOvfRes;
+      ctl->go_join = 0;
+    } else {
+      ctl->go_join = 1;
+    }
+  }
+  if (ctl->err & kErrOvfTree) ctl->built = 0;
+  const bool leaf_big = mx > 2u * ctl->th_cur;
+  const bool moved_out = (uint64_t)ctl->n_outside * 100u > ctl->n_present;
+  const bool periodic = ctl->since_build + 1u >= period;
+  ctl->want_rebuild = policy == 0u && (leaf_big || moved_out || periodic || !ctl->built);
 }
 
-__global__ void __launch_bounds__(kBlock) k_join_write(const Ctl *ctl, const uint32_t *tasks,
+__global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t *tasks,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
                                                        const float4 *qrect, const float2 *sxy,
                                                        const uint32_t *sid,
-                                                       const uint64_t *res_off,
-                                                       uint32_t *res_ids) {
-  if (!ctl->go_join) return;
-  const uint32_t nt = ctl->n_tasks;
+                                                       const uint64_t *res_off, uint32_t *res_ids,
+                                                       uint32_t nq, const uint32_t *q_ioff,
+                                                       uint64_t *q_roff) {
+  const bool go = ctl->go_join != 0;
+  // per-query offsets of the intersecting results
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
+    q_roff[k] = go ? res_off[k < nq ? q_ioff[k] : ctl->n32[0]] : 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->qry_seq += nq;
+    ctl->tick += 1;
+  }
+  if (!go) return;
+  const uint32_t nt = ctl->n_leaves;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-  for (uint32_t t = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < nt; t += nwaves) {
+  const uint32_t w0 =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  for (uint32_t t = w0; t < nt; t += nwaves) {
     const uint32_t leaf = tasks[t];
-    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
+    if (sb == se) continue;
+    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -696,13 +887,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(const Ctl *ctl, const uin
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_q_final(Ctl *ctl, uint32_t nq, const uint32_t *q_ioff,
-                                                    const uint64_t *res_off, uint64_t *q_roff,
-                                                    const uint32_t *n32) {
-  const bool ok = ctl->go_join != 0;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
-    q_roff[k] = ok ? res_off[k < nq ? q_ioff[k] : n32[0]] : 0ull;
-}
+// --------------------------------------------------------------- results --
 
 __global__ void k_counters(const Ctl *ctl, uint64_t *out) {
   const bool ok = ctl->go_join != 0;
@@ -715,13 +900,6 @@ __global__ void k_counters(const Ctl *ctl, uint64_t *out) {
   out[6] = ctl->n_tasks;
   out[7] = ctl->err;
 }
-
-__global__ void k_tick_end(Ctl *ctl, uint32_t nq) {
-  ctl->qry_seq += nq;
-  ctl->tick += 1;
-}
-
-// --------------------------------------------------------------- results --
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -823,29 +1001,26 @@ void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
 }
 
 void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const float *y, uint32_t m,
-                    hipStream_t s) {
+                    uint64_t seq_off, hipStream_t s) {
   const unsigned g = grid_for(m);
-  LAUNCH(k_upd_stamp, g, kBlock, s, id, x, y, m, B.N, B.ustamp, B.ctl);
-  LAUNCH(k_upd_write, g, kBlock, s, id, x, y, m, B.N, (const uint64_t *)B.ustamp,
+  LAUNCH(k_upd_stamp, g, kBlock, s, id, x, y, m, B.N, seq_off, B.ustamp, B.ctl);
+  LAUNCH(k_upd_write, g, kBlock, s, id, x, y, m, B.N, seq_off, (const uint64_t *)B.ustamp,
          (const Ctl *)B.ctl, B.px, B.py);
-  LAUNCH(k_upd_end, 1, 1, s, B.ctl, m);
 }
 
-void launch_index(const Bufs &B, uint32_t policy, uint32_t period, hipStream_t s) {
-  LAUNCH(k_tick_begin, 1, 1, s, B.ctl);
-  LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N, B.ctl,
-         B.blk);
-  LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, policy, period);
-  LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N,
-         (const Ctl *)B.ctl, (const uint32_t *)B.blk, B.keyA, B.valA);
+void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
+                  const uint32_t *qid, uint32_t nq, hipStream_t s) {
+  LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N,
+         (const Ctl *)B.ctl, B.blk, B.red);
+  LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, (const uint64_t *)B.red, B.front[0],
+         decision, policy, upd_total);
+  LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N, B.ctl,
+         (const uint32_t *)B.blk, B.keyA, B.valA, qid, nq, B.qstamp);
   radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist, B.tot, 0,
-                   32, s);
-  LAUNCH(k_gather, grid_for(B.N), kBlock, s, (const float *)B.px, (const float *)B.py,
-         (const uint32_t *)B.valA, (const Ctl *)B.ctl, B.sxy);
+                   32, s, B.px, B.py, B.sxy);
 }
 
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
-  LAUNCH(k_tree_init, 1, 1, s, B.ctl, B.front[0]);
   for (uint32_t l = 1; l <= l_max; ++l) {
     LAUNCH(k_tree_level, grid_for(B.FCAP), kBlock, s, B.ctl, l, l_max, (const uint32_t *)B.keyA,
            (const uint4 *)B.front[(l - 1) & 1], B.front[l & 1], B.FCAP, B.lstart, B.llevel,
@@ -856,73 +1031,75 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
                    B.hist, B.tot, 0, 32, s);
   LAUNCH(k_nodes_open, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
          (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.nopen);
-  scan_excl<uint32_t>(B.nopen, B.node_off, &B.ctl->n_leaves, 0, B.part, nullptr,
-                      &B.ctl->rebuild, s);
+  ScanJobs jobs{};
+  jobs.j[0] = job_u32(B.nopen, B.node_off, &B.ctl->n_leaves, 0);
+  mscan(jobs, 1, B.part, &B.ctl->rebuild, nullptr, s);
   LAUNCH(k_nodes_build, grid_for(B.LCAP), kBlock, s, B.ctl, (const uint32_t *)B.lstart,
          (const uint32_t *)B.llevel, (const uint32_t *)B.node_off, B.nodes, B.NCAP);
+  LAUNCH(k_table_build, kTableCells / kBlock, kBlock, s, (const Ctl *)B.ctl,
+         (const uint4 *)B.nodes, B.table);
 }
 
-void launch_leaves(const Bufs &B, uint32_t l_max, hipStream_t s) {
+void launch_leaves(const Bufs &B, hipStream_t s) {
   LAUNCH(k_leaf_ranges, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
          (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg, B.leaf_nsq);
-  LAUNCH(k_leaf_stats, grid_for(B.LCAP), kBlock, s, B.ctl, (const uint32_t *)B.leaf_beg,
-         (const uint32_t *)B.llevel, l_max);
+}
+
+static Tree tree_of(const Bufs &B) {
+  return Tree{(const uint4 *)B.nodes, (const uint32_t *)B.table, (const uint32_t *)B.lstart,
+              (const uint32_t *)B.llevel, 0u};
 }
 
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s) {
-  const unsigned gq = grid_for(nq, 4096);
-  LAUNCH(k_q_stamp, gq, kBlock, s, qid, nq, B.N, B.qstamp, B.ctl);
-  LAUNCH(k_q_count, gq, kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
-         (const uint64_t *)B.qstamp, (const uint4 *)B.nodes, (const uint32_t *)B.leaf_beg,
-         B.qrect, B.q_ni, B.q_nc, B.leaf_nsq, covering);
-  scan_excl<uint32_t>(B.q_ni, B.q_ioff, nullptr, nq, B.part, &B.ctl->n_isect, nullptr, s);
-  scan_excl<uint32_t>(B.q_nc, B.q_coff, nullptr, nq, B.part, &B.ctl->n_cov, nullptr, s);
-  scan_excl<uint32_t>(B.leaf_nsq, B.leaf_sqoff, &B.ctl->n_leaves, 0, B.part, nullptr, nullptr, s);
-  LAUNCH(k_split_check, 1, 1, s, B.ctl, B.S, B.C, B.n32);
-  LAUNCH(k_q_write, gq, kBlock, s, B.ctl, qid, nq, B.N, (const uint64_t *)B.qstamp,
-         (const uint4 *)B.nodes, (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
-         (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.leaf_sqoff,
-         B.leaf_nsq, B.sq_q, B.sq_s, B.cov_leaf, covering);
+  LAUNCH(k_q_count, grid_for(nq, 4096), kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
+         (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
+         B.q_nc, B.leaf_nsq, B.qlist, B.slots, covering);
+  ScanJobs jobs{};
+  jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
+  jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
+  jobs.j[2] = job_u32(B.leaf_nsq, B.leaf_sqoff, &B.ctl->n_leaves, 0);
+  mscan_reduce(jobs, 3, B.part, nullptr, s);
+  LAUNCH(k_split_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, B.S, B.C);
+  mscan_down(jobs, 3, (const uint64_t *)B.part, nullptr, s);
+  LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, qid, nq, B.N, (const uint64_t *)B.qstamp,
+         tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
+         (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
+         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots,
+         (const uint32_t *)B.leaf_sqoff, B.leaf_nsq, B.sq_q, B.sq_s, B.cov_leaf, covering, B.red);
 }
 
-void launch_schedule(const Bufs &B, uint32_t reorder, hipStream_t s) {
-  LAUNCH(k_task_flags, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
-         (const uint32_t *)B.leaf_sqoff, B.tflag);
-  scan_excl<uint32_t>(B.tflag, B.toff, &B.ctl->n_leaves, 0, B.part, nullptr, &B.ctl->go_split,
-                      s);
-  LAUNCH(k_task_write, grid_for(B.LCAP), kBlock, s, B.ctl, (const uint32_t *)B.tflag,
-         (const uint32_t *)B.toff, (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff,
-         B.tasks, B.tkey);
-  if (reorder)
-    radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_tasks, &B.ctl->go_split,
-                     B.hist, B.tot, 0, 32, s);
+const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, hipStream_t s) {
+  LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)B.leaf_beg,
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks, B.red);
+  if (!reorder) return B.tasks;
+  const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_leaves,
+                                    &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
+  return alt ? B.tasks2 : B.tasks;
 }
 
-void launch_join_count(const Bufs &B, hipStream_t s) {
-  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, B.ctl, (const uint32_t *)B.tasks,
+void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s) {
+  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, tasks,
          (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
          (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt);
 }
 
-void launch_join_scan(const Bufs &B, uint64_t cap_res, hipStream_t s) {
-  scan_excl<uint64_t>(B.sq_cnt, B.res_off, &B.n32[0], 0, B.part, &B.ctl->n_res, &B.ctl->go_split,
-                      s);
-  LAUNCH(k_join_check, 1, 1, s, B.ctl, cap_res);
+void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
+                      hipStream_t s) {
+  ScanJobs jobs{};
+  jobs.j[0] = job_u64(B.sq_cnt, B.res_off, &B.ctl->n32[0], 0);
+  mscan_reduce(jobs, 1, B.part, &B.ctl->go_split, s);
+  LAUNCH(k_join_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, (const uint64_t *)B.red, cap_res,
+         policy, period);
+  mscan_down(jobs, 1, (const uint64_t *)B.part, &B.ctl->go_split, s);
 }
 
-void launch_join_write(const Bufs &B, hipStream_t s) {
-  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)B.tasks,
-         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
-         (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy,
-         (const uint32_t *)B.valA, (const uint64_t *)B.res_off, B.res_ids);
-}
-
-void launch_finish(const Bufs &B, uint32_t nq, hipStream_t s) {
-  LAUNCH(k_q_final, grid_for(nq + 1, 4096), kBlock, s, B.ctl, nq, (const uint32_t *)B.q_ioff,
-         (const uint64_t *)B.res_off, B.q_roff, (const uint32_t *)B.n32);
-  LAUNCH(k_tick_end, 1, 1, s, B.ctl, nq);
+void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s) {
+  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, tasks, (const uint32_t *)B.leaf_beg,
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
+         (const float4 *)B.qrect, (const float2 *)B.sxy, (const uint32_t *)B.valA,
+         (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff);
 }
 
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s) {
@@ -937,19 +1114,20 @@ void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt,
          cnt, hash);
 }
 
+void launch_expand_count(const Bufs &B, uint32_t nq, uint64_t *off, hipStream_t s) {
+  LAUNCH(k_exp_count, grid_for(nq, 4096), kBlock, s, (const Ctl *)B.ctl, nq,
+         (const uint64_t *)B.q_roff, (const uint32_t *)B.q_coff, (const uint32_t *)B.cov_leaf,
+         (const uint32_t *)B.leaf_beg, B.q_ni);
+  ScanJobs jobs{};
+  jobs.j[0] = job_u64(B.q_ni, off, nullptr, nq);
+  mscan(jobs, 1, B.part, nullptr, nullptr, s);
+}
+
 void launch_expand(const Bufs &B, uint32_t nq, uint64_t *off, uint32_t *ids, hipStream_t s) {
   LAUNCH(k_exp_write, grid_for((uint64_t)nq * kWave, 4096), kBlock, s, (const Ctl *)B.ctl, nq,
          (const uint64_t *)B.q_roff, (const uint32_t *)B.res_ids, (const uint32_t *)B.q_coff,
          (const uint32_t *)B.cov_leaf, (const uint32_t *)B.leaf_beg, (const uint32_t *)B.valA,
          (const uint64_t *)off, ids);
-}
-
-void launch_expand_count(const Bufs &B, uint32_t nq, uint64_t *off, hipStream_t s) {
-  LAUNCH(k_exp_count, grid_for(nq, 4096), kBlock, s, (const Ctl *)B.ctl, nq,
-         (const uint64_t *)B.q_roff,
-         (const uint32_t *)B.q_coff, (const uint32_t *)B.cov_leaf, (const uint32_t *)B.leaf_beg,
-         B.q_ni);
-  scan_excl<uint64_t>(B.q_ni, off, nullptr, nq, B.part, nullptr, nullptr, s);
 }
 
 }  // namespace sj

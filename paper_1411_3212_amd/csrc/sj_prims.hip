@@ -1,98 +1,107 @@
-// Data-parallel primitives of libsj: chunked exclusive scans and a stable
-// LDS-staged LSD radix sort of (u32 key, u32 value) pairs.
+// Data-parallel primitives of libsj: chunked multi-array exclusive scans and
+// a stable LDS-staged LSD radix sort of (u32 key, u32 value) pairs.
 //
-// All kernels take their element count from device memory (or from a host
-// value when the device pointer is null) and an optional gate word: when the
-// gate reads 0 the kernel returns at once.  The grids are fixed, so a
-// sequence of launches does not depend on sizes produced on the device.
+// All kernels take their element counts from device memory (or from a host
+// value) and an optional gate word: when the gate reads 0 the kernel returns
+// at once.  Grids are fixed, so a launch sequence does not depend on sizes
+// produced on the device.
 #include "sj_device.h"
 #include "sj_host.h"
 
 namespace sj {
 
 __device__ __forceinline__ bool gated(const uint32_t *gate) { return gate && *gate == 0u; }
-__device__ __forceinline__ uint32_t count_of(const uint32_t *n_dev, uint32_t n_host) {
-  return n_dev ? *n_dev : n_host;
-}
 
 // ---------------------------------------------------------------- scans --
-// Exclusive scan of a u32 array, result type T; out[n] = total.  Block b of
-// kChunkBlocks owns the contiguous chunk [b*chunk, (b+1)*chunk).
+// Block b of kChunkBlocks owns the contiguous chunk [b*chunk, (b+1)*chunk)
+// of every array.  reduce: chunk sums -> part[job][b]; a single-block "top"
+// kernel scans part[job][*] (scan_partials) and stores the totals; down:
+// every block scans its chunk with its partial as carry-in.
 
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(const uint32_t *in, const uint32_t *n_dev,
-                                                        uint32_t n_host, const uint32_t *gate,
-                                                        uint64_t *part) {
+__global__ void __launch_bounds__(kBlock) k_mscan_reduce(ScanJobs jobs, uint64_t *part,
+                                                         const uint32_t *gate) {
   if (gated(gate)) return;
   __shared__ uint64_t lds[kWavesPerBlock];
-  const uint32_t n = count_of(n_dev, n_host);
+  const ScanJob &j = jobs.j[blockIdx.y];
+  const uint32_t n = job_n(j);
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   uint64_t s = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += in[i];
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += j.in[i];
   s = wave_sum(s);
   if (lane_id() == 0) lds[threadIdx.x / kWave] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t t = 0;
     for (int w = 0; w < kWavesPerBlock; ++w) t += lds[w];
-    part[blockIdx.x] = t;
+    part[blockIdx.y * kChunkBlocks + blockIdx.x] = t;
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kChunkBlocks) k_scan_top(uint64_t *part, T *out,
-                                                           const uint32_t *n_dev, uint32_t n_host,
-                                                           const uint32_t *gate,
-                                                           uint64_t *total_out) {
-  if (gated(gate)) return;
-  __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
-  uint64_t total;
-  uint64_t v = part[threadIdx.x];
-  uint64_t ex = block_excl_scan<uint64_t, kChunkBlocks>(v, lds, &total);
-  part[threadIdx.x] = ex;
-  if (threadIdx.x == 0) {
-    out[count_of(n_dev, n_host)] = (T)total;
-    if (total_out) *total_out = total;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_down(const uint32_t *in, T *out,
-                                                      const uint32_t *n_dev, uint32_t n_host,
-                                                      const uint32_t *gate, const uint64_t *part) {
+__global__ void __launch_bounds__(kBlock) k_mscan_down(ScanJobs jobs, const uint64_t *part,
+                                                       const uint32_t *gate) {
   if (gated(gate)) return;
   __shared__ uint64_t lds[kWavesPerBlock + 1];
-  const uint32_t n = count_of(n_dev, n_host);
+  const ScanJob &j = jobs.j[blockIdx.y];
+  const uint32_t n = job_n(j);
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
-  uint64_t run = part[blockIdx.x];
+  uint64_t run = part[blockIdx.y * kChunkBlocks + blockIdx.x];
   for (uint64_t t0 = b0; t0 < b1; t0 += kBlock) {
     const uint64_t i = t0 + threadIdx.x;
-    uint64_t v = i < b1 ? in[i] : 0;
+    const uint64_t v = i < b1 ? j.in[i] : 0;
     uint64_t tot;
-    uint64_t ex = block_excl_scan<uint64_t, kBlock>(v, lds, &tot);
-    if (i < b1) out[i] = (T)(run + ex);
+    const uint64_t ex = block_excl_scan<uint64_t, kBlock>(v, lds, &tot);
+    if (i < b1) job_store(j, i, run + ex);
     run += tot;
   }
 }
 
-template <typename T>
-void scan_excl(const uint32_t *in, T *out, const uint32_t *n_dev, uint32_t n_host,
-               uint64_t *part, uint64_t *total_out, const uint32_t *gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_reduce, dim3(kChunkBlocks), dim3(kBlock), 0, s, in, n_dev, n_host,
-                     gate, part);
-  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kChunkBlocks), 0, s, part, out, n_dev, n_host,
-                     gate, total_out);
-  hipLaunchKernelGGL(k_scan_down<T>, dim3(kChunkBlocks), dim3(kBlock), 0, s, in, out, n_dev,
-                     n_host, gate, (const uint64_t *)part);
+// Generic top: totals to out[n] and optionally to total_out[job].
+__global__ void __launch_bounds__(kChunkBlocks) k_mscan_top(ScanJobs jobs, int njobs,
+                                                            uint64_t *part, const uint32_t *gate,
+                                                            uint64_t *t0, uint64_t *t1,
+                                                            uint64_t *t2) {
+  if (gated(gate)) return;
+  __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
+  uint64_t *tout[3] = {t0, t1, t2};
+  for (int q = 0; q < njobs; ++q) {
+    const uint64_t total = scan_partials(part + q * kChunkBlocks, lds);
+    if (threadIdx.x == 0) {
+      job_store(jobs.j[q], job_n(jobs.j[q]), total);
+      if (tout[q]) *tout[q] = total;
+    }
+  }
 }
 
-template void scan_excl<uint32_t>(const uint32_t *, uint32_t *, const uint32_t *, uint32_t,
-                                  uint64_t *, uint64_t *, const uint32_t *, hipStream_t);
-template void scan_excl<uint64_t>(const uint32_t *, uint64_t *, const uint32_t *, uint32_t,
-                                  uint64_t *, uint64_t *, const uint32_t *, hipStream_t);
+void mscan_reduce(const ScanJobs &jobs, int njobs, uint64_t *part, const uint32_t *gate,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_mscan_reduce, dim3(kChunkBlocks, njobs), dim3(kBlock), 0, s, jobs, part,
+                     gate);
+}
+
+void mscan_down(const ScanJobs &jobs, int njobs, const uint64_t *part, const uint32_t *gate,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_mscan_down, dim3(kChunkBlocks, njobs), dim3(kBlock), 0, s, jobs, part,
+                     gate);
+}
+
+void mscan(const ScanJobs &jobs, int njobs, uint64_t *part, const uint32_t *gate,
+           uint64_t *total0, hipStream_t s) {
+  mscan_reduce(jobs, njobs, part, gate, s);
+  hipLaunchKernelGGL(k_mscan_top, dim3(1), dim3(kChunkBlocks), 0, s, jobs, njobs, part, gate,
+                     total0, (uint64_t *)nullptr, (uint64_t *)nullptr);
+  mscan_down(jobs, njobs, part, gate, s);
+}
+
+ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host) {
+  return ScanJob{in, out, n_dev, n_host, 0u};
+}
+ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32_t n_host) {
+  return ScanJob{in, out, n_dev, n_host, 1u};
+}
 
 // ----------------------------------------------------------- radix sort --
 // One pass sorts by the 8-bit digit (key >> shift) & 255, stably:
@@ -101,7 +110,8 @@ template void scan_excl<uint64_t>(const uint32_t *, uint64_t *, const uint32_t *
 //  scatter: every block ranks its keys tile by tile (wave ballots give the
 //           rank among equal digits of a wave), places the tile in LDS in
 //           digit order and writes each digit's run contiguously to its
-//           global offset.
+//           global offset.  The last pass can also gather the positions of
+//           the sorted values (sorted SoA of the objects).
 
 __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const uint32_t *n_dev,
                                                     const uint32_t *gate, int shift,
@@ -130,13 +140,15 @@ __global__ void __launch_bounds__(kChunkBlocks) k_rs_hscan(uint32_t *hist, const
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
+template <bool GATHER>
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restrict__ kin,
                                                        const uint32_t *__restrict__ vin,
                                                        uint32_t *__restrict__ kout,
                                                        uint32_t *__restrict__ vout,
                                                        const uint32_t *n_dev, const uint32_t *gate,
                                                        int shift, const uint32_t *hist,
-                                                       const uint32_t *tot) {
+                                                       const uint32_t *tot, const float *gx,
+                                                       const float *gy, float2 *gout) {
   if (gated(gate)) return;
   __shared__ uint32_t cnt[kSortItems * kWavesPerBlock * 256];
   __shared__ uint32_t sk[kSortTile];
@@ -148,6 +160,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  if (b0 >= b1) return;  // uniform per block: no barrier is skipped by part of it
   const int tid = threadIdx.x, w = tid / kWave;
   {
     uint32_t total;
@@ -207,8 +220,10 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       const uint32_t k = sk[i];
       const uint32_t d = (k >> shift) & 255u;
       const uint32_t g = goff[d] + (i - tbase[d]);
+      const uint32_t v = sv[i];
       kout[g] = k;
-      vout[g] = sv[i];
+      vout[g] = v;
+      if (GATHER) gout[g] = make_float2(gx[v], gy[v]);
     }
     __syncthreads();
     goff[tid] += tcnt[tid];
@@ -216,24 +231,35 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   }
 }
 
-void radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, const uint32_t *gate, uint32_t *hist, uint32_t *tot,
-                      int bit_begin, int bit_end, hipStream_t s) {
+                      int bit_begin, int bit_end, hipStream_t s, const float *gx,
+                      const float *gy, float2 *gout) {
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  bool in_alt = false;
   for (int shift = bit_begin; shift < bit_end; shift += 8) {
+    const bool last = shift + 8 >= bit_end;
     hipLaunchKernelGGL(k_rs_hist, dim3(kChunkBlocks), dim3(kBlock), 0, s, (const uint32_t *)ki,
                        n_dev, gate, shift, hist);
     hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, tot);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(kChunkBlocks), dim3(kBlock), 0, s,
-                       (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, shift,
-                       (const uint32_t *)hist, (const uint32_t *)tot);
+    if (last && gout)
+      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
+                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, shift,
+                         (const uint32_t *)hist, (const uint32_t *)tot, gx, gy, gout);
+    else
+      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
+                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, shift,
+                         (const uint32_t *)hist, (const uint32_t *)tot, (const float *)nullptr,
+                         (const float *)nullptr, (float2 *)nullptr);
     uint32_t *t = ki;
     ki = ko;
     ko = t;
     t = vi;
     vi = vo;
     vo = t;
+    in_alt = !in_alt;
   }
+  return in_alt;
 }
 
 }  // namespace sj

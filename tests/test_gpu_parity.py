@@ -112,7 +112,7 @@ def test_split_and_work_counters_equal_oracle(th):
     cl = r.cov_leaf.cpu().numpy().view(np.uint32)
     for k in range(t.nq):
         want = [x for x in lc[oc[k]:oc[k + 1]] if cnt[x] > 0]
-        assert cl[co[k]:co[k + 1]].tolist() == want
+        assert sorted(cl[co[k]:co[k + 1]].tolist()) == want
 
 
 def test_edges_corners_signed_zero_and_degenerate_queries():
@@ -292,6 +292,31 @@ def test_partial_updates_keep_last_known_positions():
         oracle_apply(st, part)
         gpu_tick(sc, part)
         assert sc.fetch().to_lists() == oracle_lists(st, part), f"tick {k}"
+
+
+def test_several_update_calls_in_one_tick():
+    # three calls before one tick: the latest update of an object wins across
+    # calls; objects not updated keep their position from earlier ticks
+    n = 2000
+    rng = np.random.default_rng(7)
+    st = oracle.State(n)
+    sc = Scene(n, n, th=16)
+    for k in range(3):
+        calls = []
+        for c in range(3):
+            ids = rng.choice(n, n // 2, replace=True).astype(np.uint32)
+            if k == 0 and c == 0:
+                ids = np.arange(n, dtype=np.uint32)
+            calls.append(T(ids=ids, x=rng.random(len(ids)), y=rng.random(len(ids))))
+        qid = rng.choice(n, 200, replace=True).astype(np.uint32)  # repeated issuers
+        c = rng.random((200, 2))
+        q = T(qid=qid, rects=tuple(a.astype(F32) for a in (c[:, 0], c[:, 1], c[:, 0] + 0.05,
+                                                           c[:, 1] + 0.05)))
+        for u in calls:
+            oracle_apply(st, u)
+            sc.apply_updates(dev_u32(u.ids), dev_f32(u.x), dev_f32(u.y))
+        sc.run_tick(dev_u32(q.qid), *(dev_f32(r) for r in q.rects))
+        assert sc.fetch().to_lists() == oracle_lists(st, q), f"tick {k}"
 
 
 # ------------------------------------------------------------- full size
