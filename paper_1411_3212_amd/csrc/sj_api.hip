@@ -41,7 +41,7 @@ static char g_create_err[256] = "";
 namespace {
 
 struct Derived {
-  uint32_t N, Q, th, th_min, l_max, period, slots;
+  uint32_t N, Q, th, th_min, l_max, period, slots, tcap;
   uint64_t S, C, R;
   uint32_t LCAP, NCAP, FCAP;
 };
@@ -100,10 +100,16 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
     if (c > fmax) fmax = c;
   }
   const uint64_t leaves = 3u * splits + 1u;
-  if (leaves >= 0x7fffffffull) {
-    snprintf(msg, msz, "quadtree bound too large: raise th_min");
+  if (leaves >= (1ull << 27)) {
+    snprintf(msg, msz, "quadtree bound above 2^27 leaves: raise th_min");
     return SJ_EINVAL;
   }
+  // Start-table level cap: about four levels below the depth of a uniform
+  // tree with th_min objects per leaf, within [4, 12] and l_max.
+  uint32_t lu = 0;
+  for (uint64_t c = 1; c < per; c *= 4u) ++lu;
+  d->tcap = lu + 4u < 4u ? 4u : (lu + 4u > 12u ? 12u : lu + 4u);
+  if (d->tcap > d->l_max) d->tcap = d->l_max;
   d->LCAP = (uint32_t)leaves;
   d->NCAP = (uint32_t)splits;
   d->FCAP = (uint32_t)fmax;
@@ -150,7 +156,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.nopen = c.take<uint32_t>(L);
   b.node_off = c.take<uint32_t>(L + 1);
   b.nodes = c.take<uint4>(d.NCAP);
-  b.table = c.take<uint32_t>(1u << 16);
+  b.table = c.take<uint32_t>(1ull << (2 * d.tcap));
   b.leaf_beg = c.take<uint32_t>(L + 1);
   b.leaf_nsq = c.take<uint32_t>(L);
   b.leaf_sqoff = c.take<uint32_t>(L + 1);
@@ -177,6 +183,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.NCAP = d.NCAP;
   b.FCAP = d.FCAP;
   b.slots = d.slots;
+  b.tcap = d.tcap;
   b.S = d.S;
   b.C = d.C;
   b.R = d.R;

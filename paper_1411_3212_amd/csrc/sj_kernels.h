@@ -29,7 +29,7 @@ struct Bufs {
   uint32_t *lstart, *llevel, *lstart2, *llevel2;
   uint32_t *nopen, *node_off;
   uint4 *nodes;
-  uint32_t *table;                      // start table (4^8 entries)
+  uint32_t *table;                      // start table (4^tcap entries)
   uint32_t *leaf_beg, *leaf_nsq, *leaf_sqoff;
   // schedule
   uint32_t *tasks, *tkey, *tasks2, *tkey2;
@@ -42,7 +42,7 @@ struct Bufs {
   uint64_t *res_off;
   uint32_t *cov_leaf, *res_ids;
   // capacities
-  uint32_t N, Q, LCAP, NCAP, FCAP, slots;
+  uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap;
   uint64_t S, C, R;
 };
 

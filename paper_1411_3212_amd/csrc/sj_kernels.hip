@@ -25,9 +25,10 @@
 
 namespace sj {
 
-constexpr uint32_t kTableLevel = 8;      // deepest level of the start table
-constexpr uint32_t kTableCells = 1u << (2 * kTableLevel);
-constexpr uint32_t kTableScanMax = 64;   // larger queries start at the root
+constexpr uint32_t kTableScanMax = 1024;  // queries over more table cells start at the root
+// Start-table entry of a leaf: flag, level - 1 (4 bits), leaf index (27 bits).
+constexpr uint32_t kLeafIdxBits = 27;
+constexpr uint32_t kLeafIdxMask = (1u << kLeafIdxBits) - 1u;
 
 // ------------------------------------------------------------- utilities --
 
@@ -376,13 +377,13 @@ __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uin
 
 // The leaf table is sized for the worst case of the smallest threshold, so
 // this never fires; if it did, the tick is flagged and no traversal runs.
-__global__ void k_tree_done(Ctl *ctl, uint32_t lcap) {
+__global__ void k_tree_done(Ctl *ctl, uint32_t lcap, uint32_t tcap) {
   if (!ctl->rebuild) return;
   if (ctl->n_leaves > lcap) {
     ctl->n_leaves = lcap;
     ctl->err |= kErrOvfTree;
   }
-  ctl->tlev = ctl->l_deep < kTableLevel ? ctl->l_deep : kTableLevel;
+  ctl->tlev = ctl->l_deep < tcap ? ctl->l_deep : tcap;
 }
 
 __device__ __forceinline__ uint32_t open_level(uint32_t s) {
@@ -432,23 +433,25 @@ __global__ void __launch_bounds__(kBlock) k_nodes_build(Ctl *ctl, const uint32_t
   }
 }
 
-// Start table at level T = min(l_deep, 8): for every level-T cell, the leaf
-// that contains it (a leaf at level <= T) or the internal node at level T.
-__global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const uint4 *nodes,
+// Start table at level T = min(l_deep, cap) in Morton order (the paper's
+// z_map, with its depth capped): for every level-T cell, the leaf that
+// contains it when that leaf is at a level <= T (entry: flag, level - 1,
+// leaf index), otherwise the internal node at level T (entry: node index).
+__global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const uint32_t *lstart,
+                                                        const uint32_t *llevel,
+                                                        const uint32_t *node_off,
                                                         uint32_t *table) {
   if (!ctl->rebuild || (ctl->err & kErrOvfTree)) return;
-  const uint32_t T = ctl->tlev;
-  const uint32_t ncell = 1u << (2 * T);
+  const uint32_t T = ctl->tlev, n = ctl->n_leaves;
+  const uint32_t ncell = 1u << (2 * T), sh = 2u * (kFine - T);
   for (uint32_t z = blockIdx.x * kBlock + threadIdx.x; z < ncell; z += gridDim.x * kBlock) {
-    const uint32_t ci = compact16(z), cj = compact16(z >> 1);
-    uint32_t ref = 0;  // root
-    for (uint32_t k = 0; k < T; ++k) {
-      const uint32_t c = ((ci >> (T - k - 1)) & 1u) | (((cj >> (T - k - 1)) & 1u) << 1);
-      const uint4 rec = nodes[ref];
-      ref = c == 0 ? rec.x : c == 1 ? rec.y : c == 2 ? rec.z : rec.w;
-      if (ref & kLeafBit) break;
-    }
-    table[z] = ref;
+    const uint32_t code = T == kFine ? z : z << sh;
+    // leaf containing code: the last leaf whose start is <= code
+    uint32_t u = lower_bound_u32(lstart, 0u, n, code);
+    if (u == n || lstart[u] != code) --u;
+    const uint32_t l = llevel[u];
+    table[z] = l <= T ? (kLeafBit | ((l - 1u) << kLeafIdxBits) | u)
+                      : node_off[u] + (T - open_level(code));
   }
 }
 
@@ -486,69 +489,95 @@ struct Tree {
   uint32_t tlev;
 };
 
+// Depth-first walk below internal node `node` at level depth0 with cell
+// coordinates (pi, pj) at that level, one node per iteration: its children
+// overlapping the query are classified at once, leaf children visited,
+// and the walk descends into the first overlapping internal child, keeping
+// the others as a 4-bit mask per level on the stack.
 template <typename Visit>
 __device__ __forceinline__ void walk_from(const uint4 *__restrict__ nodes, uint32_t *stack,
                                           uint32_t node, uint32_t depth0, uint32_t pi,
                                           uint32_t pj, const QBox q, Visit &visit) {
-  uint32_t depth = depth0, c = 0;
+  uint32_t depth = depth0;
   uint4 rec = nodes[node];
   while (true) {
-    if (c < 4) {
+    const uint32_t s = (uint32_t)kFine - (depth + 1);
+    const uint32_t span = (1u << s) - 1u;
+    uint32_t imask = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
       const uint32_t ref = c == 0 ? rec.x : c == 1 ? rec.y : c == 2 ? rec.z : rec.w;
-      const uint32_t ci = 2u * pi + (c & 1u), cj = 2u * pj + (c >> 1);
-      const uint32_t s = (uint32_t)kFine - (depth + 1);
-      const uint32_t ilo = ci << s, ihi = ilo + ((1u << s) - 1u);
-      const uint32_t jlo = cj << s, jhi = jlo + ((1u << s) - 1u);
-      const bool ov = ilo <= q.i1 && q.i0 <= ihi && jlo <= q.j1 && q.j0 <= jhi;
-      if (ov && !(ref & kLeafBit) && depth + 1 < (uint32_t)kFine) {
-        stack[depth * kBlock] = node;
-        ++depth;
-        node = ref;
-        pi = ci;
-        pj = cj;
-        c = 0;
-        rec = nodes[node];
-        continue;
-      }
-      if (ov && (ref & kLeafBit))
+      const uint32_t ilo = (2u * pi + (c & 1u)) << s, jlo = (2u * pj + (c >> 1)) << s;
+      const uint32_t ihi = ilo + span, jhi = jlo + span;
+      if (!(ilo <= q.i1 && q.i0 <= ihi && jlo <= q.j1 && q.j0 <= jhi)) continue;
+      if (ref & kLeafBit)
         visit(ref & ~kLeafBit, q.i0 < ilo && ihi < q.i1 && q.j0 < jlo && jhi < q.j1);
-      ++c;
-    } else {
-      if (depth == depth0) break;
-      --depth;
-      c = ((pi & 1u) | ((pj & 1u) << 1)) + 1u;
-      pi >>= 1;
-      pj >>= 1;
-      node = stack[depth * kBlock];
-      rec = nodes[node];
+      else if (depth + 1 < (uint32_t)kFine)
+        imask |= 1u << c;
     }
+    if (!imask) {
+      // pop to the deepest level with a pending internal child
+      while (true) {
+        if (depth == depth0) return;
+        --depth;
+        pi >>= 1;
+        pj >>= 1;
+        const uint32_t e = stack[depth * kBlock];
+        imask = e >> 28;
+        if (imask) {
+          node = e & 0x0fffffffu;
+          rec = nodes[node];
+          break;
+        }
+      }
+    }
+    const uint32_t c = (uint32_t)__ffs(imask) - 1u;
+    stack[depth * kBlock] = node | ((imask & ~(1u << c)) << 28);
+    node = c == 0 ? rec.x : c == 1 ? rec.y : c == 2 ? rec.z : rec.w;
+    pi = 2u * pi + (c & 1u);
+    pj = 2u * pj + (c >> 1);
+    ++depth;
+    rec = nodes[node];
   }
 }
 
+// Leaves overlapping a query: the query's cells of the start table are
+// read in batches; a leaf entry is visited at the cell with minimal
+// coordinates among the query's cells of that leaf, an internal node is
+// walked.  Queries over more than kTableScanMax cells walk from the root.
 template <typename Visit>
 __device__ __forceinline__ void for_each_leaf(const Tree &tr, uint32_t *stack, const QBox q,
                                               Visit &visit) {
   const uint32_t T = tr.tlev, sh = (uint32_t)kFine - T;
   const uint32_t ti0 = q.i0 >> sh, ti1 = q.i1 >> sh, tj0 = q.j0 >> sh, tj1 = q.j1 >> sh;
-  if ((ti1 - ti0 + 1) * (tj1 - tj0 + 1) > kTableScanMax) {
+  const uint32_t w = ti1 - ti0 + 1, ncell = w * (tj1 - tj0 + 1);
+  if (ncell > kTableScanMax) {
     walk_from(tr.nodes, stack, 0u, 0u, 0u, 0u, q, visit);
     return;
   }
-  for (uint32_t cj = tj0; cj <= tj1; ++cj) {
-    for (uint32_t ci = ti0; ci <= ti1; ++ci) {
-      const uint32_t ref = tr.table[morton2(ci, cj)];
-      if (!(ref & kLeafBit)) {
-        walk_from(tr.nodes, stack, ref, T, ci, cj, q, visit);
+  constexpr uint32_t kB = 4;
+  for (uint32_t c0 = 0; c0 < ncell; c0 += kB) {
+    uint32_t ent[kB];
+#pragma unroll
+    for (uint32_t b = 0; b < kB; ++b) {
+      const uint32_t c = c0 + b;
+      ent[b] = c < ncell ? tr.table[morton2(ti0 + c % w, tj0 + c / w)] : 0u;
+    }
+#pragma unroll
+    for (uint32_t b = 0; b < kB; ++b) {
+      const uint32_t c = c0 + b;
+      if (c >= ncell) break;
+      const uint32_t ci = ti0 + c % w, cj = tj0 + c / w, e = ent[b];
+      if (!(e & kLeafBit)) {
+        walk_from(tr.nodes, stack, e, T, ci, cj, q, visit);
         continue;
       }
-      const uint32_t leaf = ref & ~kLeafBit;
-      const uint32_t st = tr.lstart[leaf], l = tr.llevel[leaf];
-      const uint32_t li = compact16(st), lj = compact16(st >> 1);
-      const uint32_t li0 = li >> sh, lj0 = lj >> sh;
+      const uint32_t l = ((e >> kLeafIdxBits) & 15u) + 1u, m = T - l;
+      const uint32_t li0 = (ci >> m) << m, lj0 = (cj >> m) << m;
       if (ci != (ti0 > li0 ? ti0 : li0) || cj != (tj0 > lj0 ? tj0 : lj0)) continue;
-      const uint32_t size = 1u << (kFine - l);
-      const uint32_t ihi = li + (size - 1u), jhi = lj + (size - 1u);
-      visit(leaf, q.i0 < li && ihi < q.i1 && q.j0 < lj && jhi < q.j1);
+      const uint32_t ilo = li0 << sh, jlo = lj0 << sh, span = (1u << (kFine - l)) - 1u;
+      visit(e & kLeafIdxMask,
+            q.i0 < ilo && ilo + span < q.i1 && q.j0 < jlo && jlo + span < q.j1);
     }
   }
 }
@@ -1026,7 +1055,7 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
            (const uint4 *)B.front[(l - 1) & 1], B.front[l & 1], B.FCAP, B.lstart, B.llevel,
            B.LCAP);
   }
-  LAUNCH(k_tree_done, 1, 1, s, B.ctl, B.LCAP);
+  LAUNCH(k_tree_done, 1, 1, s, B.ctl, B.LCAP, B.tcap);
   radix_sort_pairs(B.lstart, B.llevel, B.lstart2, B.llevel2, &B.ctl->n_leaves, &B.ctl->rebuild,
                    B.hist, B.tot, 0, 32, s);
   LAUNCH(k_nodes_open, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
@@ -1036,8 +1065,9 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
   mscan(jobs, 1, B.part, &B.ctl->rebuild, nullptr, s);
   LAUNCH(k_nodes_build, grid_for(B.LCAP), kBlock, s, B.ctl, (const uint32_t *)B.lstart,
          (const uint32_t *)B.llevel, (const uint32_t *)B.node_off, B.nodes, B.NCAP);
-  LAUNCH(k_table_build, kTableCells / kBlock, kBlock, s, (const Ctl *)B.ctl,
-         (const uint4 *)B.nodes, B.table);
+  LAUNCH(k_table_build, grid_for(1ull << (2 * B.tcap), 4096), kBlock, s, (const Ctl *)B.ctl,
+         (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, (const uint32_t *)B.node_off,
+         B.table);
 }
 
 void launch_leaves(const Bufs &B, hipStream_t s) {
