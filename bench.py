@@ -190,6 +190,9 @@ def main():
     ab = algorithmic_bytes(per_tick, st["n_present"], nq)
     dom = max(("join_count", "join_write"), key=lambda k: avg[k])
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
+    from paper_1411_3212_amd.profiling import load_traffic
+    tr = load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_1m_k_{dom}_traffic.txt")
+                      if args.workload == "hotspot" else os.devnull)
     out = {
         "metric": "result pairs/s",
         "value": pairs / wall,
@@ -216,7 +219,8 @@ def main():
         "counters_per_tick": per_tick,
         "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": ab[dom],
+                     "traffic": tr["bytes"] if tr else None,
+                     "algorithmic_bytes_per_launch": ab[dom],
                      "avg_launch_ms": avg[dom]},
         "input_generation_s": t_gen,
     }
