@@ -66,22 +66,37 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--mode", default="eager", choices=["graph", "eager"],
+                    help="graph: each tick's inputs are copied into fixed buffers and the tick "
+                         "replays as one captured graph; eager: one launch per kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
 
 
+FIELDS = ("ids", "x", "y", "qid", "xa", "ya", "xb", "yb")
+
+
+def views(buf, m, nq, torch):
+    """Named views of a packed tick buffer [ids x y | qid xa ya xb yb]."""
+    sizes = (m, m, m, nq, nq, nq, nq, nq)
+    out, o = {}, 0
+    for name, n in zip(FIELDS, sizes):
+        v = buf[o:o + n]
+        out[name] = v if name in ("ids", "qid") else v.view(torch.float32)
+        o += n
+    return out
+
+
 def upload_ticks(wl, torch):
-    """All ticks of the workload as device tensors (ids as int32 bit patterns)."""
+    """Every tick of the workload packed in one device buffer (4-byte words;
+    ids as int32 bit patterns)."""
     ticks = []
     for t in wl.ticks():
-        d = dict(
-            ids=torch.from_numpy(t.ids.view(np.int32)).cuda(),
-            x=torch.from_numpy(t.x).cuda(), y=torch.from_numpy(t.y).cuda(),
-            qid=torch.from_numpy(t.qid.view(np.int32)).cuda(),
-            xa=torch.from_numpy(t.xa).cuda(), ya=torch.from_numpy(t.ya).cuda(),
-            xb=torch.from_numpy(t.xb).cuda(), yb=torch.from_numpy(t.yb).cuda())
-        ticks.append((d, t))
+        host = np.concatenate([t.ids.view(np.int32), t.x.view(np.int32), t.y.view(np.int32),
+                               t.qid.view(np.int32), t.xa.view(np.int32), t.ya.view(np.int32),
+                               t.xb.view(np.int32), t.yb.view(np.int32)])
+        ticks.append((torch.from_numpy(host).cuda(), len(t.ids), t.nq))
     torch.cuda.synchronize()
     return ticks
 
@@ -136,12 +151,14 @@ def main():
     import torch
     from paper_1411_3212_amd.binding import PHASES, Scene
 
-    n_ticks = args.warmup + args.steps
+    n_extra = 5  # eager ticks after the timed region, for the per-phase breakdown
+    n_ticks = args.warmup + args.steps + n_extra
     wl = workloads.make(args.workload, n_ticks=n_ticks)
     t_gen = time.perf_counter()
     ticks = upload_ticks(wl, torch)
     t_gen = time.perf_counter() - t_gen
-    nq = max(t.nq for _, t in ticks)
+    nq = max(q for _, _, q in ticks)
+    slot = torch.empty(max(b.numel() for b, _, _ in ticks), dtype=torch.int32, device="cuda")
     cfg = scene_config(wl, args.th)
     scene = Scene(wl.n, nq, profile=True, **cfg)
     counters = torch.zeros((n_ticks, 8), dtype=torch.int64, device="cuda")
@@ -150,32 +167,42 @@ def main():
     start_ev = torch.cuda.Event(enable_timing=True)
     end_ev = torch.cuda.Event(enable_timing=True)
 
-    def one_tick(i, timed):
-        d, _ = ticks[i]
+    def one_tick(i, timed, mode=args.mode, phases=phase_sum):
+        buf, m, q = ticks[i]
         h0 = time.perf_counter()
-        scene.apply_updates(d["ids"], d["x"], d["y"])
-        scene.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
+        if mode == "graph":
+            slot[:buf.numel()].copy_(buf)
+            d = views(slot, m, q, torch)
+            scene.tick_graph(*(d[f] for f in FIELDS))
+        else:
+            d = views(buf, m, q, torch)
+            scene.apply_updates(d["ids"], d["x"], d["y"])
+            scene.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
         scene.counters_into(counters[i])
         scene.fetch()  # synchronises: the tick's results are available
         h1 = time.perf_counter()
         if timed:
             lat.append((h1 - h0) * 1e3)
+        if phases is not None:
             ph = scene.phase_times()
             for k in PHASES:
-                phase_sum[k] += ph[k]
+                phases[k] += ph[k]
 
     for i in range(args.warmup):
-        one_tick(i, False)
+        one_tick(i, False, phases=None)
     torch.cuda.synchronize()
     start_ev.record()
     t0 = time.perf_counter()
-    for i in range(args.warmup, n_ticks):
+    for i in range(args.warmup, args.warmup + args.steps):
         one_tick(i, True)
     end_ev.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dev_ms = start_ev.elapsed_time(end_ev)
-    c = counters.cpu().numpy()[args.warmup:]
+    eager_phase = {k: 0.0 for k in PHASES}
+    for i in range(args.warmup + args.steps, n_ticks):
+        one_tick(i, False, mode="eager", phases=eager_phase)
+    c = counters.cpu().numpy()[args.warmup:args.warmup + args.steps]
     assert (c[:, 7] == 0).all(), f"device error bits {np.unique(c[:, 7])}"
     pairs = int(c[:, 0].sum())
     K = args.steps
@@ -208,7 +235,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "objects": wl.n, "queries_per_tick": nq, "ticks": K, "th_quad": args.th,
-                   "covering": True, "reorder": True, "rebuild": "auto/32"},
+                   "covering": True, "reorder": True, "rebuild": "auto/32",
+                   "launch": args.mode},
         "ticks_per_s": K / wall,
         "p50_tick_ms": float(np.percentile(lat, 50)),
         "p99_tick_ms": float(np.percentile(lat, 99)),
@@ -216,6 +244,7 @@ def main():
         "pairs_per_tick": pairs / K,
         "queries_per_s": nq * K / wall,
         "phase_ms": {k: round(v, 4) for k, v in avg.items()},
+        "phase_ms_eager_sample": {k: round(v / n_extra, 4) for k, v in eager_phase.items()},
         "counters_per_tick": per_tick,
         "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -206,6 +206,18 @@ int sj_run_tick(sj_scene *scene, const uint32_t *d_qid, const float *d_xa,
                 const float *d_ya, const float *d_xb, const float *d_yb,
                 uint32_t nq);
 
+/* One tick as a single HIP graph launch: the same work and results as
+ * sj_apply_updates(d_id, d_x, d_y, m) followed by sj_run_tick(...), on the
+ * scene's stream.  The graph is captured on first use for each quadtree
+ * decision (keep, build, decided on the device) and replayed afterwards;
+ * it is captured again whenever a pointer or a size differs from the
+ * captured ones, so callers that keep their inputs in fixed buffers replay
+ * without capture.  The graph holds kernels only.  If updates were already
+ * enqueued for this tick by sj_apply_updates, the tick runs eagerly. */
+int sj_tick_graph(sj_scene *scene, const uint32_t *d_id, const float *d_x, const float *d_y,
+                  uint32_t m, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
+                  const float *d_xb, const float *d_yb, uint32_t nq);
+
 /* Synchronises the stream and returns views of the compressed results of
  * the last tick, or the latched error of the tick. */
 int sj_fetch_results(sj_scene *scene, sj_results *out);
@@ -236,7 +248,9 @@ int sj_tick_counters(sj_scene *scene, uint64_t *d_out);
 int sj_stats(sj_scene *scene, sj_tick_stats *out);
 
 /* Device times of the phases of the last tick (SJ_PROFILE), n <=
- * SJ_PH_COUNT floats.  Synchronises. */
+ * SJ_PH_COUNT floats.  Synchronises.  After a graph tick (sj_tick_graph)
+ * only SJ_PH_JOIN_WRITE is timed (the pass runs as a graph of its own
+ * between two events); the other entries are 0. */
 int sj_phase_times(sj_scene *scene, float *ms, int n);
 
 /* Internal arrays for tests and tools (device views, valid until the next
@@ -256,6 +270,79 @@ typedef struct sj_index_view {
 } sj_index_view;
 
 int sj_index_view_get(sj_scene *scene, sj_index_view *out);
+
+/* ------------------------------------------------------------------------
+ * Tick serving: many scenes on one device with continuous batching (the
+ * batching of ticks and the latency definitions of Section "Problem
+ * setting and statement": latency = queueing + processing).
+ *
+ * The server carves every admitted scene's workspace, input slots and
+ * output slots from one caller-owned device pool with its own first-fit
+ * allocator: admission succeeds while the scene fits (an HBM budget), and
+ * retiring a scene returns its memory.  Every scene has its own stream.
+ * Tick requests queue per scene in submission order; sj_server_poll
+ * retires finished ticks and starts queued ones, up to max_running at
+ * once, so ticks of different scenes overlap on the device.  A tick copies
+ * its inputs into the scene's slots, replays the scene's captured graph
+ * (sj_tick_graph), then writes per-query counts and pair-set hashes
+ * (sj_result_hashes) and the tick counters (sj_tick_counters) into the
+ * scene's output slots.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct sj_server sj_server;
+
+typedef struct sj_served {
+  uint64_t tag;                 /* the submission's tag */
+  uint32_t scene_id;
+  int32_t status;               /* SJ_OK or the tick's error */
+  uint32_t nq;
+  const uint64_t *d_count;      /* [nq] result sizes        (valid until the */
+  const uint64_t *d_hash;       /* [nq] pair-set hashes      scene's next tick */
+  const uint64_t *d_counters;   /* [8] as sj_tick_counters   after this one is */
+} sj_served;                    /*                           retired by a poll) */
+
+typedef struct sj_server_stats {
+  uint64_t pool_bytes, pool_used;
+  uint32_t scenes, running, queued;
+} sj_server_stats;
+
+/* Device bytes a scene takes from the pool (workspace + slots). */
+size_t sj_server_scene_bytes(const sj_config *cfg, uint32_t max_updates);
+
+/* d_pool: caller-owned device memory, 256-byte aligned, pool_bytes long.
+ * max_running: ticks in flight at once (0: 4). */
+int sj_server_create(void *d_pool, size_t pool_bytes, uint32_t max_running, sj_server **out);
+int sj_server_destroy(sj_server *server);
+
+/* Admits a scene if sj_server_scene_bytes(cfg, max_updates) fit in the pool
+ * now; SJ_ENOSPACE otherwise (nothing is reserved; try again later). */
+int sj_server_admit(sj_server *server, const sj_config *cfg, uint32_t max_updates,
+                    uint32_t *scene_id);
+
+/* Releases an idle scene (no tick queued or running) and its memory. */
+int sj_server_retire(sj_server *server, uint32_t scene_id);
+
+/* Queues a tick for a scene: device inputs as sj_apply_updates + sj_run_tick
+ * (they must stay valid until the tick is retired); tags must be unique per
+ * scene.  d_record (device, 10 u64, may be NULL) receives the tick's record
+ * when it finishes: the 8 counters of sj_tick_counters, then the sum of the
+ * per-query pair-set hashes and the sum of the result sizes (mod 2^64).
+ * Non-blocking. */
+int sj_server_submit(sj_server *server, uint32_t scene_id, const uint32_t *d_id,
+                     const float *d_x, const float *d_y, uint32_t m, const uint32_t *d_qid,
+                     const float *d_xa, const float *d_ya, const float *d_xb,
+                     const float *d_yb, uint32_t nq, uint64_t tag, uint64_t *d_record);
+
+/* Retires finished ticks (at most cap, written to done[0 .. *n_done)) and
+ * starts queued ticks in submission order.  Non-blocking. */
+int sj_server_poll(sj_server *server, sj_served *done, uint32_t cap, uint32_t *n_done);
+
+int sj_server_info(const sj_server *server, sj_server_stats *out);
+
+/* The scene object of an admitted scene (results of its last retired tick
+ * stay readable until its next tick starts). */
+int sj_server_scene(sj_server *server, uint32_t scene_id, sj_scene **out);
+
+const char *sj_server_last_error(const sj_server *server);
 
 /* Message for the last error of the scene (or of creation when NULL). */
 const char *sj_last_error(const sj_scene *scene);

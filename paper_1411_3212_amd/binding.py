@@ -62,6 +62,16 @@ class SjIndexView(Structure):
                 ("d_py", c_void_p)]
 
 
+class SjServed(Structure):
+    _fields_ = [("tag", c_uint64), ("scene_id", c_uint32), ("status", c_int32), ("nq", c_uint32),
+                ("d_count", c_void_p), ("d_hash", c_void_p), ("d_counters", c_void_p)]
+
+
+class SjServerStats(Structure):
+    _fields_ = [("pool_bytes", c_uint64), ("pool_used", c_uint64), ("scenes", c_uint32),
+                ("running", c_uint32), ("queued", c_uint32)]
+
+
 EXPORTS = {
     "sj_workspace_bytes": (c_size_t, [POINTER(SjConfig)]),
     "sj_scene_create": (c_int, [POINTER(SjConfig), c_void_p, c_size_t, c_void_p,
@@ -71,6 +81,8 @@ EXPORTS = {
     "sj_build_index": (c_int, [c_void_p, c_uint32]),
     "sj_run_tick": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_uint32]),
+    "sj_tick_graph": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_void_p, c_uint32]),
     "sj_fetch_results": (c_int, [c_void_p, POINTER(SjResults)]),
     "sj_expand_results": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(c_uint64)]),
     "sj_result_hashes": (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -79,6 +91,18 @@ EXPORTS = {
     "sj_phase_times": (c_int, [c_void_p, POINTER(c_float), c_int]),
     "sj_index_view_get": (c_int, [c_void_p, POINTER(SjIndexView)]),
     "sj_last_error": (c_char_p, [c_void_p]),
+    "sj_server_scene_bytes": (c_size_t, [POINTER(SjConfig), c_uint32]),
+    "sj_server_create": (c_int, [c_void_p, c_size_t, c_uint32, POINTER(c_void_p)]),
+    "sj_server_destroy": (c_int, [c_void_p]),
+    "sj_server_admit": (c_int, [c_void_p, POINTER(SjConfig), c_uint32, POINTER(c_uint32)]),
+    "sj_server_retire": (c_int, [c_void_p, c_uint32]),
+    "sj_server_submit": (c_int, [c_void_p, c_uint32, c_void_p, c_void_p, c_void_p, c_uint32,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
+                                 c_uint64, c_void_p]),
+    "sj_server_poll": (c_int, [c_void_p, POINTER(SjServed), c_uint32, POINTER(c_uint32)]),
+    "sj_server_info": (c_int, [c_void_p, POINTER(SjServerStats)]),
+    "sj_server_scene": (c_int, [c_void_p, c_uint32, POINTER(c_void_p)]),
+    "sj_server_last_error": (c_char_p, [c_void_p]),
 }
 
 _lib = None
@@ -105,6 +129,18 @@ def _check(rc: int, handle=None):
     if rc != SJ_OK:
         msg = load().sj_last_error(handle)
         raise SjError(rc, msg.decode() if msg else "")
+
+
+def make_config(capacity_objects: int, capacity_queries: int, *, th: int = 64, th_min: int = 0,
+                l_max: int = 16, covering: bool = True, reorder: bool = True,
+                rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
+                capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
+                profile: bool = False) -> SjConfig:
+    flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
+            (SJ_PROFILE if profile else 0)
+    return SjConfig(capacity_objects, capacity_queries, capacity_subqueries, capacity_covering,
+                    capacity_results, th, th_min, l_max, flags, REBUILD[rebuild], rebuild_period,
+                    split_slots)
 
 
 def _ptr(t):
@@ -162,11 +198,13 @@ class Scene:
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
-        flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
-                (SJ_PROFILE if profile else 0)
-        self.cfg = SjConfig(capacity_objects, capacity_queries, capacity_subqueries,
-                            capacity_covering, capacity_results, th, th_min, l_max, flags,
-                            REBUILD[rebuild], rebuild_period, split_slots)
+        self.cfg = make_config(capacity_objects, capacity_queries, th=th, th_min=th_min,
+                               l_max=l_max, covering=covering, reorder=reorder, rebuild=rebuild,
+                               rebuild_period=rebuild_period,
+                               capacity_subqueries=capacity_subqueries,
+                               capacity_covering=capacity_covering,
+                               capacity_results=capacity_results, split_slots=split_slots,
+                               profile=profile)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")
@@ -232,6 +270,19 @@ class Scene:
                                      _ptr(yb), nq), self.handle)
         self._keep = [qid, xa, ya, xb, yb]
 
+    def tick_graph(self, ids, x, y, qid, xa, ya, xb, yb):
+        """Updates + tick as one graph launch (captured once per quadtree
+        decision for these buffers, replayed afterwards)."""
+        import torch
+        m, nq = ids.numel(), qid.numel()
+        for t in (ids, qid):
+            assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
+        for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
+            self._dev(t, torch.float32, n)
+        _check(self._lib.sj_tick_graph(self.handle, _ptr(ids), _ptr(x), _ptr(y), m, _ptr(qid),
+                                       _ptr(xa), _ptr(ya), _ptr(xb), _ptr(yb), nq), self.handle)
+        self._keep = [ids, x, y, qid, xa, ya, xb, yb]
+
     def fetch(self) -> Results:
         r = SjResults()
         _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
@@ -296,3 +347,74 @@ class Scene:
                     leaf_beg=self._view(v.d_leaf_beg, L + 1, torch.int32),
                     px=self._view(v.d_px, self.cfg.capacity_objects, torch.float32),
                     py=self._view(v.d_py, self.cfg.capacity_objects, torch.float32))
+
+
+class Server:
+    """Tick-serving runtime (sj_server_*): scenes admitted by the memory of
+    one device pool, ticks of different scenes overlapping on the device."""
+
+    def __init__(self, pool_bytes: int, max_running: int = 4, device=None):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        h = c_void_p()
+        rc = self._lib.sj_server_create(_ptr(self.pool), self.pool.numel(), max_running, byref(h))
+        if rc != SJ_OK:
+            raise SjError(rc, self._lib.sj_server_last_error(None).decode())
+        self.handle = h
+        self._keep = {}
+        self._done = (SjServed * 256)()
+
+    def _check(self, rc):
+        if rc != SJ_OK:
+            raise SjError(rc, self._lib.sj_server_last_error(self.handle).decode())
+
+    def scene_bytes(self, cfg: SjConfig, max_updates: int) -> int:
+        return int(self._lib.sj_server_scene_bytes(byref(cfg), max_updates))
+
+    def admit(self, cfg: SjConfig, max_updates: int):
+        """Scene id, or None if the scene does not fit in the pool now."""
+        sid = c_uint32()
+        rc = self._lib.sj_server_admit(self.handle, byref(cfg), max_updates, byref(sid))
+        if rc == SJ_ENOSPACE:
+            return None
+        self._check(rc)
+        return int(sid.value)
+
+    def retire(self, sid: int):
+        self._check(self._lib.sj_server_retire(self.handle, sid))
+        self._keep.pop(sid, None)
+
+    def submit(self, sid: int, tag: int, ids, x, y, qid, xa, ya, xb, yb, record=None):
+        """record: optional int64 CUDA tensor view of 10 elements receiving
+        the tick's counters and result digest."""
+        m, nq = ids.numel(), qid.numel()
+        self._check(self._lib.sj_server_submit(self.handle, sid, _ptr(ids), _ptr(x), _ptr(y), m,
+                                               _ptr(qid), _ptr(xa), _ptr(ya), _ptr(xb),
+                                               _ptr(yb), nq, tag, _ptr(record)))
+
+    def poll(self):
+        """Finished ticks: list of (scene, tag, status, nq, count_ptr,
+        hash_ptr, counters_ptr); outputs stay valid until the scene's next
+        tick is retired."""
+        n = c_uint32()
+        self._check(self._lib.sj_server_poll(self.handle, self._done, len(self._done), byref(n)))
+        return [(d.scene_id, d.tag, d.status, d.nq, d.d_count, d.d_hash, d.d_counters)
+                for d in self._done[:n.value]]
+
+    def info(self) -> dict:
+        st = SjServerStats()
+        self._check(self._lib.sj_server_info(self.handle, byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in SjServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.sj_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,9 +10,18 @@
 #include "sj.h"
 #include "sj_device.h"
 #include "sj_kernels.h"
+#include "sj_scene.h"
 
 using sj::Bufs;
 using sj::Ctl;
+
+struct GraphSlot {
+  hipGraphExec_t exec;   // the whole tick, or its part before the join write pass
+  hipGraphExec_t exec2;  // the join write pass (profiled scenes only)
+  bool valid;
+  uint32_t m, nq;
+  const void *ptrs[8];
+};
 
 struct sj_scene {
   sj_config cfg;
@@ -27,6 +36,10 @@ struct sj_scene {
   bool ticked;
   bool prof;
   bool known;          // host_ctl reflects the device state after the last tick
+  bool events_valid;   // phase events were recorded for the last tick
+  bool join_events;    // only the join write pass was timed (graph tick)
+  GraphSlot graphs[3]; // captured ticks per rebuild decision (keep, build, device)
+  hipStream_t cap_stream;  // private stream graphs are captured on
   bool force_pending;  // sj_build_index since the last tick
   uint64_t upd_pending;  // updates enqueued since the last tick
   bool upd_open;  // an update event interval is open since the last tick
@@ -227,8 +240,73 @@ int sync_ctl(sj_scene *s) {
   return SJ_OK;
 }
 
-void record(sj_scene *s, int i) {
-  if (s->prof) (void)hipEventRecord(s->ev[i], s->stream);
+int check_tick_args(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
+                    const float *d_xb, const float *d_yb, uint32_t nq) {
+  if (nq > s->B.Q) return fail(s, SJ_EINVAL, "run_tick: nq above capacity_queries");
+  if (nq && (!d_qid || !d_xa || !d_ya || !d_xb || !d_yb || ((uintptr_t)d_qid & 3u) ||
+             ((uintptr_t)d_xa & 3u) || ((uintptr_t)d_ya & 3u) || ((uintptr_t)d_xb & 3u) ||
+             ((uintptr_t)d_yb & 3u)))
+    return fail(s, SJ_EINVAL, "run_tick: null or misaligned pointer");
+  return SJ_OK;
+}
+
+// Rebuild decision: when the host has seen the device state after the last
+// tick it decides (and launches the build kernels only if needed);
+// otherwise the device decides and the build kernels are launched gated.
+uint32_t host_decision(const sj_scene *s) {
+  if (!s->known) return 2u;
+  const Ctl &c = s->host_ctl;
+  const uint32_t policy = s->cfg.rebuild_policy;
+  const bool r = s->force_pending || !c.built || policy == SJ_REBUILD_ALWAYS ||
+                 (policy == SJ_REBUILD_AUTO && c.want_rebuild);
+  return r ? 1u : 0u;
+}
+
+// part: 0 the whole tick; 1 up to the result-offset scan; 2 the join write.
+void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
+                  const float *d_xb, const float *d_yb, uint32_t nq, uint32_t decision,
+                  uint64_t upd_total, bool events, int part = 0) {
+  const hipStream_t st = s->stream;
+  const uint32_t flags = s->cfg.flags;
+  const uint32_t policy = s->cfg.rebuild_policy;
+  auto rec = [&](int i) {
+    if (events) (void)hipEventRecord(s->ev[i], st);
+  };
+  if (part == 2) {
+    const uint32_t *tasks = (flags & SJ_REORDER) ? s->B.tasks2 : s->B.tasks;
+    sj::launch_join_write(s->B, tasks, nq, st);
+    return;
+  }
+  rec(0);
+  sj::launch_index(s->B, decision, policy, upd_total, d_qid, nq, st);
+  rec(1);
+  if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
+  rec(2);
+  sj::launch_leaves(s->B, st);
+  rec(3);
+  sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  rec(4);
+  const uint32_t *tasks = sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, st);
+  rec(5);
+  sj::launch_join_count(s->B, tasks, st);
+  rec(6);
+  sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
+  rec(7);
+  if (part == 1) return;
+  sj::launch_join_write(s->B, tasks, nq, st);
+  rec(8);
+  rec(9);
+  s->events_valid = events;
+  s->join_events = false;
+}
+
+void after_tick(sj_scene *s, const uint32_t *d_qid, uint32_t nq) {
+  s->upd_pending = 0;
+  s->force_pending = false;
+  s->known = false;
+  s->last_nq = nq;
+  s->last_qid = d_qid;
+  s->ticked = true;
 }
 
 }  // namespace
@@ -300,6 +378,12 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
 
 int sj_scene_destroy(sj_scene *s) {
   if (!s) return SJ_EINVAL;
+  for (auto &g : s->graphs) {
+    if (!g.valid) continue;
+    (void)hipGraphExecDestroy(g.exec);
+    if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+  }
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->prof) {
     for (auto &e : s->ev) (void)hipEventDestroy(e);
     (void)hipEventDestroy(s->ev_u0);
@@ -340,50 +424,89 @@ int sj_build_index(sj_scene *s, uint32_t th) {
 int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
                 const float *d_xb, const float *d_yb, uint32_t nq) {
   if (!s) return SJ_EINVAL;
-  if (nq > s->B.Q) return fail(s, SJ_EINVAL, "run_tick: nq above capacity_queries");
-  if (nq && (!d_qid || !d_xa || !d_ya || !d_xb || !d_yb || ((uintptr_t)d_qid & 3u) ||
-             ((uintptr_t)d_xa & 3u) || ((uintptr_t)d_ya & 3u) || ((uintptr_t)d_xb & 3u) ||
-             ((uintptr_t)d_yb & 3u)))
-    return fail(s, SJ_EINVAL, "run_tick: null or misaligned pointer");
-  const hipStream_t st = s->stream;
-  const uint32_t flags = s->cfg.flags;
-  const uint32_t policy = s->cfg.rebuild_policy;
-  // Rebuild decision: when the host has seen the device state after the
-  // last tick it decides (and launches the build kernels only if needed);
-  // otherwise the device decides and the build kernels are launched gated.
-  uint32_t decision = 2u;
-  if (s->known) {
-    const Ctl &c = s->host_ctl;
-    const bool r = s->force_pending || !c.built || policy == SJ_REBUILD_ALWAYS ||
-                   (policy == SJ_REBUILD_AUTO && c.want_rebuild);
-    decision = r ? 1u : 0u;
-  }
-  record(s, 0);
-  sj::launch_index(s->B, decision, policy, s->upd_pending, d_qid, nq, st);
-  record(s, 1);
-  if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
-  record(s, 2);
-  sj::launch_leaves(s->B, st);
-  record(s, 3);
-  sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
-  record(s, 4);
-  const uint32_t *tasks = sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, st);
-  record(s, 5);
-  sj::launch_join_count(s->B, tasks, st);
-  record(s, 6);
-  sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
-  record(s, 7);
-  sj::launch_join_write(s->B, tasks, nq, st);
-  record(s, 8);
-  record(s, 9);
-  s->upd_pending = 0;
-  s->force_pending = false;
-  s->known = false;
-  s->last_nq = nq;
-  s->last_qid = d_qid;
-  s->ticked = true;
+  int rc = check_tick_args(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq);
+  if (rc != SJ_OK) return rc;
+  enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, host_decision(s), s->upd_pending, s->prof);
+  after_tick(s, d_qid, nq);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "run_tick launch");
+}
+
+int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const float *d_y,
+                  uint32_t m, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
+                  const float *d_xb, const float *d_yb, uint32_t nq) {
+  if (!s) return SJ_EINVAL;
+  if (m && (!d_id || !d_x || !d_y || ((uintptr_t)d_id & 3u) || ((uintptr_t)d_x & 3u) ||
+            ((uintptr_t)d_y & 3u)))
+    return fail(s, SJ_EINVAL, "tick_graph: null or misaligned update pointer");
+  int rc = check_tick_args(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq);
+  if (rc != SJ_OK) return rc;
+  if (s->upd_pending) {
+    // updates already enqueued for this tick: their sequence numbers are
+    // not those a graph would replay, so run this tick eagerly
+    rc = sj_apply_updates(s, d_id, d_x, d_y, m);
+    return rc != SJ_OK ? rc : sj_run_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq);
+  }
+  const uint32_t decision = host_decision(s);
+  GraphSlot &g = s->graphs[decision];
+  const void *ptrs[8] = {d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
+  bool same = g.valid && g.m == m && g.nq == nq;
+  for (int i = 0; same && i < 8; ++i) same = g.ptrs[i] == ptrs[i];
+  if (!same) {
+    if (g.valid) {
+      (void)hipGraphExecDestroy(g.exec);
+      if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+      g.valid = false;
+    }
+    // capture on a private stream (the caller's may be the null stream,
+    // which cannot be captured); the graph is launched on the scene's stream.
+    // Profiled scenes capture the join write pass as a graph of its own and
+    // time it with events recorded between the two launches.
+    if (!s->cap_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(s, e, "hipStreamCreate");
+    }
+    const hipStream_t user = s->stream;
+    auto capture = [&](int part, hipGraphExec_t *out) -> int {
+      hipGraph_t graph;
+      hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
+      s->stream = s->cap_stream;
+      if (part != 2 && m) sj::launch_updates(s->B, d_id, d_x, d_y, m, 0, s->stream);
+      enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, m, false, part);
+      s->stream = user;
+      e = hipStreamEndCapture(s->cap_stream, &graph);
+      if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipGraphInstantiate");
+    };
+    rc = capture(s->prof ? 1 : 0, &g.exec);
+    if (rc != SJ_OK) return rc;
+    if (s->prof) {
+      rc = capture(2, &g.exec2);
+      if (rc != SJ_OK) {
+        (void)hipGraphExecDestroy(g.exec);
+        return rc;
+      }
+    }
+    g.valid = true;
+    g.m = m;
+    g.nq = nq;
+    for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
+  }
+  hipError_t e = hipGraphLaunch(g.exec, s->stream);
+  if (e == hipSuccess && s->prof) {
+    e = hipEventRecord(s->ev[7], s->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(g.exec2, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(s->ev[8], s->stream);
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "hipGraphLaunch");
+  after_tick(s, d_qid, nq);
+  s->events_valid = false;
+  s->join_events = s->prof;
+  s->upd_open = false;
+  return SJ_OK;
 }
 
 int sj_tick_counters(sj_scene *s, uint64_t *d_out) {
@@ -471,25 +594,39 @@ int sj_expand_results(sj_scene *s, uint64_t *d_off, uint32_t *d_ids, uint64_t id
 int sj_phase_times(sj_scene *s, float *ms, int n) {
   if (!s || !ms || n < 0) return SJ_EINVAL;
   if (!s->prof) return fail(s, SJ_ESTATE, "scene created without SJ_PROFILE");
+  if (!s->events_valid && !s->join_events) return fail(s, SJ_ESTATE, "no tick timed yet");
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "phase_times sync");
   float t[SJ_PH_COUNT] = {0};
-  if (s->upd_open) (void)hipEventElapsedTime(&t[SJ_PH_UPDATES], s->ev_u0, s->ev_u1);
-  // events 0..9 bracket: index, build, leaves, split, schedule, join count,
-  // join scan, join write, finish (counted with the join scan)
-  float d[9];
-  for (int i = 0; i < 9; ++i) (void)hipEventElapsedTime(&d[i], s->ev[i], s->ev[i + 1]);
-  t[SJ_PH_INDEX] = d[0];
-  t[SJ_PH_BUILD] = d[1];
-  t[SJ_PH_LEAVES] = d[2];
-  t[SJ_PH_SPLIT] = d[3];
-  t[SJ_PH_SCHEDULE] = d[4];
-  t[SJ_PH_JOIN_COUNT] = d[5];
-  t[SJ_PH_JOIN_SCAN] = d[6] + d[8];
-  t[SJ_PH_JOIN_WRITE] = d[7];
+  auto elapsed = [&](float *out, hipEvent_t a, hipEvent_t b) {
+    hipError_t r = hipEventElapsedTime(out, a, b);
+    if (r != hipSuccess) {
+      (void)hipGetLastError();  // do not leave a sticky error for other callers
+      if (e == hipSuccess) e = r;
+      *out = 0.0f;
+    }
+  };
+  if (s->join_events) {
+    // graph tick: only the join write pass is bracketed by events
+    elapsed(&t[SJ_PH_JOIN_WRITE], s->ev[7], s->ev[8]);
+  } else {
+    if (s->upd_open) elapsed(&t[SJ_PH_UPDATES], s->ev_u0, s->ev_u1);
+    // events 0..9 bracket: index, build, leaves, split, schedule, join count,
+    // join scan, join write, finish (counted with the join scan)
+    float d[9];
+    for (int i = 0; i < 9; ++i) elapsed(&d[i], s->ev[i], s->ev[i + 1]);
+    t[SJ_PH_INDEX] = d[0];
+    t[SJ_PH_BUILD] = d[1];
+    t[SJ_PH_LEAVES] = d[2];
+    t[SJ_PH_SPLIT] = d[3];
+    t[SJ_PH_SCHEDULE] = d[4];
+    t[SJ_PH_JOIN_COUNT] = d[5];
+    t[SJ_PH_JOIN_SCAN] = d[6] + d[8];
+    t[SJ_PH_JOIN_WRITE] = d[7];
+  }
   for (int i = 0; i < n && i < SJ_PH_COUNT; ++i) ms[i] = t[i];
   s->upd_open = false;
-  return SJ_OK;
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipEventElapsedTime");
 }
 
 int sj_index_view_get(sj_scene *s, sj_index_view *out) {
@@ -517,3 +654,15 @@ int sj_index_view_get(sj_scene *s, sj_index_view *out) {
 const char *sj_last_error(const sj_scene *s) { return s ? s->err : g_create_err; }
 
 }  // extern "C"
+
+int sj_scene_ctl_to_host_async(sj_scene *s, Ctl *h_ctl) {
+  hipError_t e = hipMemcpyAsync(h_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream);
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "control block copy");
+}
+
+void sj_scene_ctl_from_host(sj_scene *s, const Ctl *h_ctl) {
+  memcpy(&s->host_ctl, h_ctl, sizeof(Ctl));
+  s->known = true;
+}
+
+int sj_scene_status(sj_scene *s) { return status_of(s, s->host_ctl.err); }

@@ -343,3 +343,35 @@ def test_hotspot_full_size_ticks():
             sub = T(qid=t.qid[sample], rects=tuple(r[sample] for r in t.rects))
             want = oracle_lists(st, sub)
             assert [lists[i] for i in sample] == want
+
+
+def test_graph_ticks_equal_eager_ticks():
+    """Updates + tick replayed as a captured graph give the same bytes as the
+    eager calls, through quadtree builds, reuse, and buffer changes."""
+    import torch
+    wl = workloads.make("hotspot", n=40_000, n_ticks=6)
+    eager = Scene(wl.n, wl.n, th=32, rebuild_period=3)
+    graph = Scene(wl.n, wl.n, th=32, rebuild_period=3)
+    slots = None
+    st = oracle.State(wl.n)
+    for k, t in enumerate(wl.ticks()):
+        say(f"graph tick {k}")
+        oracle_apply(st, t)
+        gpu_tick(eager, t)
+        d = [dev_u32(t.ids), dev_f32(t.x), dev_f32(t.y), dev_u32(t.qid)] + \
+            [dev_f32(r) for r in t.rects]
+        if slots is None or k == 4:  # new buffers on tick 4: captured again
+            slots = [torch.empty_like(a) for a in d]
+        for a, b in zip(slots, d):
+            a.copy_(b)
+        graph.tick_graph(*slots)
+        if k % 2 == 1:  # ticks the host has not fetched: device decides
+            continue
+        re, rg = eager.fetch(), graph.fetch()
+        for a, b in zip((re.isect_off, re.isect_id, re.cov_off, re.cov_leaf, re.leaf_beg),
+                        (rg.isect_off, rg.isect_id, rg.cov_off, rg.cov_leaf, rg.leaf_beg)):
+            assert torch.equal(a, b)
+        cnt, h = gpu_count_hash(graph)
+        oc, oh = oracle_count_hash(st, t, grid=False)
+        assert np.array_equal(cnt, oc) and np.array_equal(h, oh), f"tick {k}"
+        assert eager.stats()["rebuilt"] == graph.stats()["rebuilt"]
