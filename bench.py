@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
-    ap.add_argument("--mode", default="eager", choices=["graph", "eager"],
+    ap.add_argument("--mode", default="graph", choices=["graph", "eager"],
                     help="graph: each tick's inputs are copied into fixed buffers and the tick "
                          "replays as one captured graph; eager: one launch per kernel")
     ap.add_argument("--copy-probe", action="store_true",
