@@ -70,7 +70,8 @@ enum sj_flags {
   SJ_REORDER = 1u << 1,  /* task scheduling optimisation: leaves processed
                             heaviest first, weight = intersecting subqueries x
                             objects (Section "Optimizations") */
-  SJ_PROFILE = 1u << 2   /* record per-phase device times (sj_phase_times) */
+  SJ_PROFILE = 1u << 2,  /* record per-phase device times (sj_phase_times) */
+  SJ_TIMING_LOG = 1u << 3 /* per-leaf join timing log (sj_timing_log) */
 };
 
 /* Quadtree reuse across ticks (the paper builds the partitioning on the
@@ -247,6 +248,20 @@ int sj_tick_counters(sj_scene *scene, uint64_t *d_out);
 /* Counters of the last tick; synchronises; returns the latched error. */
 int sj_stats(sj_scene *scene, sj_tick_stats *out);
 
+/* Per-leaf timing log of the last tick (SJ_TIMING_LOG): for every leaf,
+ * 8 floats: objects, intersecting subqueries, level, mean overlap area
+ * fraction of its intersecting subqueries with the leaf, device-clock ticks
+ * of the wave that joined it in the count pass and in the write pass, 0, 0.
+ * clock_mhz converts ticks to microseconds.  Device view valid until the
+ * next call; synchronises. */
+typedef struct sj_timing_view {
+  uint32_t n_leaves;
+  float clock_mhz;
+  const float *d_records; /* [n_leaves][8] */
+} sj_timing_view;
+
+int sj_timing_log(sj_scene *scene, sj_timing_view *out);
+
 /* Device times of the phases of the last tick (SJ_PROFILE), n <=
  * SJ_PH_COUNT floats.  Synchronises.  After a graph tick (sj_tick_graph)
  * only SJ_PH_JOIN_WRITE is timed (the pass runs as a graph of its own
@@ -344,7 +359,40 @@ int sj_server_scene(sj_server *server, uint32_t scene_id, sj_scene **out);
 
 const char *sj_server_last_error(const sj_server *server);
 
-/* Message for the last error of the scene (or of creation when NULL). */
+/* ------------------------------------------------------------------------
+ * Cost model: an MLP 4 -> 64 -> 64 -> 1 with ReLU that predicts the join
+ * time of a quadtree leaf (natural log of microseconds).  Inputs per leaf
+ * (float[4]): log2(1 + objects), log2(1 + intersecting subqueries),
+ * level / 16, mean overlap area fraction of its intersecting subqueries.
+ * Parameters: sj_mlp_param_count() values, layout W1[64][4], b1[64],
+ * W2[64][64], b2[64], w3[64], b3; used as BF16 (round to nearest even of
+ * FP32 masters), arithmetic in FP32.  Not part of the paper: it chooses the
+ * split threshold (the paper's th_quad, fixed there) for the quadtree.
+ * All pointers are device pointers; calls are asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+uint32_t sj_mlp_param_count(void);
+
+/* d_w[i] = BF16 rounding of d_master[i]. */
+int sj_mlp_round(const float *d_master, uint16_t *d_w, hipStream_t stream);
+
+/* d_y[s] = MLP(d_x[4 s .. 4 s + 3]) for s < n. */
+int sj_mlp_forward(const uint16_t *d_w, const float *d_x, uint32_t n, float *d_y,
+                   hipStream_t stream);
+
+/* Gradient of L = (1/n) sum_s (MLP(x_s) - t_s)^2 with respect to the BF16
+ * parameters: d_grad[0 .. P) (P = sj_mlp_param_count()), and d_grad[P] = L.
+ * d_scratch: sj_mlp_scratch_bytes(n) bytes.  Deterministic. */
+size_t sj_mlp_scratch_bytes(uint32_t n);
+int sj_mlp_grad(const uint16_t *d_w, const float *d_x, const float *d_t, uint32_t n,
+                float *d_grad, void *d_scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on the FP32 masters with moments d_m, d_v; writes the BF16 copy d_w. */
+int sj_mlp_adam(float *d_master, const float *d_grad, float *d_m, float *d_v, uint16_t *d_w,
+                uint32_t step, float lr, hipStream_t stream);
+
+/* Message for the last error of the scene; with NULL, of the last failed
+ * scene creation or call that takes no scene (server creation, sj_mlp_*). */
 const char *sj_last_error(const sj_scene *scene);
 
 #ifdef __cplusplus

@@ -17,7 +17,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
 
 SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SJ_COVERING, SJ_REORDER, SJ_PROFILE = 1, 2, 4
+SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG = 1, 2, 4, 8
 REBUILD = {"auto": 0, "always": 1, "never": 2}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
           "join_write"]
@@ -62,6 +62,10 @@ class SjIndexView(Structure):
                 ("d_py", c_void_p)]
 
 
+class SjTimingView(Structure):
+    _fields_ = [("n_leaves", c_uint32), ("clock_mhz", c_float), ("d_records", c_void_p)]
+
+
 class SjServed(Structure):
     _fields_ = [("tag", c_uint64), ("scene_id", c_uint32), ("status", c_int32), ("nq", c_uint32),
                 ("d_count", c_void_p), ("d_hash", c_void_p), ("d_counters", c_void_p)]
@@ -90,6 +94,7 @@ EXPORTS = {
     "sj_stats": (c_int, [c_void_p, POINTER(SjTickStats)]),
     "sj_phase_times": (c_int, [c_void_p, POINTER(c_float), c_int]),
     "sj_index_view_get": (c_int, [c_void_p, POINTER(SjIndexView)]),
+    "sj_timing_log": (c_int, [c_void_p, POINTER(SjTimingView)]),
     "sj_last_error": (c_char_p, [c_void_p]),
     "sj_server_scene_bytes": (c_size_t, [POINTER(SjConfig), c_uint32]),
     "sj_server_create": (c_int, [c_void_p, c_size_t, c_uint32, POINTER(c_void_p)]),
@@ -103,6 +108,14 @@ EXPORTS = {
     "sj_server_info": (c_int, [c_void_p, POINTER(SjServerStats)]),
     "sj_server_scene": (c_int, [c_void_p, c_uint32, POINTER(c_void_p)]),
     "sj_server_last_error": (c_char_p, [c_void_p]),
+    "sj_mlp_param_count": (c_uint32, []),
+    "sj_mlp_round": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "sj_mlp_forward": (c_int, [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
+    "sj_mlp_scratch_bytes": (c_size_t, [c_uint32]),
+    "sj_mlp_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p, c_size_t,
+                            c_void_p]),
+    "sj_mlp_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_float,
+                            c_void_p]),
 }
 
 _lib = None
@@ -135,9 +148,9 @@ def make_config(capacity_objects: int, capacity_queries: int, *, th: int = 64, t
                 l_max: int = 16, covering: bool = True, reorder: bool = True,
                 rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                 capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
-                profile: bool = False) -> SjConfig:
+                profile: bool = False, timing_log: bool = False) -> SjConfig:
     flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
-            (SJ_PROFILE if profile else 0)
+            (SJ_PROFILE if profile else 0) | (SJ_TIMING_LOG if timing_log else 0)
     return SjConfig(capacity_objects, capacity_queries, capacity_subqueries, capacity_covering,
                     capacity_results, th, th_min, l_max, flags, REBUILD[rebuild], rebuild_period,
                     split_slots)
@@ -194,7 +207,7 @@ class Scene:
                  th_min: int = 0, l_max: int = 16, covering: bool = True, reorder: bool = True,
                  rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                  capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
-                 profile: bool = False, device=None, stream=None):
+                 profile: bool = False, timing_log: bool = False, device=None, stream=None):
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
@@ -204,7 +217,7 @@ class Scene:
                                capacity_subqueries=capacity_subqueries,
                                capacity_covering=capacity_covering,
                                capacity_results=capacity_results, split_slots=split_slots,
-                               profile=profile)
+                               profile=profile, timing_log=timing_log)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")
@@ -332,6 +345,16 @@ class Scene:
         buf = (c_float * len(PHASES))()
         _check(self._lib.sj_phase_times(self.handle, buf, len(PHASES)), self.handle)
         return {k: float(buf[i]) for i, k in enumerate(PHASES)}
+
+    def timing_log(self):
+        """(records [n_leaves, 8] float32 device view, clock MHz) of the
+        last tick: objects, intersecting subqueries, level, mean overlap,
+        count-pass ticks, write-pass ticks, 0, 0."""
+        import torch
+        v = SjTimingView()
+        _check(self._lib.sj_timing_log(self.handle, byref(v)), self.handle)
+        rec = self._view(v.d_records, int(v.n_leaves) * 8, torch.float32)
+        return rec.view(int(v.n_leaves), 8), float(v.clock_mhz)
 
     def index_view(self) -> dict:
         import torch

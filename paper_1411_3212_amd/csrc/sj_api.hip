@@ -1,6 +1,7 @@
 // C ABI of libsj (declared in include/sj.h): scene lifecycle, workspace
 // layout, and the host side of the tick pipeline.
 #include <hip/hip_runtime.h>
+#include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -55,6 +56,7 @@ namespace {
 
 struct Derived {
   uint32_t N, Q, th, th_min, l_max, period, slots, tcap;
+  bool log;
   uint64_t S, C, R;
   uint32_t LCAP, NCAP, FCAP;
 };
@@ -94,6 +96,7 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
   }
   d->period = cfg->rebuild_period ? cfg->rebuild_period : 32u;
   d->slots = cfg->split_slots ? cfg->split_slots : 32u;
+  d->log = (cfg->flags & SJ_TIMING_LOG) != 0;
   if (d->slots > 4096u) {
     snprintf(msg, msz, "split_slots must be at most 4096");
     return SJ_EINVAL;
@@ -190,6 +193,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.res_off = c.take<uint64_t>(d.S + 1);
   b.cov_leaf = c.take<uint32_t>(d.C);
   b.res_ids = c.take<uint32_t>(d.R);
+  b.tlog = d.log ? c.take<float>((uint64_t)L * 8) : nullptr;
   b.N = d.N;
   b.Q = d.Q;
   b.LCAP = d.LCAP;
@@ -629,6 +633,20 @@ int sj_phase_times(sj_scene *s, float *ms, int n) {
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipEventElapsedTime");
 }
 
+int sj_timing_log(sj_scene *s, sj_timing_view *out) {
+  if (!s || !out) return SJ_EINVAL;
+  if (!s->B.tlog) return fail(s, SJ_ESTATE, "scene created without SJ_TIMING_LOG");
+  int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  int khz = 0;
+  hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device);
+  if (e != hipSuccess) return hip_fail(s, e, "wall clock rate");
+  out->n_leaves = s->host_ctl.n_leaves;
+  out->clock_mhz = (float)khz / 1000.0f;
+  out->d_records = s->B.tlog;
+  return SJ_OK;
+}
+
 int sj_index_view_get(sj_scene *s, sj_index_view *out) {
   if (!s || !out) return SJ_EINVAL;
   int rc = sync_ctl(s);
@@ -653,6 +671,7 @@ int sj_index_view_get(sj_scene *s, sj_index_view *out) {
 
 const char *sj_last_error(const sj_scene *s) { return s ? s->err : g_create_err; }
 
+
 }  // extern "C"
 
 int sj_scene_ctl_to_host_async(sj_scene *s, Ctl *h_ctl) {
@@ -666,3 +685,10 @@ void sj_scene_ctl_from_host(sj_scene *s, const Ctl *h_ctl) {
 }
 
 int sj_scene_status(sj_scene *s) { return status_of(s, s->host_ctl.err); }
+
+void sj_set_global_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_create_err, sizeof g_create_err, fmt, ap);
+  va_end(ap);
+}

@@ -41,6 +41,7 @@ struct Bufs {
   uint32_t *sq_q, *sq_s, *sq_cnt;
   uint64_t *res_off;
   uint32_t *cov_leaf, *res_ids;
+  float *tlog;                          // per-leaf timing log (or null)
   // capacities
   uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap;
   uint64_t S, C, R;

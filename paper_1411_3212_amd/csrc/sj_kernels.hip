@@ -732,7 +732,7 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
                                                       const uint32_t *leaf_sqoff,
                                                       const uint32_t *llevel, uint32_t l_max,
                                                       uint32_t *tkey, uint32_t *tasks,
-                                                      uint64_t *red) {
+                                                      uint64_t *red, float *tlog) {
   __shared__ uint64_t s_tests[kWavesPerBlock];
   __shared__ uint32_t s_max[kWavesPerBlock], s_tasks[kWavesPerBlock];
   const uint32_t n = ctl->n_leaves;
@@ -748,6 +748,13 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
     if (llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
     tkey[t] = w == 0 ? 255u : 255u - (uint32_t)(64 - __clzll((long long)w));
     tasks[t] = t;
+    if (tlog) {
+      float *rec = tlog + (uint64_t)t * 8;
+      rec[0] = (float)cnt;
+      rec[1] = (float)nsq;
+      rec[2] = (float)llevel[t];
+      rec[3] = rec[4] = rec[5] = rec[6] = rec[7] = 0.0f;
+    }
   }
   tests = wave_sum(tests);
   nt = wave_sum(nt);
@@ -780,12 +787,25 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
 // set writes its object id at the subquery's offset plus the number of set
 // bits below it (coalesced, no atomics, no bitmap in memory).
 
+// Area fraction of leaf `leaf` covered by rectangle r (timing-log feature).
+__device__ __forceinline__ float overlap_frac(const Ctl *ctl, const uint32_t *lstart,
+                                              const uint32_t *llevel, uint32_t leaf, float4 r) {
+  const uint32_t st = lstart[leaf], l = llevel[leaf];
+  const float inv = 1.0f / ctl->scale, size = (float)(1u << (kFine - l)) * inv;
+  const float x0 = ctl->x0 + (float)compact16(st) * inv, y0 = ctl->y0 + (float)compact16(st >> 1) * inv;
+  const float w = fminf(r.z, x0 + size) - fmaxf(r.x, x0);
+  const float h = fminf(r.w, y0 + size) - fmaxf(r.y, y0);
+  return (w > 0.0f && h > 0.0f) ? fminf(1.0f, (w / size) * (h / size)) : 0.0f;
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint32_t *tasks,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
                                                        const float4 *qrect, const float2 *sxy,
-                                                       uint32_t *sq_cnt) {
+                                                       uint32_t *sq_cnt, float *tlog,
+                                                       const uint32_t *lstart,
+                                                       const uint32_t *llevel) {
   if (!ctl->go_split) return;
   const uint32_t nt = ctl->n_leaves;
   const uint32_t lane = lane_id();
@@ -797,6 +817,8 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
     const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
     if (sb == se) continue;
     const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
+    const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
+    float ovl = 0.0f;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -804,6 +826,7 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
       if (lane < nk) {
         slot = sq_s[sc + lane];
         r = qrect[sq_q[sc + lane]];
+        if (tlog) ovl += overlap_frac(ctl, lstart, llevel, leaf, r);
       }
       for (uint32_t o = ob; o < oe; o += kWave) {
         const bool has = o + lane < oe;
@@ -817,6 +840,14 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
         }
       }
       if (lane < nk) sq_cnt[slot] = cnt;
+    }
+    if (tlog) {
+      ovl = wave_sum(ovl);
+      const uint64_t clk1 = __builtin_amdgcn_s_memrealtime();
+      if (lane == 0) {
+        tlog[(uint64_t)leaf * 8 + 3] = ovl / (float)(se - sb);
+        tlog[(uint64_t)leaf * 8 + 4] = (float)(clk1 - clk0);
+      }
     }
   }
 }
@@ -870,7 +901,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
                                                        const uint32_t *sid,
                                                        const uint64_t *res_off, uint32_t *res_ids,
                                                        uint32_t nq, const uint32_t *q_ioff,
-                                                       uint64_t *q_roff) {
+                                                       uint64_t *q_roff, float *tlog) {
   const bool go = ctl->go_join != 0;
   // per-query offsets of the intersecting results
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
@@ -890,6 +921,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
     const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
     if (sb == se) continue;
     const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
+    const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -913,6 +945,8 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
         }
       }
     }
+    if (tlog && lane == 0)
+      tlog[(uint64_t)leaf * 8 + 5] = (float)(__builtin_amdgcn_s_memrealtime() - clk0);
   }
 }
 
@@ -1102,7 +1136,8 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
 
 const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, hipStream_t s) {
   LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)B.leaf_beg,
-         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks, B.red);
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks, B.red,
+         B.tlog);
   if (!reorder) return B.tasks;
   const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_leaves,
                                     &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
@@ -1112,7 +1147,8 @@ const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max,
 void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s) {
   LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, tasks,
          (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
-         (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt);
+         (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
+         B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel);
 }
 
 void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
@@ -1129,7 +1165,7 @@ void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStr
   LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, tasks, (const uint32_t *)B.leaf_beg,
          (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
          (const float4 *)B.qrect, (const float2 *)B.sxy, (const uint32_t *)B.valA,
-         (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff);
+         (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
 }
 
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s) {

@@ -11,3 +11,6 @@ int sj_scene_ctl_to_host_async(sj_scene *scene, sj::Ctl *h_ctl);
 void sj_scene_ctl_from_host(sj_scene *scene, const sj::Ctl *h_ctl);
 // Status of the last tick from the adopted control block.
 int sj_scene_status(sj_scene *scene);
+// Message returned by sj_last_error(NULL) (creation and the calls that take
+// no scene).
+void sj_set_global_error(const char *fmt, ...);
