@@ -71,7 +71,9 @@ enum sj_flags {
                             heaviest first, weight = intersecting subqueries x
                             objects (Section "Optimizations") */
   SJ_PROFILE = 1u << 2,  /* record per-phase device times (sj_phase_times) */
-  SJ_TIMING_LOG = 1u << 3 /* per-leaf join timing log (sj_timing_log) */
+  SJ_TIMING_LOG = 1u << 3, /* per-leaf join timing log (sj_timing_log) */
+  SJ_THRESH_MLP = 1u << 4  /* builds pick their threshold with the cost
+                              model installed by sj_set_cost_model */
 };
 
 /* Quadtree reuse across ticks (the paper builds the partitioning on the
@@ -109,6 +111,8 @@ typedef struct sj_config {
   uint32_t split_slots;         /* subqueries per query remembered between the
                                    count and write passes of query splitting;
                                    queries with more are walked twice (0: 32) */
+  uint32_t tune_every;          /* SJ_THRESH_MLP: host-decided builds between
+                                   two tunings; the first build is tuned (0: 8) */
 } sj_config;
 
 /* Compressed results of the last tick (Sections "Bitmap decoding" and
@@ -247,6 +251,40 @@ int sj_tick_counters(sj_scene *scene, uint64_t *d_out);
 
 /* Counters of the last tick; synchronises; returns the latched error. */
 int sj_stats(sj_scene *scene, sj_tick_stats *out);
+
+/* Learned threshold (not in the paper, which fixes th_quad after a sweep,
+ * Experimental evaluation S5; the terms of the cost follow the
+ * Computational Complexity section).  With SJ_THRESH_MLP and a model
+ * installed, a tick that builds the quadtree on the host's decision (the
+ * host decides when a call that synchronises, such as sj_fetch_results or
+ * sj_stats, has read the scene's state after the previous tick), the first
+ * such build and then every tune_every-th, first builds and splits at every
+ * candidate threshold, predicts
+ *   cost = coef[0] * sum over active leaves c of exp(MLP(f_c))
+ *        + coef[1] |Q_I| + coef[2] |Q_C| + coef[3] * leaves
+ * with f_c = (log2(1 + |P^c|), log2(1 + |Q_I^c|), level / 16, mean over the
+ * intersecting subqueries of c of the fraction of c's area they cover), and
+ * builds the cheapest (the first of equal costs; a candidate that overflows
+ * a capacity is infeasible; with none feasible the threshold is kept).
+ * Results do not depend on it.
+ * d_w: sj_mlp_param_count() BF16 parameters (device, copied); cand: n_cand
+ * (1..8) thresholds, each >= th_min.  Synchronises the scene's stream.
+ * Errors: SJ_EINVAL (null pointers, bad n_cand or a candidate below th_min). */
+int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[4],
+                      const uint32_t *cand, uint32_t n_cand);
+
+typedef struct sj_tune_info {
+  uint32_t n_cand;
+  uint32_t cand[8];
+  float cost[8];        /* predicted cost per candidate (inf: infeasible) */
+  float mlp_sum[8];     /* sum over active leaves of exp(MLP) */
+  uint32_t chosen;      /* threshold of the last tuning */
+  uint32_t n_tunes;     /* tunings so far */
+  uint32_t tuned_tick;  /* ticks completed before the last tuning */
+} sj_tune_info;
+
+/* Outcome of the last tuning; synchronises. */
+int sj_tune_info_get(sj_scene *scene, sj_tune_info *out);
 
 /* Per-leaf timing log of the last tick (SJ_TIMING_LOG): for every leaf,
  * 8 floats: objects, intersecting subqueries, level, mean overlap area

@@ -17,7 +17,7 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
 
 SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG = 1, 2, 4, 8
+SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG, SJ_THRESH_MLP = 1, 2, 4, 8, 16
 REBUILD = {"auto": 0, "always": 1, "never": 2}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
           "join_write"]
@@ -36,7 +36,7 @@ class SjConfig(Structure):
                 ("capacity_subqueries", c_uint64), ("capacity_covering", c_uint64),
                 ("capacity_results", c_uint64), ("th_quad", c_uint32), ("th_min", c_uint32),
                 ("l_max", c_uint32), ("flags", c_uint32), ("rebuild_policy", c_uint32),
-                ("rebuild_period", c_uint32), ("split_slots", c_uint32)]
+                ("rebuild_period", c_uint32), ("split_slots", c_uint32), ("tune_every", c_uint32)]
 
 
 class SjResults(Structure):
@@ -64,6 +64,12 @@ class SjIndexView(Structure):
 
 class SjTimingView(Structure):
     _fields_ = [("n_leaves", c_uint32), ("clock_mhz", c_float), ("d_records", c_void_p)]
+
+
+class SjTuneInfo(Structure):
+    _fields_ = [("n_cand", c_uint32), ("cand", c_uint32 * 8), ("cost", c_float * 8),
+                ("mlp_sum", c_float * 8), ("chosen", c_uint32), ("n_tunes", c_uint32),
+                ("tuned_tick", c_uint32)]
 
 
 class SjServed(Structure):
@@ -95,6 +101,9 @@ EXPORTS = {
     "sj_phase_times": (c_int, [c_void_p, POINTER(c_float), c_int]),
     "sj_index_view_get": (c_int, [c_void_p, POINTER(SjIndexView)]),
     "sj_timing_log": (c_int, [c_void_p, POINTER(SjTimingView)]),
+    "sj_set_cost_model": (c_int, [c_void_p, c_void_p, POINTER(c_float), POINTER(c_uint32),
+                                  c_uint32]),
+    "sj_tune_info_get": (c_int, [c_void_p, POINTER(SjTuneInfo)]),
     "sj_last_error": (c_char_p, [c_void_p]),
     "sj_server_scene_bytes": (c_size_t, [POINTER(SjConfig), c_uint32]),
     "sj_server_create": (c_int, [c_void_p, c_size_t, c_uint32, POINTER(c_void_p)]),
@@ -148,12 +157,14 @@ def make_config(capacity_objects: int, capacity_queries: int, *, th: int = 64, t
                 l_max: int = 16, covering: bool = True, reorder: bool = True,
                 rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                 capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
-                profile: bool = False, timing_log: bool = False) -> SjConfig:
+                profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
+                tune_every: int = 0) -> SjConfig:
     flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
-            (SJ_PROFILE if profile else 0) | (SJ_TIMING_LOG if timing_log else 0)
+            (SJ_PROFILE if profile else 0) | (SJ_TIMING_LOG if timing_log else 0) | \
+            (SJ_THRESH_MLP if thresh_mlp else 0)
     return SjConfig(capacity_objects, capacity_queries, capacity_subqueries, capacity_covering,
                     capacity_results, th, th_min, l_max, flags, REBUILD[rebuild], rebuild_period,
-                    split_slots)
+                    split_slots, tune_every)
 
 
 def _ptr(t):
@@ -207,7 +218,8 @@ class Scene:
                  th_min: int = 0, l_max: int = 16, covering: bool = True, reorder: bool = True,
                  rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                  capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
-                 profile: bool = False, timing_log: bool = False, device=None, stream=None):
+                 profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
+                 tune_every: int = 0, device=None, stream=None):
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
@@ -217,7 +229,8 @@ class Scene:
                                capacity_subqueries=capacity_subqueries,
                                capacity_covering=capacity_covering,
                                capacity_results=capacity_results, split_slots=split_slots,
-                               profile=profile, timing_log=timing_log)
+                               profile=profile, timing_log=timing_log, thresh_mlp=thresh_mlp,
+                               tune_every=tune_every)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")
@@ -345,6 +358,23 @@ class Scene:
         buf = (c_float * len(PHASES))()
         _check(self._lib.sj_phase_times(self.handle, buf, len(PHASES)), self.handle)
         return {k: float(buf[i]) for i, k in enumerate(PHASES)}
+
+    def set_cost_model(self, w, coef, cand):
+        """Installs the cost model: w = BF16 parameters (int16/uint16 device
+        tensor of sj_mlp_param_count() values, copied), coef = 4 floats,
+        cand = candidate thresholds (1..8, each >= th_min)."""
+        import torch
+        assert w.is_cuda and w.dtype in (torch.int16, torch.uint16) and w.is_contiguous()
+        cf = (c_float * 4)(*[float(v) for v in coef])
+        cd = (c_uint32 * len(cand))(*[int(v) for v in cand])
+        _check(self._lib.sj_set_cost_model(self.handle, _ptr(w), cf, cd, len(cand)), self.handle)
+
+    def tune_info(self) -> dict:
+        t = SjTuneInfo()
+        _check(self._lib.sj_tune_info_get(self.handle, byref(t)), self.handle)
+        n = int(t.n_cand)
+        return dict(cand=list(t.cand[:n]), cost=list(t.cost[:n]), mlp_sum=list(t.mlp_sum[:n]),
+                    chosen=int(t.chosen), n_tunes=int(t.n_tunes), tuned_tick=int(t.tuned_tick))
 
     def timing_log(self):
         """(records [n_leaves, 8] float32 device view, clock MHz) of the

@@ -2,6 +2,7 @@
 // layout, and the host side of the tick pipeline.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -39,7 +40,7 @@ struct sj_scene {
   bool known;          // host_ctl reflects the device state after the last tick
   bool events_valid;   // phase events were recorded for the last tick
   bool join_events;    // only the join write pass was timed (graph tick)
-  GraphSlot graphs[3]; // captured ticks per rebuild decision (keep, build, device)
+  GraphSlot graphs[4]; // captured ticks per decision (keep, build, device, build + tune)
   hipStream_t cap_stream;  // private stream graphs are captured on
   bool force_pending;  // sj_build_index since the last tick
   uint64_t upd_pending;  // updates enqueued since the last tick
@@ -47,6 +48,11 @@ struct sj_scene {
   hipEvent_t ev[SJ_PH_COUNT + 2];
   hipEvent_t ev_u0, ev_u1;
   Ctl host_ctl;
+  bool cm_set;          // a cost model is installed (sj_set_cost_model)
+  uint32_t n_cand;      // its candidate thresholds
+  uint32_t tune_every;  // host-decided builds between two tunings
+  uint32_t since_tune;  // host-decided builds since the last tuning
+  bool tuned;           // a tuning has been enqueued
   char err[256];
 };
 
@@ -55,7 +61,7 @@ static char g_create_err[256] = "";
 namespace {
 
 struct Derived {
-  uint32_t N, Q, th, th_min, l_max, period, slots, tcap;
+  uint32_t N, Q, th, th_min, l_max, period, slots, tcap, tune_every;
   bool log;
   uint64_t S, C, R;
   uint32_t LCAP, NCAP, FCAP;
@@ -97,6 +103,7 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
   d->period = cfg->rebuild_period ? cfg->rebuild_period : 32u;
   d->slots = cfg->split_slots ? cfg->split_slots : 32u;
   d->log = (cfg->flags & SJ_TIMING_LOG) != 0;
+  d->tune_every = cfg->tune_every ? cfg->tune_every : 8u;
   if (d->slots > 4096u) {
     snprintf(msg, msz, "split_slots must be at most 4096");
     return SJ_EINVAL;
@@ -194,6 +201,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.cov_leaf = c.take<uint32_t>(d.C);
   b.res_ids = c.take<uint32_t>(d.R);
   b.tlog = d.log ? c.take<float>((uint64_t)L * 8) : nullptr;
+  b.tune = c.take<sj::TuneState>(1);
   b.N = d.N;
   b.Q = d.Q;
   b.LCAP = d.LCAP;
@@ -266,10 +274,27 @@ uint32_t host_decision(const sj_scene *s) {
   return r ? 1u : 0u;
 }
 
+// Whether a tick with this rebuild decision tunes the threshold first: the
+// first build decided on the host and every tune_every-th after it.
+bool want_tune(const sj_scene *s, uint32_t decision) {
+  return s->cm_set && (s->cfg.flags & SJ_THRESH_MLP) && decision == 1u &&
+         (!s->tuned || s->since_tune + 1u >= s->tune_every);
+}
+
+void count_build(sj_scene *s, uint32_t decision, bool tune) {
+  if (decision != 1u) return;
+  if (tune) {
+    s->tuned = true;
+    s->since_tune = 0;
+  } else {
+    s->since_tune += 1;
+  }
+}
+
 // part: 0 the whole tick; 1 up to the result-offset scan; 2 the join write.
 void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
                   const float *d_xb, const float *d_yb, uint32_t nq, uint32_t decision,
-                  uint64_t upd_total, bool events, int part = 0) {
+                  uint64_t upd_total, bool events, int part = 0, bool tune = false) {
   const hipStream_t st = s->stream;
   const uint32_t flags = s->cfg.flags;
   const uint32_t policy = s->cfg.rebuild_policy;
@@ -284,6 +309,9 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
   rec(0);
   sj::launch_index(s->B, decision, policy, upd_total, d_qid, nq, st);
   rec(1);
+  if (tune)
+    sj::launch_tune(s->B, s->n_cand, s->l_max, d_qid, d_xa, d_ya, d_xb, d_yb, nq,
+                    (flags & SJ_COVERING) ? 1u : 0u, st);
   if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
   rec(2);
   sj::launch_leaves(s->B, st);
@@ -351,6 +379,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   s->l_max = d.l_max;
   s->period = d.period;
   s->prof = (cfg->flags & SJ_PROFILE) != 0;
+  s->tune_every = d.tune_every;
   s->known = true;  // host_ctl is zero: not built, the first tick builds
   (void)hipGetDevice(&s->device);
   carve(d, s->ws, &s->B);
@@ -370,6 +399,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   sj::launch_fill_u32((uint32_t *)s->B.py, d.N, 0x7fc00000u, stream);
   sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
   sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
+  sj::launch_fill_u32((uint32_t *)s->B.tune, sizeof(sj::TuneState) / 4, 0u, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     snprintf(g_create_err, sizeof g_create_err, "kernel launch: %s", hipGetErrorString(e));
@@ -430,7 +460,10 @@ int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const flo
   if (!s) return SJ_EINVAL;
   int rc = check_tick_args(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq);
   if (rc != SJ_OK) return rc;
-  enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, host_decision(s), s->upd_pending, s->prof);
+  const uint32_t decision = host_decision(s);
+  const bool tune = want_tune(s, decision);
+  enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, s->upd_pending, s->prof, 0, tune);
+  count_build(s, decision, tune);
   after_tick(s, d_qid, nq);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "run_tick launch");
@@ -452,7 +485,8 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     return rc != SJ_OK ? rc : sj_run_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq);
   }
   const uint32_t decision = host_decision(s);
-  GraphSlot &g = s->graphs[decision];
+  const bool tune = want_tune(s, decision);
+  GraphSlot &g = s->graphs[tune ? 3u : decision];
   const void *ptrs[8] = {d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
   bool same = g.valid && g.m == m && g.nq == nq;
   for (int i = 0; same && i < 8; ++i) same = g.ptrs[i] == ptrs[i];
@@ -477,7 +511,7 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
       if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
       s->stream = s->cap_stream;
       if (part != 2 && m) sj::launch_updates(s->B, d_id, d_x, d_y, m, 0, s->stream);
-      enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, m, false, part);
+      enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, m, false, part, tune);
       s->stream = user;
       e = hipStreamEndCapture(s->cap_stream, &graph);
       if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
@@ -506,6 +540,7 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     if (e == hipSuccess) e = hipEventRecord(s->ev[8], s->stream);
   }
   if (e != hipSuccess) return hip_fail(s, e, "hipGraphLaunch");
+  count_build(s, decision, tune);
   after_tick(s, d_qid, nq);
   s->events_valid = false;
   s->join_events = s->prof;
@@ -631,6 +666,64 @@ int sj_phase_times(sj_scene *s, float *ms, int n) {
   for (int i = 0; i < n && i < SJ_PH_COUNT; ++i) ms[i] = t[i];
   s->upd_open = false;
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipEventElapsedTime");
+}
+
+int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[4], const uint32_t *cand,
+                      uint32_t n_cand) {
+  if (!s || !d_w || !coef || !cand) return SJ_EINVAL;
+  if (n_cand == 0 || n_cand > (uint32_t)sj::kMaxCand)
+    return fail(s, SJ_EINVAL, "set_cost_model: n_cand must be in 1..8");
+  const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
+  for (uint32_t c = 0; c < n_cand; ++c)
+    if (cand[c] < th_min || cand[c] == 0)
+      return fail(s, SJ_EINVAL, "set_cost_model: candidate below th_min");
+  struct {
+    float coef[4];
+    uint32_t n_cand;
+    uint32_t cand[sj::kMaxCand];
+  } h{};
+  for (int i = 0; i < 4; ++i) h.coef[i] = coef[i];
+  h.n_cand = n_cand;
+  for (uint32_t c = 0; c < n_cand; ++c) h.cand[c] = cand[c];
+  static_assert(offsetof(sj::TuneState, n_cand) == offsetof(sj::TuneState, coef) + 16, "layout");
+  static_assert(offsetof(sj::TuneState, cand) == offsetof(sj::TuneState, n_cand) + 4, "layout");
+  sj::TuneState *ts = s->B.tune;
+  hipError_t e = hipMemcpyAsync(ts->w, d_w, 4545 * sizeof(uint16_t), hipMemcpyDeviceToDevice,
+                                s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ts->coef, &h, sizeof h, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "set_cost_model copy");
+  s->cm_set = true;
+  s->n_cand = n_cand;
+  s->tuned = false;
+  s->since_tune = 0;
+  GraphSlot &g = s->graphs[3];  // captured with the previous candidate count
+  if (g.valid) {
+    (void)hipGraphExecDestroy(g.exec);
+    if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+    g.valid = false;
+  }
+  return SJ_OK;
+}
+
+int sj_tune_info_get(sj_scene *s, sj_tune_info *out) {
+  if (!s || !out) return SJ_EINVAL;
+  sj::TuneState h;
+  hipError_t e = hipMemcpyAsync(&h, s->B.tune, sizeof h, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "tune_info copy");
+  memset(out, 0, sizeof *out);
+  out->n_cand = h.n_cand < (uint32_t)sj::kMaxCand ? h.n_cand : (uint32_t)sj::kMaxCand;
+  for (uint32_t c = 0; c < out->n_cand; ++c) {
+    out->cand[c] = h.cand[c];
+    out->cost[c] = h.cost[c];
+    out->mlp_sum[c] = h.msum[c];
+  }
+  out->chosen = h.chosen;
+  out->n_tunes = h.n_tunes;
+  out->tuned_tick = h.tuned_tick;
+  return SJ_OK;
 }
 
 int sj_timing_log(sj_scene *s, sj_timing_view *out) {

@@ -62,7 +62,7 @@ struct Ctl {
 // Slots of the per-block partial reductions (red[slot * kChunkBlocks + b]).
 enum : int {
   kRedMinX = 0, kRedMinY, kRedMaxX, kRedMaxY, kRedOutside,
-  kRedCovPairs, kRedTests, kRedMaxLeaf, kRedTasks, kRedSlots
+  kRedCovPairs, kRedTests, kRedMaxLeaf, kRedTasks, kRedCost, kRedSlots
 };
 
 __device__ __forceinline__ uint32_t fenc(float f) {
@@ -94,6 +94,16 @@ __device__ __forceinline__ uint32_t spread16(uint32_t x) {
 }
 __device__ __forceinline__ uint32_t morton2(uint32_t i, uint32_t j) {
   return spread16(i) | (spread16(j) << 1);
+}
+
+// Inverse of spread16: the even bits of x.
+__device__ __forceinline__ uint32_t compact16(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -231,5 +241,34 @@ __device__ __forceinline__ uint64_t scan_partials(uint64_t *part, uint64_t *lds)
   part[threadIdx.x] = ex;
   return total;
 }
+
+// Fraction of the area of leaf `leaf` (level l, first finest cell st) that
+// rectangle r covers, clamped to [0, 1]: the overlap feature of the cost
+// model (timing log and threshold tuner).
+__device__ __forceinline__ float overlap_frac(const Ctl *ctl, const uint32_t *lstart,
+                                              const uint32_t *llevel, uint32_t leaf, float4 r) {
+  const uint32_t st = lstart[leaf], l = llevel[leaf];
+  const float inv = 1.0f / ctl->scale, size = (float)(1u << (kFine - l)) * inv;
+  const float x0 = ctl->x0 + (float)compact16(st) * inv;
+  const float y0 = ctl->y0 + (float)compact16(st >> 1) * inv;
+  const float w = fminf(r.z, x0 + size) - fmaxf(r.x, x0);
+  const float h = fminf(r.w, y0 + size) - fmaxf(r.y, y0);
+  return (w > 0.0f && h > 0.0f) ? fminf(1.0f, (w / size) * (h / size)) : 0.0f;
+}
+
+// Threshold tuner state (device memory): the installed cost model and the
+// outcome of the last tuning.
+constexpr int kMaxCand = 8;
+struct TuneState {
+  uint16_t w[4548];          // BF16 MLP parameters (4545 used)
+  float coef[4];             // cost = c0 * sum exp(mlp) + c1 |Q_I| + c2 |Q_C| + c3 leaves
+  uint32_t n_cand;
+  uint32_t cand[kMaxCand];   // candidate thresholds
+  float cost[kMaxCand];      // predicted cost per candidate (inf: infeasible)
+  float msum[kMaxCand];      // sum over active leaves of exp(mlp) per candidate
+  uint32_t err_saved;        // tick errors before the trial builds
+  uint32_t th_before;        // threshold before the tuning
+  uint32_t chosen, n_tunes, tuned_tick;
+};
 
 }  // namespace sj

@@ -9,6 +9,7 @@
 namespace sj {
 
 struct Ctl;
+struct TuneState;
 
 constexpr unsigned kJoinBlocks = 4096;  // 16384 waves for the join passes
 
@@ -42,6 +43,7 @@ struct Bufs {
   uint64_t *res_off;
   uint32_t *cov_leaf, *res_ids;
   float *tlog;                          // per-leaf timing log (or null)
+  TuneState *tune;                      // threshold tuner state
   // capacities
   uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap;
   uint64_t S, C, R;
@@ -65,6 +67,11 @@ void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s);
 void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
                       hipStream_t s);
 void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s);
+// Trial builds and splits at every candidate threshold, cost prediction,
+// and the choice of the threshold that the tick's build then uses.
+void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
+                 const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,
+                 uint32_t covering, hipStream_t s);
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s);
 void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt, uint64_t *hash,
                  hipStream_t s);

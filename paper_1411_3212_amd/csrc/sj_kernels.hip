@@ -58,14 +58,6 @@ __global__ void k_request_build(Ctl *ctl, uint32_t th) {
   if (th) ctl->th_next = th;
 }
 
-__device__ __forceinline__ uint32_t compact16(uint32_t x) {
-  x &= 0x55555555u;
-  x = (x | (x >> 1)) & 0x33333333u;
-  x = (x | (x >> 2)) & 0x0f0f0f0fu;
-  x = (x | (x >> 4)) & 0x00ff00ffu;
-  x = (x | (x >> 8)) & 0x0000ffffu;
-  return x;
-}
 
 // --------------------------------------------------------------- updates --
 // Tick batching: within a tick the most recent update of an object wins.
@@ -377,13 +369,21 @@ __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uin
 
 // The leaf table is sized for the worst case of the smallest threshold, so
 // this never fires; if it did, the tick is flagged and no traversal runs.
-__global__ void k_tree_done(Ctl *ctl, uint32_t lcap, uint32_t tcap) {
+// Start-table level: about four levels below the depth of a uniform tree
+// with th objects per leaf for the capacity n_cap, within [4, 12], the
+// allocated level tcap and the deepest leaf.
+__global__ void k_tree_done(Ctl *ctl, uint32_t lcap, uint32_t tcap, uint32_t n_cap) {
   if (!ctl->rebuild) return;
   if (ctl->n_leaves > lcap) {
     ctl->n_leaves = lcap;
     ctl->err |= kErrOvfTree;
   }
-  ctl->tlev = ctl->l_deep < tcap ? ctl->l_deep : tcap;
+  const uint64_t per = (uint64_t)n_cap / ((uint64_t)ctl->th_cur + 1u);
+  uint32_t lu = 0;
+  for (uint64_t c = 1; c < per; c *= 4u) ++lu;
+  uint32_t t = lu + 4u > 12u ? 12u : lu + 4u;
+  t = t < tcap ? t : tcap;
+  ctl->tlev = ctl->l_deep < t ? ctl->l_deep : t;
 }
 
 __device__ __forceinline__ uint32_t open_level(uint32_t s) {
@@ -787,17 +787,6 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
 // set writes its object id at the subquery's offset plus the number of set
 // bits below it (coalesced, no atomics, no bitmap in memory).
 
-// Area fraction of leaf `leaf` covered by rectangle r (timing-log feature).
-__device__ __forceinline__ float overlap_frac(const Ctl *ctl, const uint32_t *lstart,
-                                              const uint32_t *llevel, uint32_t leaf, float4 r) {
-  const uint32_t st = lstart[leaf], l = llevel[leaf];
-  const float inv = 1.0f / ctl->scale, size = (float)(1u << (kFine - l)) * inv;
-  const float x0 = ctl->x0 + (float)compact16(st) * inv, y0 = ctl->y0 + (float)compact16(st >> 1) * inv;
-  const float w = fminf(r.z, x0 + size) - fmaxf(r.x, x0);
-  const float h = fminf(r.w, y0 + size) - fmaxf(r.y, y0);
-  return (w > 0.0f && h > 0.0f) ? fminf(1.0f, (w / size) * (h / size)) : 0.0f;
-}
-
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint32_t *tasks,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
@@ -1089,7 +1078,7 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
            (const uint4 *)B.front[(l - 1) & 1], B.front[l & 1], B.FCAP, B.lstart, B.llevel,
            B.LCAP);
   }
-  LAUNCH(k_tree_done, 1, 1, s, B.ctl, B.LCAP, B.tcap);
+  LAUNCH(k_tree_done, 1, 1, s, B.ctl, B.LCAP, B.tcap, B.N);
   radix_sort_pairs(B.lstart, B.llevel, B.lstart2, B.llevel2, &B.ctl->n_leaves, &B.ctl->rebuild,
                    B.hist, B.tot, 0, 32, s);
   LAUNCH(k_nodes_open, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,

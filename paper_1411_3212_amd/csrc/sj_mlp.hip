@@ -2,11 +2,6 @@
 // FP32 arithmetic, predicting the join time of a quadtree leaf (natural log
 // of microseconds) from (log2(1 + objects), log2(1 + intersecting
 // subqueries), level / 16, mean overlap of the subqueries with the leaf).
-//
-// Parameter layout (kMlpParams floats / bf16 values):
-//   W1 [64][4]   at 0      b1 [64] at 256
-//   W2 [64][64]  at 320    b2 [64] at 4416   (row i = hidden unit i)
-//   w3 [64]      at 4480   b3      at 4544
 // Training keeps FP32 master parameters; the forward and backward passes use
 // their BF16 rounding (round to nearest even) and the gradient with respect
 // to the rounded values updates the masters (Adam).
@@ -15,22 +10,10 @@
 
 #include "sj.h"
 #include "sj_device.h"
+#include "sj_mlp.h"
 #include "sj_scene.h"
 
 namespace sj {
-
-constexpr int kH = 64, kF = 4;
-constexpr int kOW1 = 0, kOB1 = 256, kOW2 = 320, kOB2 = 4416, kOW3 = 4480, kOB3 = 4544;
-constexpr int kMlpParams = 4545;
-
-__device__ __forceinline__ float bf2f(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
-
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
 
 __global__ void k_mlp_round(const float *master, uint16_t *w, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)

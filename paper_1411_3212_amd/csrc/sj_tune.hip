@@ -1,0 +1,169 @@
+// Threshold tuner: picks the leaf threshold of a quadtree build with the
+// learned cost model.  For every candidate threshold it builds the quadtree
+// (Algorithm 1) on the tick's sorted codes, splits the tick's queries
+// against it, and predicts the cost of the tick's filtering and decoding
+// from the terms of their complexity (Computational Complexity section,
+// filtering and decoding equations): per active leaf c, the MLP predicts the
+// join time of |P^c| objects against |Q_I^c| intersecting subqueries; the
+// split and the leaf passes add terms linear in |Q_I|, |Q_C| and the number
+// of leaves.  The cheapest candidate is then built for the tick.  The paper
+// fixes the threshold by hand after a sweep (Experimental evaluation, S5);
+// this replaces the sweep, and the results of a tick do not depend on it.
+//
+// Everything runs on the device, with a launch sequence that depends only on
+// the number of candidates, so a tuning tick can be captured in a graph.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "sj_device.h"
+#include "sj_kernels.h"
+#include "sj_mlp.h"
+
+namespace sj {
+
+// Clean state for one build at threshold th: the tick's errors as they were
+// before the trial builds, an empty frontier holding the root.
+__device__ void reset_build(Ctl *ctl, const TuneState *ts, uint4 *front0, uint32_t th) {
+  ctl->err = ts->err_saved;
+  ctl->th_cur = th;
+  for (int l = 0; l < kFine + 2; ++l) ctl->fcount[l] = 0;
+  ctl->fcount[0] = 1;
+  ctl->n_leaves = 0;
+  ctl->l_deep = 0;
+  ctl->go_split = 0;
+  ctl->n_isect = ctl->n_cov = 0;
+  ctl->n32[0] = ctl->n32[1] = 0;
+  front0[0] = make_uint4(0u, 0u, ctl->n_present, 0u);
+}
+
+__global__ void k_tune_begin(Ctl *ctl, TuneState *ts) {
+  ts->err_saved = ctl->err;
+  ts->th_before = ctl->th_cur;
+}
+
+__global__ void k_tune_set(Ctl *ctl, const TuneState *ts, uint32_t c, uint4 *front0) {
+  reset_build(ctl, ts, front0, ts->cand[c]);
+}
+
+// Per-block partial of sum over active leaves of exp(MLP(features)).  One
+// wave per leaf: lanes average the overlap of the leaf's intersecting
+// subqueries, then lane j computes hidden unit j of both layers (the first
+// layer's outputs are broadcast lane by lane) and a wave sum gives the
+// output.  Parameters are staged in LDS as FP32 (W2 rows padded to 65).
+__global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const TuneState *ts,
+                                                        const uint32_t *leaf_beg,
+                                                        const uint32_t *leaf_sqoff,
+                                                        const uint32_t *sq_q, const float4 *qrect,
+                                                        const uint32_t *lstart,
+                                                        const uint32_t *llevel, uint64_t *red) {
+  __shared__ float sW2[kH][kH + 1];
+  __shared__ float sW1[kH][kF], sB1[kH], sB2[kH], sW3[kH];
+  __shared__ double sacc[kWavesPerBlock];
+  for (int i = threadIdx.x; i < kH * kH; i += kBlock) sW2[i / kH][i % kH] = bf2f(ts->w[kOW2 + i]);
+  for (int i = threadIdx.x; i < kH * kF; i += kBlock) sW1[i / kF][i % kF] = bf2f(ts->w[kOW1 + i]);
+  if (threadIdx.x < kH) {
+    sB1[threadIdx.x] = bf2f(ts->w[kOB1 + threadIdx.x]);
+    sB2[threadIdx.x] = bf2f(ts->w[kOB2 + threadIdx.x]);
+    sW3[threadIdx.x] = bf2f(ts->w[kOW3 + threadIdx.x]);
+  }
+  __syncthreads();
+  const float b3 = bf2f(ts->w[kOB3]);
+  const uint32_t lane = lane_id();
+  double acc = 0.0;
+  if (ctl->go_split) {
+    const uint32_t n = ctl->n_leaves;
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t w0 =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+    for (uint32_t t = w0; t < n; t += nwaves) {
+      const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
+      const uint32_t sb = leaf_sqoff[t], se = leaf_sqoff[t + 1];
+      if (cnt == 0 || sb == se) continue;
+      float ov = 0.0f;
+      for (uint32_t i = sb + lane; i < se; i += kWave)
+        ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq_q[i]]);
+      ov = wave_sum(ov) / (float)(se - sb);
+      const float x0 = log2f(1.0f + (float)cnt), x1 = log2f(1.0f + (float)(se - sb));
+      const float x2 = (float)llevel[t] * (1.0f / 16.0f);
+      float a = sB1[lane];
+      a = fmaf(sW1[lane][0], x0, a);
+      a = fmaf(sW1[lane][1], x1, a);
+      a = fmaf(sW1[lane][2], x2, a);
+      a = fmaf(sW1[lane][3], ov, a);
+      const float h1 = a > 0.0f ? a : 0.0f;
+      float a2 = sB2[lane];
+      for (int j = 0; j < kH; ++j) a2 = fmaf(sW2[lane][j], readlane_f(h1, j), a2);
+      const float h2 = a2 > 0.0f ? a2 : 0.0f;
+      const float y = wave_sum(sW3[lane] * h2) + b3;
+      acc += (double)expf(y);
+    }
+  }
+  if (lane == 0) sacc[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) s += sacc[w];
+    red[kRedCost * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(s);
+  }
+}
+
+// Predicted cost of candidate c (one block of kChunkBlocks threads): the
+// MLP sum plus the linear terms; infinite when the candidate overflowed a
+// capacity.
+__global__ void __launch_bounds__(kChunkBlocks) k_tune_cost(const Ctl *ctl, TuneState *ts,
+                                                            uint32_t c, const uint64_t *red) {
+  __shared__ double lds[kChunkBlocks / kWave];
+  double v = __longlong_as_double((long long)red[kRedCost * kChunkBlocks + threadIdx.x]);
+  v = wave_sum(v);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int w = 0; w < kChunkBlocks / kWave; ++w) s += lds[w];
+  const bool ok = ctl->go_split && !(ctl->err & kErrOverflow);
+  const double cost = (double)ts->coef[0] * s + (double)ts->coef[1] * (double)ctl->n_isect +
+                      (double)ts->coef[2] * (double)ctl->n_cov +
+                      (double)ts->coef[3] * (double)ctl->n_leaves;
+  ts->cost[c] = ok ? (float)cost : INFINITY;
+  ts->msum[c] = (float)s;
+}
+
+// Cheapest candidate (the first of equal costs; the threshold before the
+// tuning when none is feasible), then a clean state for its build.
+__global__ void k_tune_pick(Ctl *ctl, TuneState *ts, uint4 *front0) {
+  uint32_t best = ts->th_before;
+  float bc = INFINITY;
+  for (uint32_t c = 0; c < ts->n_cand && c < (uint32_t)kMaxCand; ++c) {
+    if (ts->cost[c] < bc) {
+      bc = ts->cost[c];
+      best = ts->cand[c];
+    }
+  }
+  ts->chosen = best;
+  ts->n_tunes += 1;
+  ts->tuned_tick = ctl->tick;
+  reset_build(ctl, ts, front0, best);
+}
+
+#define LAUNCH(k, g, b, s, ...) hipLaunchKernelGGL(k, dim3(g), dim3(b), 0, s, __VA_ARGS__)
+
+void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
+                 const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,
+                 uint32_t covering, hipStream_t s) {
+  LAUNCH(k_tune_begin, 1, 1, s, B.ctl, B.tune);
+  for (uint32_t c = 0; c < n_cand; ++c) {
+    LAUNCH(k_tune_set, 1, 1, s, B.ctl, (const TuneState *)B.tune, c, B.front[0]);
+    launch_build(B, l_max, s);
+    launch_leaves(B, s);
+    launch_split(B, qid, xa, ya, xb, yb, nq, covering, s);
+    LAUNCH(k_cost_leaves, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
+           (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
+           (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.red);
+    LAUNCH(k_tune_cost, 1, kChunkBlocks, s, (const Ctl *)B.ctl, B.tune, c,
+           (const uint64_t *)B.red);
+  }
+  LAUNCH(k_tune_pick, 1, 1, s, B.ctl, B.tune, B.front[0]);
+}
+
+}  // namespace sj
