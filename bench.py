@@ -8,8 +8,9 @@ every tick are generated up front and resident in HBM before timing starts.
 
 Prints one JSON line: result pairs/s (value), ticks/s, p50/p99 tick latency,
 the roofline figure of the dominant kernel (measured with HIP events on the
-scene's stream inside the timed region) and the CPU oracle's throughput on a
-bounded sample of the same workload.
+scene's stream inside the timed region), the CPU oracle's throughput on a
+bounded sample of the same workload, and the same ticks run again with the
+learned leaf threshold (cost model) beside the fixed one.
 """
 from __future__ import annotations
 
@@ -42,18 +43,10 @@ WORKLOAD_TEXT = {
 def scene_config(wl: workloads.Workload, th: int = 64) -> dict:
     """Capacities sized for a workload (subqueries, covering entries and
     result ids per tick, with headroom)."""
-    rate = float(wl.params.get("query_rate", 0.1 if wl.params.get("kind") == "hotspot" else 0.5))
-    q = max(1, int(round(rate * wl.n)))
-    kind = wl.params.get("kind", wl.name)
-    if kind == "hotspot":
-        per_q = dict(sub=48, cov=48, res=512) if wl.n <= 2_000_000 else dict(sub=160, cov=160,
-                                                                              res=2048)
-    elif kind == "segments":
-        per_q = dict(sub=16, cov=16, res=96)
-    else:
-        per_q = dict(sub=32, cov=32, res=256)
-    return dict(th=th, capacity_subqueries=per_q["sub"] * q, capacity_covering=per_q["cov"] * q,
-                capacity_results=per_q["res"] * q)
+    from paper_1411_3212_amd.serving import scene_capacities
+    c = scene_capacities(wl, th)
+    c.pop("nq")
+    return c
 
 
 def parse():
@@ -71,6 +64,8 @@ def parse():
                          "replays as one captured graph; eager: one launch per kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the run with the learned threshold")
     return ap.parse_args()
 
 
@@ -140,6 +135,59 @@ def cpu_baseline(wl, target_s: float):
             "sample": f"brute force (Definition 1), tick 0, {n} of {t.nq} queries sampled "
                       f"uniformly against all {wl.n} objects; {pairs} pairs in {dt:.2f} s; "
                       f"{n / dt:.1f} queries/s"}
+
+
+MODEL = os.path.join(ROOT, "paper_1411_3212_amd", "data", "cost_model.json")
+
+
+def learned_run(args, wl, ticks, slot, nq, cfg, c_fixed, lat_fixed, wall_fixed, torch) -> dict:
+    """The timed ticks again on a scene whose builds choose their threshold
+    with the learned cost model (same loop, same launch mode)."""
+    from paper_1411_3212_amd import costmodel
+    from paper_1411_3212_amd.binding import Scene
+    model = costmodel.load(MODEL)
+    kw = {k: v for k, v in cfg.items() if k != "th"}
+    sc = Scene(wl.n, nq, th=args.th, th_min=min(model["cand"]), thresh_mlp=True, **kw)
+    costmodel.install(sc, model, torch)
+    counters = torch.zeros((args.warmup + args.steps, 8), dtype=torch.int64, device="cuda")
+    lat = []
+    for i in range(args.warmup + args.steps):
+        if i == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        buf, m, q = ticks[i]
+        h0 = time.perf_counter()
+        if args.mode == "graph":
+            slot[:buf.numel()].copy_(buf)
+            d = views(slot, m, q, torch)
+            sc.tick_graph(*(d[f] for f in FIELDS))
+        else:
+            d = views(buf, m, q, torch)
+            sc.apply_updates(d["ids"], d["x"], d["y"])
+            sc.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
+        sc.counters_into(counters[i])
+        sc.fetch()
+        if i >= args.warmup:
+            lat.append((time.perf_counter() - h0) * 1e3)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c = counters.cpu().numpy()[args.warmup:]
+    info = sc.tune_info()
+    K = args.steps
+    pairs = int(c[:, 0].sum())
+    learned = dict(ticks_per_s=K / wall, ms_per_step=wall * 1e3 / K, pairs_per_s=pairs / wall,
+                   p50_tick_ms=float(np.percentile(lat, 50)),
+                   p99_tick_ms=float(np.percentile(lat, 99)), th_last=sc.stats()["th"],
+                   tunings=info["n_tunes"], chosen=info["chosen"],
+                   predicted_cost=dict(zip(map(str, info["cand"]), info["cost"])))
+    fixed = dict(ticks_per_s=K / wall_fixed, ms_per_step=wall_fixed * 1e3 / K,
+                 p50_tick_ms=float(np.percentile(lat_fixed, 50)),
+                 p99_tick_ms=float(np.percentile(lat_fixed, 99)), th=args.th)
+    return dict(fixed=fixed, learned=learned,
+                speedup=learned["ticks_per_s"] / fixed["ticks_per_s"],
+                p99_ratio=learned["p99_tick_ms"] / fixed["p99_tick_ms"],
+                same_pairs_every_tick=bool(np.array_equal(c[:, 0], c_fixed[:, 0])),
+                model="paper_1411_3212_amd/data/cost_model.json")
 
 
 def main():
@@ -253,6 +301,9 @@ def main():
                      "avg_launch_ms": avg[dom]},
         "input_generation_s": t_gen,
     }
+    if not args.no_learned and os.path.exists(MODEL):
+        out["learned_vs_fixed"] = learned_run(args, wl, ticks, slot, nq, cfg, c, lat, wall,
+                                              torch)
     if args.copy_probe:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

@@ -262,15 +262,18 @@ int sj_stats(sj_scene *scene, sj_tick_stats *out);
  * candidate threshold, predicts
  *   cost = coef[0] * sum over active leaves c of exp(MLP(f_c))
  *        + coef[1] |Q_I| + coef[2] |Q_C| + coef[3] * leaves
+ *        + coef[4] * max over active leaves c of exp(MLP(f_c))
  * with f_c = (log2(1 + |P^c|), log2(1 + |Q_I^c|), level / 16, mean over the
  * intersecting subqueries of c of the fraction of c's area they cover), and
  * builds the cheapest (the first of equal costs; a candidate that overflows
  * a capacity is infeasible; with none feasible the threshold is kept).
+ * The sum is the join's work and the maximum its critical path, since one
+ * wave joins a leaf.
  * Results do not depend on it.
  * d_w: sj_mlp_param_count() BF16 parameters (device, copied); cand: n_cand
  * (1..8) thresholds, each >= th_min.  Synchronises the scene's stream.
  * Errors: SJ_EINVAL (null pointers, bad n_cand or a candidate below th_min). */
-int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[4],
+int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[5],
                       const uint32_t *cand, uint32_t n_cand);
 
 typedef struct sj_tune_info {
@@ -278,6 +281,7 @@ typedef struct sj_tune_info {
   uint32_t cand[8];
   float cost[8];        /* predicted cost per candidate (inf: infeasible) */
   float mlp_sum[8];     /* sum over active leaves of exp(MLP) */
+  float mlp_max[8];     /* largest exp(MLP) of an active leaf */
   uint32_t chosen;      /* threshold of the last tuning */
   uint32_t n_tunes;     /* tunings so far */
   uint32_t tuned_tick;  /* ticks completed before the last tuning */

@@ -11,10 +11,11 @@ exp(MLP(f_c)) with
            mean over the intersecting subqueries of c of the fraction of the
            area of c that their rectangle covers),
 
-plus terms linear in |Q_I|, |Q_C| and the number of leaves:
+plus terms linear in |Q_I|, |Q_C|, the number of leaves and the largest
+prediction (the join's critical path: one wave joins a leaf):
 
     cost = coef[0] sum_c exp(MLP(f_c)) + coef[1] |Q_I| + coef[2] |Q_C|
-           + coef[3] leaves.
+           + coef[3] leaves + coef[4] max_c exp(MLP(f_c)).
 
 Leaves without objects are inactive and hold no subqueries.  Float64
 throughout; shares no code with the HIP kernels.
@@ -73,10 +74,12 @@ def candidate_terms(live, rects, fr, leaves: oracle.Leaves):
 
 
 def cost(params, coef, feats, n_isect, n_cov, n_leaves):
-    """Predicted cost from the features and counts (params: the BF16-rounded
-    MLP parameters as values)."""
-    s = float(np.exp(mlp.forward(params, feats)).sum()) if len(feats) else 0.0
-    return (coef[0] * s + coef[1] * n_isect + coef[2] * n_cov + coef[3] * n_leaves), s
+    """Predicted cost and the sum of the predictions from the features and
+    counts (params: the BF16-rounded MLP parameters as values)."""
+    e = np.exp(mlp.forward(params, feats)) if len(feats) else np.zeros(1)
+    s, m = float(e.sum()), float(e.max())
+    return (coef[0] * s + coef[1] * n_isect + coef[2] * n_cov + coef[3] * n_leaves +
+            coef[4] * m), s
 
 
 def choose(st: oracle.State, live, rects, params, coef, cand, l_max: int = 16,

@@ -68,7 +68,8 @@ class SjTimingView(Structure):
 
 class SjTuneInfo(Structure):
     _fields_ = [("n_cand", c_uint32), ("cand", c_uint32 * 8), ("cost", c_float * 8),
-                ("mlp_sum", c_float * 8), ("chosen", c_uint32), ("n_tunes", c_uint32),
+                ("mlp_sum", c_float * 8), ("mlp_max", c_float * 8), ("chosen", c_uint32),
+                ("n_tunes", c_uint32),
                 ("tuned_tick", c_uint32)]
 
 
@@ -361,11 +362,12 @@ class Scene:
 
     def set_cost_model(self, w, coef, cand):
         """Installs the cost model: w = BF16 parameters (int16/uint16 device
-        tensor of sj_mlp_param_count() values, copied), coef = 4 floats,
+        tensor of sj_mlp_param_count() values, copied), coef = 5 floats,
         cand = candidate thresholds (1..8, each >= th_min)."""
         import torch
         assert w.is_cuda and w.dtype in (torch.int16, torch.uint16) and w.is_contiguous()
-        cf = (c_float * 4)(*[float(v) for v in coef])
+        assert len(coef) == 5
+        cf = (c_float * 5)(*[float(v) for v in coef])
         cd = (c_uint32 * len(cand))(*[int(v) for v in cand])
         _check(self._lib.sj_set_cost_model(self.handle, _ptr(w), cf, cd, len(cand)), self.handle)
 
@@ -374,6 +376,7 @@ class Scene:
         _check(self._lib.sj_tune_info_get(self.handle, byref(t)), self.handle)
         n = int(t.n_cand)
         return dict(cand=list(t.cand[:n]), cost=list(t.cost[:n]), mlp_sum=list(t.mlp_sum[:n]),
+                    mlp_max=list(t.mlp_max[:n]),
                     chosen=int(t.chosen), n_tunes=int(t.n_tunes), tuned_tick=int(t.tuned_tick))
 
     def timing_log(self):

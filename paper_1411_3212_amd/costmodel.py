@@ -1,0 +1,371 @@
+"""Learned cost model of the leaf threshold: data, training and evaluation.
+
+The paper fixes the leaf threshold th_quad by hand after a sweep
+(Experimental evaluation, S5).  Here a small network predicts the join time
+of a quadtree leaf from (log2(1 + objects), log2(1 + intersecting
+subqueries), level / 16, mean overlap of the subqueries with the leaf), and
+the library's threshold tuner (SJ_THRESH_MLP) adds terms linear in the
+subqueries and leaves (the complexity terms of the Computational Complexity
+section) to choose the cheapest candidate threshold when it builds.
+
+    python -m paper_1411_3212_amd.costmodel train [--out FILE]
+        logs per-leaf join timings (SJ_TIMING_LOG) of hotspot (1M objects)
+        and segment (4M objects) ticks at every candidate threshold, trains
+        the network on the GPU with the library's forward, gradient and Adam
+        kernels, fits the linear terms on the measured tick phases, and
+        writes the model as JSON.
+    python -m paper_1411_3212_amd.costmodel compare [--workload NAME]
+        runs the same ticks with the fixed threshold and with the learned
+        one (graph launches) and prints ticks/s, p50/p99 tick latency and
+        whether every tick's result set is the same.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+from . import binding, serving, workloads
+from .binding import PHASES, Scene
+
+CAND = (32, 64, 128, 256, 512, 1024)
+MODEL_PATH = Path(__file__).resolve().parent / "data" / "cost_model.json"
+# tick phases whose time depends on the threshold (the build is amortised
+# over the rebuild period and left out)
+COST_PHASES = ("leaves", "split", "schedule", "join_count", "join_scan", "join_write")
+TRAIN_SETS = (("hotspot", 20), ("segments", 20))  # 2 x 6 thresholds x 17 logged ticks
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def leaf_samples(rec: np.ndarray, mhz: float):
+    """Features and measured join time (microseconds, count + write pass) of
+    the active leaves of one tick's timing log (rows of 8 floats)."""
+    cnt, nsq = rec[:, 0], rec[:, 1]
+    a = (cnt > 0) & (nsq > 0)
+    X = np.stack([np.log2(np.float32(1) + cnt[a]), np.log2(np.float32(1) + nsq[a]),
+                  rec[a, 2] * np.float32(1 / 16), rec[a, 3]], axis=1).astype(np.float32)
+    us = (rec[a, 4].astype(np.float64) + rec[a, 5]) / mhz
+    return X, us
+
+
+def collect(name: str, n_ticks: int, cand=CAND, warm: int = 3, torch=None, log=print) -> list:
+    """One record per logged tick of every candidate threshold: features,
+    measured leaf times, counts and phase times (eager, profiled)."""
+    wl = workloads.make(name, n_ticks=n_ticks)
+    ticks = serving.pack_ticks(wl, torch)
+    caps = serving.scene_capacities(wl)
+    nq = max(q for _, _, q in ticks)
+    rows = []
+    for th in cand:
+        sc = Scene(wl.n, nq, th=th, timing_log=True, profile=True,
+                   capacity_subqueries=caps["capacity_subqueries"],
+                   capacity_covering=caps["capacity_covering"],
+                   capacity_results=caps["capacity_results"])
+        for i, (buf, m, q) in enumerate(ticks):
+            ids, x, y, qid, xa, ya, xb, yb = serving.tick_views(buf, m, q, torch)
+            sc.apply_updates(ids, x, y)
+            sc.run_tick(qid, xa, ya, xb, yb)
+            s = sc.stats()
+            if i < warm:
+                continue
+            rec, mhz = sc.timing_log()
+            X, us = leaf_samples(rec.cpu().numpy(), mhz)
+            ph = sc.phase_times()
+            rows.append(dict(wl=name, th=th, tick=i, X=X, us=us, n_isect=s["n_isect"],
+                             n_cov=s["n_cov"], n_leaves=s["n_leaves"], rebuilt=s["rebuilt"],
+                             phase_ms={k: ph[k] for k in PHASES}))
+        log(f"collected {name} th={th}: {len(ticks) - warm} ticks, "
+            f"{sum(len(r['us']) for r in rows if r['th'] == th and r['wl'] == name)} leaves")
+        sc.close()
+    del ticks
+    torch.cuda.empty_cache()
+    return rows
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He initialisation of the FP32 master parameters (biases zero)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.zeros(4545, np.float32)
+    p[0:256] = rng.normal(0, math.sqrt(2 / 4), 256)        # W1
+    p[320:4416] = rng.normal(0, math.sqrt(2 / 64), 4096)   # W2
+    p[4480:4544] = rng.normal(0, math.sqrt(1 / 64), 64)    # w3
+    return p
+
+
+class Trainer:
+    """FP32 master parameters, Adam moments and the BF16 copy on the device;
+    every step runs the library's gradient and Adam kernels."""
+
+    def __init__(self, torch, seed: int = 0, batch: int = 65536):
+        self.torch, self.lib = torch, binding.load()
+        self.P = int(self.lib.sj_mlp_param_count())
+        dev = "cuda"
+        self.master = torch.from_numpy(init_params(seed)).to(dev)
+        self.m = torch.zeros(self.P, device=dev)
+        self.v = torch.zeros(self.P, device=dev)
+        self.w = torch.empty(self.P, dtype=torch.int16, device=dev)
+        self.g = torch.empty(self.P + 1, device=dev)
+        self.nb = int(self.lib.sj_mlp_scratch_bytes(batch))
+        self.scratch = torch.empty(self.nb, dtype=torch.uint8, device=dev)
+        self.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self.steps = 0
+        self._ok(self.lib.sj_mlp_round(_ptr(self.master), _ptr(self.w), self.stream))
+
+    def _ok(self, rc):
+        if rc != 0:
+            raise RuntimeError(f"MLP call failed ({rc}): {self.lib.sj_last_error(None).decode()}")
+
+    def step(self, X, T, lr: float) -> None:
+        n = X.shape[0]
+        self.steps += 1
+        self._ok(self.lib.sj_mlp_grad(_ptr(self.w), _ptr(X), _ptr(T), n, _ptr(self.g),
+                                      _ptr(self.scratch), self.nb, self.stream))
+        self._ok(self.lib.sj_mlp_adam(_ptr(self.master), _ptr(self.g), _ptr(self.m), _ptr(self.v),
+                                      _ptr(self.w), self.steps, ctypes.c_float(lr), self.stream))
+
+    def loss(self, X, T) -> float:
+        """Mean squared error of the current BF16 network on (X, T)."""
+        self._ok(self.lib.sj_mlp_grad(_ptr(self.w), _ptr(X), _ptr(T), X.shape[0], _ptr(self.g),
+                                      _ptr(self.scratch), self.nb, self.stream))
+        return float(self.g[-1].item())
+
+    def predict(self, X):
+        y = self.torch.empty(X.shape[0], dtype=self.torch.float32, device="cuda")
+        if X.shape[0]:
+            self._ok(self.lib.sj_mlp_forward(_ptr(self.w), _ptr(X), X.shape[0], _ptr(y),
+                                             self.stream))
+        return y
+
+    def bits(self) -> np.ndarray:
+        return self.w.cpu().numpy().view(np.uint16).copy()
+
+
+def train(rows: list, torch, steps: int = 3000, batch: int = 65536, lr: float = 3e-3,
+          max_samples: int = 2_000_000, seed: int = 0, log=print) -> tuple:
+    """Trains on the rows' leaves (ticks with index % 6 == 5 held out):
+    minibatch Adam on ln(microseconds), cosine learning-rate decay."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    val = [r for r in rows if r["tick"] % 6 == 5]
+    trn = [r for r in rows if r["tick"] % 6 != 5]
+
+    def stack(rs):
+        X = np.concatenate([r["X"] for r in rs])
+        T = np.log(np.maximum(np.concatenate([r["us"] for r in rs]), 0.02)).astype(np.float32)
+        return X, T
+
+    Xt, Tt = stack(trn)
+    Xv, Tv = stack(val)
+    if len(Tt) > max_samples:
+        pick = rng.choice(len(Tt), max_samples, replace=False)
+        Xt, Tt = Xt[pick], Tt[pick]
+    tr = Trainer(torch, seed=seed, batch=batch)
+    dXv, dTv = torch.from_numpy(Xv).cuda(), torch.from_numpy(Tv).cuda()
+    n = len(Tt)
+    nbatch = max(1, n // batch)
+    t0 = time.perf_counter()
+    k = 0
+    history = []
+    while k < steps:
+        perm = rng.permutation(n)
+        dX = torch.from_numpy(Xt[perm]).cuda()
+        dT = torch.from_numpy(Tt[perm]).cuda()
+        for b in range(nbatch):
+            if k >= steps:
+                break
+            lo, hi = b * batch, min(n, (b + 1) * batch)
+            cur = lr * (0.02 + 0.98 * 0.5 * (1 + math.cos(math.pi * k / steps)))
+            tr.step(dX[lo:hi], dT[lo:hi], cur)
+            k += 1
+            if k % 500 == 0 or k == steps:
+                history.append((k, tr.loss(dXv, dTv)))
+                log(f"step {k}: validation MSE {history[-1][1]:.4f}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    yv = tr.predict(dXv).cpu().numpy().astype(np.float64)
+    res = yv - Tv
+    stats = dict(train_samples=int(n), val_samples=int(len(Tv)), steps=steps, batch=batch,
+                 seconds=round(secs, 2), val_mse=float(np.mean(res ** 2)),
+                 val_r2=float(1 - np.mean(res ** 2) / np.var(Tv)),
+                 val_median_abs_ln_error=float(np.median(np.abs(res))), history=history)
+    return tr, stats
+
+
+def fit_terms(rows: list, tr: Trainer, torch) -> tuple:
+    """Non-negative least squares of the threshold-dependent phase time of a
+    tick (microseconds) on [sum exp(prediction), |Q_I|, |Q_C|, leaves,
+    max exp(prediction)] plus one intercept per workload (constants do not
+    move the argmin).  The sum is the join's work, the maximum its critical
+    path (one wave per leaf); a linear fit of both stands for the makespan."""
+    from scipy.optimize import nnls
+    names = sorted({r["wl"] for r in rows})
+    A, b = [], []
+    for r in rows:
+        y = tr.predict(torch.from_numpy(r["X"]).cuda()).cpu().numpy().astype(np.float64)
+        e = np.exp(y) if len(y) else np.zeros(1)
+        r["msum"], r["mmax"] = float(e.sum()), float(e.max())
+        A.append([r["msum"], r["n_isect"], r["n_cov"], r["n_leaves"], r["mmax"]] +
+                 [1.0 if r["wl"] == nm else 0.0 for nm in names])
+        b.append(1e3 * sum(r["phase_ms"][k] for k in COST_PHASES))
+    A, b = np.array(A), np.array(b)
+    scale = np.maximum(np.abs(A).max(axis=0), 1e-30)
+    x, _ = nnls(A / scale, b)
+    x = x / scale
+    pred = A @ x
+    r2 = float(1 - np.sum((b - pred) ** 2) / np.sum((b - b.mean()) ** 2))
+    # per workload: measured mean time per threshold and the threshold the
+    # fitted cost picks on average
+    per = {}
+    for nm in names:
+        meas, cost = {}, {}
+        for th in sorted({r["th"] for r in rows}):
+            sel = [i for i, r in enumerate(rows) if r["wl"] == nm and r["th"] == th]
+            meas[th] = float(b[sel].mean())
+            cost[th] = float((A[sel, :5] @ x[:5]).mean())
+        per[nm] = dict(measured_us=meas, predicted_us=cost,
+                       best_measured=min(meas, key=meas.get), best_predicted=min(cost, key=cost.get))
+    return [float(v) for v in x[:5]], dict(r2=r2, intercepts=dict(zip(names, map(float, x[5:]))),
+                                           per_workload=per)
+
+
+def save(path: Path, bits: np.ndarray, coef, cand, info: dict) -> None:
+    path.parent.mkdir(parents=True, exist_ok=True)
+    doc = dict(format=1, params_bf16=[int(v) for v in bits], coef=list(coef), cand=list(cand),
+               features="log2(1+objects), log2(1+intersecting subqueries), level/16, "
+                        "mean overlap fraction of the subqueries with the leaf",
+               target="ln microseconds of the leaf's join (count + write pass, one wave)",
+               cost="coef0*sum exp(mlp) + coef1*|Q_I| + coef2*|Q_C| + coef3*leaves "
+                    "+ coef4*max exp(mlp) (microseconds of the threshold-dependent tick "
+                    "phases)",
+               training=info)
+    path.write_text(json.dumps(doc, indent=1) + "\n")
+
+
+def load(path: Path = MODEL_PATH) -> dict:
+    doc = json.loads(Path(path).read_text())
+    bits = np.array(doc["params_bf16"], np.uint16)
+    if len(bits) != 4545:
+        raise ValueError(f"{path}: expected 4545 parameters, found {len(bits)}")
+    return dict(bits=bits, coef=[float(v) for v in doc["coef"]],
+                cand=[int(v) for v in doc["cand"]], doc=doc)
+
+
+def install(scene: Scene, model: dict, torch) -> None:
+    w = torch.from_numpy(model["bits"].view(np.int16).copy()).cuda()
+    scene.set_cost_model(w, model["coef"], model["cand"])
+
+
+def run_ticks(scene: Scene, ticks: list, torch, warm: int, hashes: bool = True) -> dict:
+    """Graph-launched ticks; per-tick latency (launch to results on the host)
+    of the ticks after warm, and each tick's (count, hash) per query.  The
+    first tick (the build, its tuning and the graph capture) is reported
+    apart."""
+    slot = torch.empty(max(b.numel() for b, _, _ in ticks), dtype=torch.int32, device="cuda")
+    lat, pairs, digests, ths = [], 0, [], []
+    torch.cuda.synchronize()
+    first = None
+    for i, (buf, m, q) in enumerate(ticks):
+        h0 = time.perf_counter()
+        slot[:buf.numel()].copy_(buf)
+        scene.tick_graph(*serving.tick_views(slot, m, q, torch))
+        r = scene.fetch()
+        h1 = time.perf_counter()
+        if i == 0:
+            first = (h1 - h0) * 1e3
+        if i >= warm:
+            lat.append((h1 - h0) * 1e3)
+            pairs += r.total_pairs
+        s = scene.stats()
+        ths.append(s["th"])
+        if hashes:
+            c, h = scene.hashes()
+            digests.append((c.cpu().numpy().tobytes(), h.cpu().numpy().tobytes()))
+    wall = 1e-3 * sum(lat)  # ticks run back to back; checks between them are not counted
+    k = len(ticks) - warm
+    return dict(ticks_per_s=k / wall, ms_per_tick=1e3 * wall / k, first_tick_ms=first,
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                pairs_per_s=pairs / wall, th=ths, digests=digests)
+
+
+def compare(name: str, n_ticks: int, warm: int, torch, model: dict, th_fixed: int = 64,
+            tune_every: int = 0, log=print, **overrides) -> dict:
+    """The same ticks with the fixed threshold and with the learned one."""
+    wl = workloads.make(name, n_ticks=n_ticks, **overrides)
+    ticks = serving.pack_ticks(wl, torch)
+    caps = serving.scene_capacities(wl)
+    nq = max(q for _, _, q in ticks)
+    kw = dict(capacity_subqueries=caps["capacity_subqueries"],
+              capacity_covering=caps["capacity_covering"],
+              capacity_results=caps["capacity_results"])
+    out = dict(workload=name, objects=wl.n, queries_per_tick=nq, ticks=n_ticks - warm)
+    fixed = Scene(wl.n, nq, th=th_fixed, **kw)
+    out["fixed"] = run_ticks(fixed, ticks, torch, warm)
+    fixed.close()
+    del fixed
+    torch.cuda.empty_cache()
+    log(f"{name}: fixed th={th_fixed} {out['fixed']['ms_per_tick']:.3f} ms/tick")
+    learned = Scene(wl.n, nq, th=th_fixed, th_min=min(model["cand"]), thresh_mlp=True,
+                    tune_every=tune_every, **kw)
+    install(learned, model, torch)
+    out["learned"] = run_ticks(learned, ticks, torch, warm)
+    info = learned.tune_info()
+    learned.close()
+    del learned
+    log(f"{name}: learned {out['learned']['ms_per_tick']:.3f} ms/tick, th {sorted(set(out['learned']['th']))}")
+    out["identical_results"] = out["fixed"].pop("digests") == out["learned"].pop("digests")
+    out["fixed"]["th"] = sorted(set(out["fixed"]["th"]))
+    out["learned"]["th"] = sorted(set(out["learned"]["th"]))
+    out["learned"]["tunings"] = info["n_tunes"]
+    out["learned"]["last_costs"] = dict(zip(info["cand"], info["cost"]))
+    out["speedup_ticks_per_s"] = out["learned"]["ticks_per_s"] / out["fixed"]["ticks_per_s"]
+    out["p99_ratio"] = out["learned"]["p99_ms"] / out["fixed"]["p99_ms"]
+    del ticks
+    torch.cuda.empty_cache()
+    return out
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", default=str(MODEL_PATH))
+    t.add_argument("--steps", type=int, default=3000)
+    t.add_argument("--seed", type=int, default=0)
+    c = sub.add_parser("compare")
+    c.add_argument("--workload", default="hotspot", choices=sorted(workloads.WORKLOADS))
+    c.add_argument("--ticks", type=int, default=60)
+    c.add_argument("--warmup", type=int, default=8)
+    c.add_argument("--model", default=str(MODEL_PATH))
+    args = ap.parse_args(argv)
+    import torch
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.cmd == "train":
+        rows = []
+        for name, n in TRAIN_SETS:
+            rows += collect(name, n, torch=torch, log=log)
+        tr, stats = train(rows, torch, steps=args.steps, seed=args.seed, log=log)
+        coef, fit = fit_terms(rows, tr, torch)
+        info = dict(logged_ticks=len(rows), sets=[f"{n}:{k}" for n, k in TRAIN_SETS],
+                    network=stats, terms=fit)
+        save(Path(args.out), tr.bits(), coef, CAND, info)
+        print(json.dumps(dict(coef=coef, logged_ticks=len(rows), val_r2=stats["val_r2"],
+                              terms_r2=fit["r2"], per_workload={
+                                  k: (v["best_measured"], v["best_predicted"])
+                                  for k, v in fit["per_workload"].items()})))
+        return 0
+    model = load(Path(args.model))
+    out = compare(args.workload, args.ticks + args.warmup, args.warmup, torch, model, log=log)
+    print(json.dumps(out))
+    return 0 if out["identical_results"] else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -668,7 +668,7 @@ int sj_phase_times(sj_scene *s, float *ms, int n) {
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipEventElapsedTime");
 }
 
-int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[4], const uint32_t *cand,
+int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[5], const uint32_t *cand,
                       uint32_t n_cand) {
   if (!s || !d_w || !coef || !cand) return SJ_EINVAL;
   if (n_cand == 0 || n_cand > (uint32_t)sj::kMaxCand)
@@ -678,14 +678,14 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[4], con
     if (cand[c] < th_min || cand[c] == 0)
       return fail(s, SJ_EINVAL, "set_cost_model: candidate below th_min");
   struct {
-    float coef[4];
+    float coef[5];
     uint32_t n_cand;
     uint32_t cand[sj::kMaxCand];
   } h{};
-  for (int i = 0; i < 4; ++i) h.coef[i] = coef[i];
+  for (int i = 0; i < 5; ++i) h.coef[i] = coef[i];
   h.n_cand = n_cand;
   for (uint32_t c = 0; c < n_cand; ++c) h.cand[c] = cand[c];
-  static_assert(offsetof(sj::TuneState, n_cand) == offsetof(sj::TuneState, coef) + 16, "layout");
+  static_assert(offsetof(sj::TuneState, n_cand) == offsetof(sj::TuneState, coef) + 20, "layout");
   static_assert(offsetof(sj::TuneState, cand) == offsetof(sj::TuneState, n_cand) + 4, "layout");
   sj::TuneState *ts = s->B.tune;
   hipError_t e = hipMemcpyAsync(ts->w, d_w, 4545 * sizeof(uint16_t), hipMemcpyDeviceToDevice,
@@ -719,6 +719,7 @@ int sj_tune_info_get(sj_scene *s, sj_tune_info *out) {
     out->cand[c] = h.cand[c];
     out->cost[c] = h.cost[c];
     out->mlp_sum[c] = h.msum[c];
+    out->mlp_max[c] = h.mmax[c];
   }
   out->chosen = h.chosen;
   out->n_tunes = h.n_tunes;

@@ -62,7 +62,7 @@ struct Ctl {
 // Slots of the per-block partial reductions (red[slot * kChunkBlocks + b]).
 enum : int {
   kRedMinX = 0, kRedMinY, kRedMaxX, kRedMaxY, kRedOutside,
-  kRedCovPairs, kRedTests, kRedMaxLeaf, kRedTasks, kRedCost, kRedSlots
+  kRedCovPairs, kRedTests, kRedMaxLeaf, kRedTasks, kRedCost, kRedCostMax, kRedSlots
 };
 
 __device__ __forceinline__ uint32_t fenc(float f) {
@@ -261,11 +261,13 @@ __device__ __forceinline__ float overlap_frac(const Ctl *ctl, const uint32_t *ls
 constexpr int kMaxCand = 8;
 struct TuneState {
   uint16_t w[4548];          // BF16 MLP parameters (4545 used)
-  float coef[4];             // cost = c0 * sum exp(mlp) + c1 |Q_I| + c2 |Q_C| + c3 leaves
+  float coef[5];             // cost = c0 * sum exp(mlp) + c1 |Q_I| + c2 |Q_C| + c3 leaves
+                             //        + c4 * max exp(mlp)
   uint32_t n_cand;
   uint32_t cand[kMaxCand];   // candidate thresholds
   float cost[kMaxCand];      // predicted cost per candidate (inf: infeasible)
   float msum[kMaxCand];      // sum over active leaves of exp(mlp) per candidate
+  float mmax[kMaxCand];      // largest exp(mlp) of an active leaf per candidate
   uint32_t err_saved;        // tick errors before the trial builds
   uint32_t th_before;        // threshold before the tuning
   uint32_t chosen, n_tunes, tuned_tick;

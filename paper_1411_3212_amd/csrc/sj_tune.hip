@@ -5,10 +5,12 @@
 // from the terms of their complexity (Computational Complexity section,
 // filtering and decoding equations): per active leaf c, the MLP predicts the
 // join time of |P^c| objects against |Q_I^c| intersecting subqueries; the
-// split and the leaf passes add terms linear in |Q_I|, |Q_C| and the number
-// of leaves.  The cheapest candidate is then built for the tick.  The paper
-// fixes the threshold by hand after a sweep (Experimental evaluation, S5);
-// this replaces the sweep, and the results of a tick do not depend on it.
+// sum over leaves is the join's work, the largest one its critical path (one
+// wave joins a leaf); the split and the leaf passes add terms linear in
+// |Q_I|, |Q_C| and the number of leaves.  The cheapest candidate is then
+// built for the tick.  The paper fixes the threshold by hand after a sweep
+// (Experimental evaluation, S5); this replaces the sweep, and the results
+// of a tick do not depend on it.
 //
 // Everything runs on the device, with a launch sequence that depends only on
 // the number of candidates, so a tuning tick can be captured in a graph.
@@ -46,11 +48,12 @@ __global__ void k_tune_set(Ctl *ctl, const TuneState *ts, uint32_t c, uint4 *fro
   reset_build(ctl, ts, front0, ts->cand[c]);
 }
 
-// Per-block partial of sum over active leaves of exp(MLP(features)).  One
-// wave per leaf: lanes average the overlap of the leaf's intersecting
-// subqueries, then lane j computes hidden unit j of both layers (the first
-// layer's outputs are broadcast lane by lane) and a wave sum gives the
-// output.  Parameters are staged in LDS as FP32 (W2 rows padded to 65).
+// Per-block partials of the sum and the maximum over active leaves of
+// exp(MLP(features)).  One wave per leaf: lanes average the overlap of the
+// leaf's intersecting subqueries, then lane j computes hidden unit j of both
+// layers (the first layer's outputs are broadcast lane by lane) and a wave
+// sum gives the output.  Parameters are staged in LDS as FP32 (W2 rows
+// padded to 65).
 __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const TuneState *ts,
                                                         const uint32_t *leaf_beg,
                                                         const uint32_t *leaf_sqoff,
@@ -59,7 +62,7 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
                                                         const uint32_t *llevel, uint64_t *red) {
   __shared__ float sW2[kH][kH + 1];
   __shared__ float sW1[kH][kF], sB1[kH], sB2[kH], sW3[kH];
-  __shared__ double sacc[kWavesPerBlock];
+  __shared__ double sacc[kWavesPerBlock], smax[kWavesPerBlock];
   for (int i = threadIdx.x; i < kH * kH; i += kBlock) sW2[i / kH][i % kH] = bf2f(ts->w[kOW2 + i]);
   for (int i = threadIdx.x; i < kH * kF; i += kBlock) sW1[i / kF][i % kF] = bf2f(ts->w[kOW1 + i]);
   if (threadIdx.x < kH) {
@@ -70,7 +73,7 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
   __syncthreads();
   const float b3 = bf2f(ts->w[kOB3]);
   const uint32_t lane = lane_id();
-  double acc = 0.0;
+  double acc = 0.0, mx = 0.0;
   if (ctl->go_split) {
     const uint32_t n = ctl->n_leaves;
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
@@ -96,37 +99,55 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
       for (int j = 0; j < kH; ++j) a2 = fmaf(sW2[lane][j], readlane_f(h1, j), a2);
       const float h2 = a2 > 0.0f ? a2 : 0.0f;
       const float y = wave_sum(sW3[lane] * h2) + b3;
-      acc += (double)expf(y);
+      const double e = (double)expf(y);
+      acc += e;
+      mx = e > mx ? e : mx;
     }
   }
-  if (lane == 0) sacc[threadIdx.x / kWave] = acc;
+  if (lane == 0) {
+    sacc[threadIdx.x / kWave] = acc;
+    smax[threadIdx.x / kWave] = mx;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < kWavesPerBlock; ++w) s += sacc[w];
+    double s = 0.0, m = 0.0;
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      s += sacc[w];
+      m = smax[w] > m ? smax[w] : m;
+    }
     red[kRedCost * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(s);
+    red[kRedCostMax * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(m);
   }
 }
 
 // Predicted cost of candidate c (one block of kChunkBlocks threads): the
-// MLP sum plus the linear terms; infinite when the candidate overflowed a
-// capacity.
+// MLP sum and maximum plus the linear terms; infinite when the candidate
+// overflowed a capacity.
 __global__ void __launch_bounds__(kChunkBlocks) k_tune_cost(const Ctl *ctl, TuneState *ts,
                                                             uint32_t c, const uint64_t *red) {
-  __shared__ double lds[kChunkBlocks / kWave];
+  __shared__ double lds[kChunkBlocks / kWave], ldm[kChunkBlocks / kWave];
   double v = __longlong_as_double((long long)red[kRedCost * kChunkBlocks + threadIdx.x]);
+  double u = __longlong_as_double((long long)red[kRedCostMax * kChunkBlocks + threadIdx.x]);
   v = wave_sum(v);
-  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  u = wave_max(u);
+  if (lane_id() == 0) {
+    lds[threadIdx.x / kWave] = v;
+    ldm[threadIdx.x / kWave] = u;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int w = 0; w < kChunkBlocks / kWave; ++w) s += lds[w];
+  double s = 0.0, m = 0.0;
+  for (int w = 0; w < kChunkBlocks / kWave; ++w) {
+    s += lds[w];
+    m = ldm[w] > m ? ldm[w] : m;
+  }
   const bool ok = ctl->go_split && !(ctl->err & kErrOverflow);
   const double cost = (double)ts->coef[0] * s + (double)ts->coef[1] * (double)ctl->n_isect +
                       (double)ts->coef[2] * (double)ctl->n_cov +
-                      (double)ts->coef[3] * (double)ctl->n_leaves;
+                      (double)ts->coef[3] * (double)ctl->n_leaves + (double)ts->coef[4] * m;
   ts->cost[c] = ok ? (float)cost : INFINITY;
   ts->msum[c] = (float)s;
+  ts->mmax[c] = (float)m;
 }
 
 // Cheapest candidate (the first of equal costs; the threshold before the

@@ -45,7 +45,11 @@ def scene_capacities(wl: workloads.Workload, th: int = 64) -> dict:
     kind = wl.params.get("kind", wl.name)
     rate = float(wl.params.get("query_rate", 0.1 if kind == "hotspot" else 0.5))
     q = max(1, int(round(rate * wl.n)))
-    per = dict(sub=48, cov=48, res=512) if kind == "hotspot" else dict(sub=16, cov=16, res=96)
+    if kind == "hotspot":  # denser hotspots hold more leaves and results per query
+        per = dict(sub=48, cov=48, res=512) if wl.n <= 2_000_000 else \
+            dict(sub=160, cov=160, res=2048)
+    else:
+        per = dict(sub=16, cov=16, res=96)
     return dict(nq=q, th=th, capacity_subqueries=per["sub"] * q,
                 capacity_covering=per["cov"] * q, capacity_results=per["res"] * q)
 
@@ -68,19 +72,24 @@ def make_specs(n_scenes: int = 16, seed: int = 5, nmin: float = 1e5, nmax: float
     return specs
 
 
+def pack_ticks(wl: workloads.Workload, torch) -> list:
+    """Every tick of a workload in a packed device buffer [ids x y | qid xa
+    ya xb yb] (4-byte words): a list of (buffer, updates, queries)."""
+    out = []
+    for t in wl.ticks():
+        host = np.concatenate([t.ids.view(np.int32), t.x.view(np.int32), t.y.view(np.int32),
+                               t.qid.view(np.int32), t.xa.view(np.int32), t.ya.view(np.int32),
+                               t.xb.view(np.int32), t.yb.view(np.int32)])
+        out.append((torch.from_numpy(host).cuda(), len(t.ids), t.nq))
+    torch.cuda.synchronize()
+    return out
+
+
 def upload(specs: list, n_ticks: int, torch) -> None:
-    """Generates n_ticks ticks per scene into packed device buffers
-    [ids x y | qid xa ya xb yb] (4-byte words)."""
+    """Generates n_ticks ticks per scene into packed device buffers."""
     for sp in specs:
         sp.wl.n_ticks = n_ticks
-        sp.ticks = []
-        for t in sp.wl.ticks():
-            host = np.concatenate([t.ids.view(np.int32), t.x.view(np.int32), t.y.view(np.int32),
-                                   t.qid.view(np.int32), t.xa.view(np.int32),
-                                   t.ya.view(np.int32), t.xb.view(np.int32),
-                                   t.yb.view(np.int32)])
-            sp.ticks.append((torch.from_numpy(host).cuda(), len(t.ids), t.nq))
-    torch.cuda.synchronize()
+        sp.ticks = pack_ticks(sp.wl, torch)
 
 
 def tick_views(buf, m, nq, torch):

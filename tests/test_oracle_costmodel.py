@@ -68,9 +68,9 @@ def test_cost_of_a_constant_network(k):
     st, live, rects = hand_scene()
     p = np.zeros(mlp.P)
     p[-1] = np.log(k)
-    coef = (2.0, 3.0, 5.0, 7.0)
+    coef = (2.0, 3.0, 5.0, 7.0, 11.0)
     costs, sums, chosen = costmodel.choose(st, live, rects, p, coef, [8, 2])
     # th 2: the hand scene; th 8: the same tree, since the root is always split
     assert np.allclose(sums, 3 * k)
-    assert np.allclose(costs, 2 * 3 * k + 3 * 3 + 5 * 0 + 7 * 4)
+    assert np.allclose(costs, 2 * 3 * k + 3 * 3 + 5 * 0 + 7 * 4 + 11 * k)
     assert chosen == 8  # the first of equal costs
