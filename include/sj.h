@@ -72,8 +72,12 @@ enum sj_flags {
                             objects (Section "Optimizations") */
   SJ_PROFILE = 1u << 2,  /* record per-phase device times (sj_phase_times) */
   SJ_TIMING_LOG = 1u << 3, /* per-leaf join timing log (sj_timing_log) */
-  SJ_THRESH_MLP = 1u << 4  /* builds pick their threshold with the cost
+  SJ_THRESH_MLP = 1u << 4, /* builds pick their threshold with the cost
                               model installed by sj_set_cost_model */
+  SJ_SCHEDULE_MLP = 1u << 5 /* with SJ_REORDER and a cost model installed:
+                              join tasks run in the order of the model's
+                              predicted task time instead of the weight
+                              |Q_I^c| x |P^c| (learned schedule) */
 };
 
 /* Quadtree reuse across ticks (the paper builds the partitioning on the
@@ -262,13 +266,15 @@ int sj_stats(sj_scene *scene, sj_tick_stats *out);
  * candidate threshold, predicts
  *   cost = coef[0] * sum over active leaves c of exp(MLP(f_c))
  *        + coef[1] |Q_I| + coef[2] |Q_C| + coef[3] * leaves
- *        + coef[4] * max over active leaves c of exp(MLP(f_c))
+ *        + coef[4] * max over active leaves c of exp(MLP(f'_c))
  * with f_c = (log2(1 + |P^c|), log2(1 + |Q_I^c|), level / 16, mean over the
- * intersecting subqueries of c of the fraction of c's area they cover), and
+ * intersecting subqueries of c of the fraction of c's area they cover), f'_c
+ * = f_c with |Q_I^c| capped at 64 (a join task takes at most 64 subqueries
+ * of a leaf), and
  * builds the cheapest (the first of equal costs; a candidate that overflows
  * a capacity is infeasible; with none feasible the threshold is kept).
  * The sum is the join's work and the maximum its critical path, since one
- * wave joins a leaf.
+ * wave runs a join task.
  * Results do not depend on it.
  * d_w: sj_mlp_param_count() BF16 parameters (device, copied); cand: n_cand
  * (1..8) thresholds, each >= th_min.  Synchronises the scene's stream.
@@ -318,12 +324,15 @@ typedef struct sj_index_view {
   uint32_t n_present, n_leaves, l_deep;
   float x0, y0;
   int32_t e;                 /* frame side is 2^e */
-  const uint32_t *d_codes;   /* [n_present] */
+  const uint32_t *d_codes;   /* [n_present] sort keys: level-16 Morton codes
+                                after a tick that built the quadtree, leaf
+                                indices after one that kept it */
   const uint32_t *d_ids;     /* [n_present] */
   const uint32_t *d_leaf_start; /* [n_leaves] */
   const uint32_t *d_leaf_level; /* [n_leaves] */
   const uint32_t *d_leaf_beg;   /* [n_leaves + 1] */
-  const float *d_px, *d_py;     /* positions by id (NaN: no position) */
+  const float *d_pos;           /* [capacity_objects][2]: (x, y) by id (NaN: no
+                                   position) */
 } sj_index_view;
 
 int sj_index_view_get(sj_scene *scene, sj_index_view *out);

@@ -11,11 +11,13 @@ exp(MLP(f_c)) with
            mean over the intersecting subqueries of c of the fraction of the
            area of c that their rectangle covers),
 
-plus terms linear in |Q_I|, |Q_C|, the number of leaves and the largest
-prediction (the join's critical path: one wave joins a leaf):
+plus terms linear in |Q_I|, |Q_C|, the number of leaves, and the largest
+prediction for one join task (the join's critical path: one wave joins at
+most 64 intersecting subqueries of a leaf; f'_c is f_c with |Q_I^c| capped
+at 64):
 
     cost = coef[0] sum_c exp(MLP(f_c)) + coef[1] |Q_I| + coef[2] |Q_C|
-           + coef[3] leaves + coef[4] max_c exp(MLP(f_c)).
+           + coef[3] leaves + coef[4] max_c exp(MLP(f'_c)).
 
 Leaves without objects are inactive and hold no subqueries.  Float64
 throughout; shares no code with the HIP kernels.
@@ -26,6 +28,8 @@ import numpy as np
 
 import oracle
 from oracle import mlp
+
+TASK_SUB = 64  # intersecting subqueries of a leaf joined by one task
 
 
 def leaf_geometry(fr, leaves: oracle.Leaves):
@@ -76,8 +80,13 @@ def candidate_terms(live, rects, fr, leaves: oracle.Leaves):
 def cost(params, coef, feats, n_isect, n_cov, n_leaves):
     """Predicted cost and the sum of the predictions from the features and
     counts (params: the BF16-rounded MLP parameters as values)."""
-    e = np.exp(mlp.forward(params, feats)) if len(feats) else np.zeros(1)
-    s, m = float(e.sum()), float(e.max())
+    if len(feats):
+        e = np.exp(mlp.forward(params, feats))
+        capped = feats.copy()
+        capped[:, 1] = np.minimum(capped[:, 1], np.log2(1.0 + TASK_SUB))
+        s, m = float(e.sum()), float(np.exp(mlp.forward(params, capped)).max())
+    else:
+        s, m = 0.0, 0.0
     return (coef[0] * s + coef[1] * n_isect + coef[2] * n_cov + coef[3] * n_leaves +
             coef[4] * m), s
 

@@ -17,7 +17,8 @@ import numpy as np
 LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
 
 SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG, SJ_THRESH_MLP = 1, 2, 4, 8, 16
+SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG, SJ_THRESH_MLP, SJ_SCHEDULE_MLP = \
+    1, 2, 4, 8, 16, 32
 REBUILD = {"auto": 0, "always": 1, "never": 2}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
           "join_write"]
@@ -58,8 +59,7 @@ class SjIndexView(Structure):
     _fields_ = [("n_present", c_uint32), ("n_leaves", c_uint32), ("l_deep", c_uint32),
                 ("x0", c_float), ("y0", c_float), ("e", c_int32),
                 ("d_codes", c_void_p), ("d_ids", c_void_p), ("d_leaf_start", c_void_p),
-                ("d_leaf_level", c_void_p), ("d_leaf_beg", c_void_p), ("d_px", c_void_p),
-                ("d_py", c_void_p)]
+                ("d_leaf_level", c_void_p), ("d_leaf_beg", c_void_p), ("d_pos", c_void_p)]
 
 
 class SjTimingView(Structure):
@@ -159,10 +159,10 @@ def make_config(capacity_objects: int, capacity_queries: int, *, th: int = 64, t
                 rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                 capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
                 profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
-                tune_every: int = 0) -> SjConfig:
+                schedule_mlp: bool = False, tune_every: int = 0) -> SjConfig:
     flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
             (SJ_PROFILE if profile else 0) | (SJ_TIMING_LOG if timing_log else 0) | \
-            (SJ_THRESH_MLP if thresh_mlp else 0)
+            (SJ_THRESH_MLP if thresh_mlp else 0) | (SJ_SCHEDULE_MLP if schedule_mlp else 0)
     return SjConfig(capacity_objects, capacity_queries, capacity_subqueries, capacity_covering,
                     capacity_results, th, th_min, l_max, flags, REBUILD[rebuild], rebuild_period,
                     split_slots, tune_every)
@@ -220,7 +220,7 @@ class Scene:
                  rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                  capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
                  profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
-                 tune_every: int = 0, device=None, stream=None):
+                 schedule_mlp: bool = False, tune_every: int = 0, device=None, stream=None):
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
@@ -231,7 +231,7 @@ class Scene:
                                capacity_covering=capacity_covering,
                                capacity_results=capacity_results, split_slots=split_slots,
                                profile=profile, timing_log=timing_log, thresh_mlp=thresh_mlp,
-                               tune_every=tune_every)
+                               schedule_mlp=schedule_mlp, tune_every=tune_every)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")
@@ -401,8 +401,8 @@ class Scene:
                     leaf_start=self._view(v.d_leaf_start, L, torch.int32),
                     leaf_level=self._view(v.d_leaf_level, L, torch.int32),
                     leaf_beg=self._view(v.d_leaf_beg, L + 1, torch.int32),
-                    px=self._view(v.d_px, self.cfg.capacity_objects, torch.float32),
-                    py=self._view(v.d_py, self.cfg.capacity_objects, torch.float32))
+                    pos=self._view(v.d_pos, 2 * self.cfg.capacity_objects,
+                                   torch.float32).view(-1, 2))
 
 
 class Server:

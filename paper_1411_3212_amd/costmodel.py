@@ -296,8 +296,9 @@ def run_ticks(scene: Scene, ticks: list, torch, warm: int, hashes: bool = True) 
 
 
 def compare(name: str, n_ticks: int, warm: int, torch, model: dict, th_fixed: int = 64,
-            tune_every: int = 0, log=print, **overrides) -> dict:
-    """The same ticks with the fixed threshold and with the learned one."""
+            tune_every: int = 0, schedule: bool = False, log=print, **overrides) -> dict:
+    """The same ticks with the fixed threshold and with the learned one (and,
+    with schedule, the learned threshold plus the learned task order)."""
     wl = workloads.make(name, n_ticks=n_ticks, **overrides)
     ticks = serving.pack_ticks(wl, torch)
     caps = serving.scene_capacities(wl)
@@ -320,6 +321,20 @@ def compare(name: str, n_ticks: int, warm: int, torch, model: dict, th_fixed: in
     learned.close()
     del learned
     log(f"{name}: learned {out['learned']['ms_per_tick']:.3f} ms/tick, th {sorted(set(out['learned']['th']))}")
+    if schedule:
+        sch = Scene(wl.n, nq, th=th_fixed, th_min=min(model["cand"]), thresh_mlp=True,
+                    schedule_mlp=True, tune_every=tune_every, **kw)
+        install(sch, model, torch)
+        out["learned_schedule"] = run_ticks(sch, ticks, torch, warm)
+        sch.close()
+        del sch
+        d = out["learned_schedule"].pop("digests")
+        out["learned_schedule"]["th"] = sorted(set(out["learned_schedule"]["th"]))
+        out["learned_schedule"]["identical_results"] = d == out["fixed"]["digests"]
+        out["learned_schedule"]["speedup_ticks_per_s"] = (
+            out["learned_schedule"]["ticks_per_s"] / out["fixed"]["ticks_per_s"])
+        log(f"{name}: learned threshold + schedule "
+            f"{out['learned_schedule']['ms_per_tick']:.3f} ms/tick")
     out["identical_results"] = out["fixed"].pop("digests") == out["learned"].pop("digests")
     out["fixed"]["th"] = sorted(set(out["fixed"]["th"]))
     out["learned"]["th"] = sorted(set(out["learned"]["th"]))
@@ -344,6 +359,8 @@ def main(argv=None) -> int:
     c.add_argument("--ticks", type=int, default=60)
     c.add_argument("--warmup", type=int, default=8)
     c.add_argument("--model", default=str(MODEL_PATH))
+    c.add_argument("--schedule", action="store_true",
+                   help="also run the learned threshold with the learned task order")
     args = ap.parse_args(argv)
     import torch
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
@@ -362,7 +379,8 @@ def main(argv=None) -> int:
                                   for k, v in fit["per_workload"].items()})))
         return 0
     model = load(Path(args.model))
-    out = compare(args.workload, args.ticks + args.warmup, args.warmup, torch, model, log=log)
+    out = compare(args.workload, args.ticks + args.warmup, args.warmup, torch, model,
+                  schedule=args.schedule, log=log)
     print(json.dumps(out))
     return 0 if out["identical_results"] else 1
 

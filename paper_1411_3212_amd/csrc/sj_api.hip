@@ -156,8 +156,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   Bufs b{};
   const uint64_t N = d.N, Q = d.Q, L = d.LCAP;
   b.ctl = c.take<Ctl>(1);
-  b.px = c.take<float>(N);
-  b.py = c.take<float>(N);
+  b.pos = c.take<float2>(N);
   b.ustamp = c.take<uint64_t>(N);
   b.qstamp = c.take<uint64_t>(N);
   b.keyA = c.take<uint32_t>(N);
@@ -183,10 +182,15 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.leaf_beg = c.take<uint32_t>(L + 1);
   b.leaf_nsq = c.take<uint32_t>(L);
   b.leaf_sqoff = c.take<uint32_t>(L + 1);
-  b.tasks = c.take<uint32_t>(L);
-  b.tkey = c.take<uint32_t>(L);
-  b.tasks2 = c.take<uint32_t>(L);
-  b.tkey2 = c.take<uint32_t>(L);
+  // join tasks: one per leaf and one per further kTaskSub subqueries of a leaf
+  const uint64_t T = (uint64_t)L + d.S / sj::kTaskSub + 1u;
+  b.tasks = c.take<uint32_t>(T);
+  b.tkey = c.take<uint32_t>(T);
+  b.tasks2 = c.take<uint32_t>(T);
+  b.tkey2 = c.take<uint32_t>(T);
+  b.vtask = c.take<uint2>(T - L);
+  b.xbase = c.take<uint32_t>(L);
+  b.TCAP = (uint32_t)T;
   b.qrect = c.take<float4>(Q);
   b.q_ni = c.take<uint32_t>(Q);
   b.q_nc = c.take<uint32_t>(Q);
@@ -318,7 +322,9 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
   rec(3);
   sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   rec(4);
-  const uint32_t *tasks = sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, st);
+  const bool learned = (flags & SJ_SCHEDULE_MLP) && s->cm_set;
+  const uint32_t *tasks =
+      sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, learned, st);
   rec(5);
   sj::launch_join_count(s->B, tasks, st);
   rec(6);
@@ -395,8 +401,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
     }
   }
   sj::launch_ctl_init(s->B.ctl, d.th, stream);
-  sj::launch_fill_u32((uint32_t *)s->B.px, d.N, 0x7fc00000u, stream);  // NaN: no position
-  sj::launch_fill_u32((uint32_t *)s->B.py, d.N, 0x7fc00000u, stream);
+  sj::launch_fill_u32((uint32_t *)s->B.pos, 2ull * d.N, 0x7fc00000u, stream);  // NaN: no position
   sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
   sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
   sj::launch_fill_u32((uint32_t *)s->B.tune, sizeof(sj::TuneState) / 4, 0u, stream);
@@ -698,8 +703,8 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[5], con
   s->n_cand = n_cand;
   s->tuned = false;
   s->since_tune = 0;
-  GraphSlot &g = s->graphs[3];  // captured with the previous candidate count
-  if (g.valid) {
+  for (GraphSlot &g : s->graphs) {  // captured with the previous model state
+    if (!g.valid) continue;
     (void)hipGraphExecDestroy(g.exec);
     if (s->prof) (void)hipGraphExecDestroy(g.exec2);
     g.valid = false;
@@ -758,8 +763,7 @@ int sj_index_view_get(sj_scene *s, sj_index_view *out) {
   out->d_leaf_start = s->B.lstart;
   out->d_leaf_level = s->B.llevel;
   out->d_leaf_beg = s->B.leaf_beg;
-  out->d_px = s->B.px;
-  out->d_py = s->B.py;
+  out->d_pos = (const float *)s->B.pos;
   return SJ_OK;
 }
 

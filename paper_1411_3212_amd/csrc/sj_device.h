@@ -14,6 +14,7 @@ constexpr int kFine = 16;                 // bits per axis of the finest grid
 constexpr uint32_t kLeafBit = 0x80000000u; // child reference: leaf index
 constexpr int kSortItems = 8;             // keys per thread per sort tile
 constexpr int kSortTile = kBlock * kSortItems;
+constexpr uint32_t kTaskSub = 64;         // intersecting subqueries per join task
 
 // Error bits latched on the device.
 enum : uint32_t {
@@ -41,6 +42,7 @@ struct Ctl {
   uint32_t th_next;       // threshold requested for the next build (0: keep)
   uint32_t force;         // build requested by the host
   uint32_t rebuild;       // the current tick builds the quadtree
+  uint32_t sort_skip;     // radix passes from this shift on only copy (keys are below 2^it)
   uint32_t want_rebuild;  // automatic policy: build on the next tick
   uint32_t since_build;   // ticks since the last build
   uint32_t tick;
@@ -48,7 +50,8 @@ struct Ctl {
   uint32_t n_outside;     // present objects outside the frame
   uint32_t n_leaves, l_deep, tlev;
   uint32_t fcount[kFine + 2];  // frontier sizes per level of the build
-  uint32_t n_tasks;
+  uint32_t n_tasks;       // leaves with join work
+  uint32_t n_entries;     // join tasks: one per leaf + one per further kTaskSub subqueries
   uint32_t max_leaf;
   uint32_t err_upd;       // errors of updates since the last tick
   uint32_t err;           // errors of the current tick (includes err_upd)

@@ -30,8 +30,8 @@ void mscan_down(const ScanJobs &jobs, int njobs, const uint64_t *part, const uin
 // v.  hist: 256 * kChunkBlocks u32, tot: 256 u32.  Skipped when *gate == 0.
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, const uint32_t *gate, uint32_t *hist, uint32_t *tot,
-                      int bit_begin, int bit_end, hipStream_t s, const float *gx = nullptr,
-                      const float *gy = nullptr, float2 *gout = nullptr);
+                      int bit_begin, int bit_end, hipStream_t s, const float2 *gpos = nullptr,
+                      float2 *gout = nullptr, const uint32_t *skip = nullptr);
 
 inline unsigned grid_for(uint64_t n, unsigned cap = 2048) {
   uint64_t g = (n + 255) / 256;

@@ -17,7 +17,7 @@ constexpr unsigned kJoinBlocks = 4096;  // 16384 waves for the join passes
 struct Bufs {
   Ctl *ctl;
   // objects (by id) and per-tick sorted arrays
-  float *px, *py;
+  float2 *pos;                          // position by id (NaN x: no position)
   uint64_t *ustamp, *qstamp;
   uint32_t *keyA, *valA, *keyB, *valB;  // sorted (code, id) end in A
   float2 *sxy;                          // positions in sorted order
@@ -33,7 +33,9 @@ struct Bufs {
   uint32_t *table;                      // start table (4^tcap entries)
   uint32_t *leaf_beg, *leaf_nsq, *leaf_sqoff;
   // schedule
-  uint32_t *tasks, *tkey, *tasks2, *tkey2;
+  uint32_t *tasks, *tkey, *tasks2, *tkey2;  // join tasks (TCAP)
+  uint2 *vtask;                         // further chunks of heavy leaves: (leaf, chunk)
+  uint32_t *xbase;                      // per leaf: task index of its second chunk
   // queries and subqueries
   float4 *qrect;
   uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;
@@ -45,7 +47,7 @@ struct Bufs {
   float *tlog;                          // per-leaf timing log (or null)
   TuneState *tune;                      // threshold tuner state
   // capacities
-  uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap;
+  uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap, TCAP;
   uint64_t S, C, R;
 };
 
@@ -62,7 +64,10 @@ void launch_leaves(const Bufs &B, hipStream_t s);
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s);
-const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, hipStream_t s);
+const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
+                                hipStream_t s);
+// Task keys from the cost model's predicted task times (learned schedule).
+void launch_schedule_mlp(const Bufs &B, hipStream_t s);
 void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s);
 void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
                       hipStream_t s);

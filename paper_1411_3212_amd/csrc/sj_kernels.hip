@@ -30,6 +30,33 @@ constexpr uint32_t kTableScanMax = 1024;  // queries over more table cells start
 constexpr uint32_t kLeafIdxBits = 27;
 constexpr uint32_t kLeafIdxMask = (1u << kLeafIdxBits) - 1u;
 
+// The quadtree as the traversals see it: node table (4 child references,
+// kLeafBit marks a leaf), start table at level tlev, leaf starts and levels.
+struct Tree {
+  const uint4 *nodes;
+  const uint32_t *table;
+  const uint32_t *lstart, *llevel;
+  uint32_t tlev;
+};
+
+// Leaf containing the finest-level code `code`: its start-table cell gives
+// the leaf, or the internal node at level tlev to descend from (one child
+// reference per level, at most kFine - tlev of them).
+__device__ __forceinline__ uint32_t leaf_of(const Tree &tr, uint32_t code) {
+  const uint32_t T = tr.tlev;
+  const uint32_t e = tr.table[code >> (2u * (kFine - T))];
+  if (e & kLeafBit) return e & kLeafIdxMask;
+  uint32_t node = e;
+  for (uint32_t k = T; k < (uint32_t)kFine; ++k) {
+    const uint32_t q = (code >> (2u * (kFine - k - 1u))) & 3u;
+    const uint4 nd = tr.nodes[node];
+    const uint32_t r = q == 0u ? nd.x : q == 1u ? nd.y : q == 2u ? nd.z : nd.w;
+    if (r & kLeafBit) return r & ~kLeafBit;
+    node = r;
+  }
+  return 0u;  // not reached: every level-16 cell lies in a leaf
+}
+
 // ------------------------------------------------------------- utilities --
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -91,14 +118,11 @@ __global__ void __launch_bounds__(kBlock) k_upd_stamp(const uint32_t *id, const 
 __global__ void __launch_bounds__(kBlock) k_upd_write(const uint32_t *id, const float *x,
                                                       const float *y, uint32_t m, uint32_t N,
                                                       uint64_t seq_off, const uint64_t *stamp,
-                                                      const Ctl *ctl, float *px, float *py) {
+                                                      const Ctl *ctl, float2 *pos) {
   const uint64_t seq = ctl->upd_seq + seq_off;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < m; k += gridDim.x * kBlock) {
     const uint32_t o = id[k];
-    if (o < N && stamp[o] == seq + k + 1) {
-      px[o] = x[k];
-      py[o] = y[k];
-    }
+    if (o < N && stamp[o] == seq + k + 1) pos[o] = make_float2(x[k], y[k]);
   }
 }
 
@@ -106,8 +130,8 @@ __global__ void __launch_bounds__(kBlock) k_upd_write(const uint32_t *id, const 
 
 // Per block of ids: present count (position not NaN), MBR and number of
 // present objects outside the current frame, as partials.
-__global__ void __launch_bounds__(kBlock) k_mbr(const float *px, const float *py, uint32_t N,
-                                                const Ctl *ctl, uint32_t *blk, uint64_t *red) {
+__global__ void __launch_bounds__(kBlock) k_mbr(const float2 *pos, uint32_t N, const Ctl *ctl,
+                                                uint32_t *blk, uint64_t *red) {
   __shared__ float s_mnx[kWavesPerBlock], s_mny[kWavesPerBlock], s_mxx[kWavesPerBlock],
       s_mxy[kWavesPerBlock];
   __shared__ uint32_t s_cnt[kWavesPerBlock], s_out[kWavesPerBlock];
@@ -119,9 +143,9 @@ __global__ void __launch_bounds__(kBlock) k_mbr(const float *px, const float *py
   float mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
   uint32_t cnt = 0, out = 0;
   for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
-    const float xv = px[i];
+    const float2 p = pos[i];
+    const float xv = p.x, yv = p.y;
     if (xv == xv) {
-      const float yv = py[i];
       ++cnt;
       mnx = fminf(mnx, xv);
       mxx = fmaxf(mxx, xv);
@@ -238,8 +262,14 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   ctl->rebuild = r ? 1u : 0u;
   if (!r) {
     ctl->since_build += 1;
+    // leaf keys are below n_leaves: digits from the first zero one on are
+    // passes that only copy
+    const uint32_t nl = ctl->n_leaves;
+    const uint32_t bits = nl > 1u ? 32u - (uint32_t)__clz((int)(nl - 1u)) : 0u;
+    ctl->sort_skip = (bits + 7u) / 8u * 8u;
     return;
   }
+  ctl->sort_skip = 32u;
   if (ctl->th_next) ctl->th_cur = ctl->th_next;
   ctl->th_next = 0;
   ctl->force = 0;
@@ -264,10 +294,13 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   front0[0] = make_uint4(0u, 0u, total, 0u);
 }
 
-// Morton codes of present objects, compacted in id order; then the
-// sequence stamps of the tick's queries (the latest query of an object is
-// the one answered).
-__global__ void __launch_bounds__(kBlock) k_morton(const float *px, const float *py, uint32_t N,
+// Sort keys of present objects, compacted in id order: their Morton codes
+// when the tick builds the quadtree, else the index of the leaf holding
+// them (the leaves are in Morton order, so grouping by leaf is what the
+// join needs, and leaf indices take fewer radix digits than codes).  Then
+// the sequence stamps of the tick's queries (the latest query of an object
+// is the one answered).
+__global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N, Tree tr,
                                                    Ctl *ctl, const uint32_t *blk, uint32_t *keys,
                                                    uint32_t *vals, const uint32_t *qid,
                                                    uint32_t nq, uint64_t *qstamp) {
@@ -276,16 +309,19 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float *px, const float 
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < N ? b0 + chunk : N;
   const float x0 = ctl->x0, y0 = ctl->y0, sc = ctl->scale;
+  const bool keep = !ctl->rebuild;  // the quadtree is kept: sort by leaf
+  tr.tlev = ctl->tlev;
   uint32_t base = blk[blockIdx.x];
   for (uint64_t t0 = b0; t0 < b1; t0 += kBlock) {
     const uint64_t i = t0 + threadIdx.x;
-    const float xv = i < b1 ? px[i] : NAN;
-    const bool pres = xv == xv;
+    const float2 p = i < b1 ? pos[i] : make_float2(NAN, NAN);
+    const bool pres = p.x == p.x;
     uint32_t tot;
     const uint32_t ex = block_excl_scan<uint32_t, kBlock>(pres ? 1u : 0u, lds, &tot);
     if (pres) {
-      const float yv = py[i];
-      keys[base + ex] = morton2(cell_of(xv, x0, sc), cell_of(yv, y0, sc));
+      const float xv = p.x, yv = p.y;
+      const uint32_t code = morton2(cell_of(xv, x0, sc), cell_of(yv, y0, sc));
+      keys[base + ex] = keep ? leaf_of(tr, code) : code;
       vals[base + ex] = (uint32_t)i;
     }
     base += tot;
@@ -457,12 +493,15 @@ __global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const ui
 
 // ---------------------------------------------------------------- leaves --
 
-__global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const uint32_t *codes,
+// Object range of every leaf in the sorted keys: codes after a build
+// (first code >= the leaf's start), leaf indices otherwise.
+__global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const uint32_t *keys,
                                                         const uint32_t *lstart, uint32_t *leaf_beg,
                                                         uint32_t *leaf_nsq) {
   const uint32_t n = ctl->n_leaves, np = ctl->n_present;
+  const bool by_code = ctl->rebuild != 0;
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
-    leaf_beg[t] = lower_bound_u32(codes, 0u, np, lstart[t]);
+    leaf_beg[t] = lower_bound_u32(keys, 0u, np, by_code ? lstart[t] : t);
     leaf_nsq[t] = 0u;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) leaf_beg[n] = np;
@@ -482,12 +521,6 @@ struct QBox {
   uint32_t i0, i1, j0, j1;
 };
 
-struct Tree {
-  const uint4 *nodes;
-  const uint32_t *table;
-  const uint32_t *lstart, *llevel;
-  uint32_t tlev;
-};
 
 // Depth-first walk below internal node `node` at level depth0 with cell
 // coordinates (pi, pj) at that level, one node per iteration: its children
@@ -659,6 +692,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
   ctl->err |= err;
   ctl->n_isect = tot[0];
   ctl->n_cov = tot[1];
+  ctl->n_entries = ctl->n_leaves;
   ctl->go_split = err ? 0u : 1u;
   ctl->n32[0] = err ? 0u : (uint32_t)tot[0];
   ctl->n32[1] = err ? 0u : (uint32_t)tot[1];
@@ -723,31 +757,59 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 }
 
 // -------------------------------------------------------------- schedule --
-// Task key of every leaf: 255 - bit length of its weight |intersecting
-// subqueries| x |objects| (ascending keys = heaviest first; weight 0 last);
-// a stable one-pass radix sort of the keys gives the order, ties in leaf
-// order.  Also the per-block partials of the containment-test count, the
-// largest leaf above l_max and the number of tasks.
-__global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint32_t *leaf_beg,
+// Join tasks: a leaf's intersecting subqueries are joined kTaskSub at a
+// time, so a leaf that many queries overlap is spread over several waves.
+// Task e < n_leaves is the first chunk of leaf e; the further chunks of
+// heavy leaves are appended (vtask: leaf, chunk).  Key of a task: 255 - bit
+// length of its weight |subqueries of the chunk| x |objects| (ascending =
+// heaviest first; weight 0 last); a one-pass radix sort of the keys gives
+// the order.  Which task joins which subquery does not depend on the order,
+// so neither do the results.  Also the per-block partials of the
+// containment-test count, the largest leaf above l_max and the number of
+// leaves with work.
+__device__ __forceinline__ uint32_t task_key(uint64_t w) {
+  return w == 0 ? 255u : 255u - (uint32_t)(64 - __clzll((long long)w));
+}
+
+__global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *leaf_beg,
                                                       const uint32_t *leaf_sqoff,
                                                       const uint32_t *llevel, uint32_t l_max,
                                                       uint32_t *tkey, uint32_t *tasks,
-                                                      uint64_t *red, float *tlog) {
+                                                      uint2 *vtask, uint32_t *xbase,
+                                                      uint32_t tcap, uint64_t *red, float *tlog) {
   __shared__ uint64_t s_tests[kWavesPerBlock];
   __shared__ uint32_t s_max[kWavesPerBlock], s_tasks[kWavesPerBlock];
   const uint32_t n = ctl->n_leaves;
   const bool ok = ctl->go_split != 0;
   uint64_t tests = 0;
   uint32_t mx = 0, nt = 0;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
-    const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
-    const uint32_t nsq = ok ? leaf_sqoff[t + 1] - leaf_sqoff[t] : 0u;
+  bool ovf = false;
+  const uint32_t nr = (n + kWave - 1) / kWave * kWave;
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nr; t += gridDim.x * kBlock) {
+    const bool valid = t < n;
+    const uint32_t cnt = valid ? leaf_beg[t + 1] - leaf_beg[t] : 0u;
+    const uint32_t nsq = valid && ok ? leaf_sqoff[t + 1] - leaf_sqoff[t] : 0u;
     const uint64_t w = (uint64_t)nsq * cnt;
+    const uint32_t more = w != 0 ? (nsq - 1u) / kTaskSub : 0u;  // chunks after the first
+    const uint32_t base = wave_append(&ctl->n_entries, more);
+    if (!valid) continue;
     tests += w;
     nt += w != 0;
     if (llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
-    tkey[t] = w == 0 ? 255u : 255u - (uint32_t)(64 - __clzll((long long)w));
+    tkey[t] = task_key((uint64_t)(nsq < kTaskSub ? nsq : kTaskSub) * cnt);
     tasks[t] = t;
+    if (more) xbase[t] = base;
+    for (uint32_t c = 1; c <= more; ++c) {
+      const uint32_t e = base + c - 1u;
+      if (e >= tcap) {
+        ovf = true;
+        break;
+      }
+      const uint32_t sub = nsq - c * kTaskSub;
+      vtask[e - n] = make_uint2(t, c);
+      tkey[e] = task_key((uint64_t)(sub < kTaskSub ? sub : kTaskSub) * cnt);
+      tasks[e] = e;
+    }
     if (tlog) {
       float *rec = tlog + (uint64_t)t * 8;
       rec[0] = (float)cnt;
@@ -756,6 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
       rec[3] = rec[4] = rec[5] = rec[6] = rec[7] = 0.0f;
     }
   }
+  flag_error(ctl, kErrOvfSubq, ovf);  // unreachable: entries <= leaves + subqueries / kTaskSub
   tests = wave_sum(tests);
   nt = wave_sum(nt);
   mx = wave_max(mx);
@@ -787,7 +850,24 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(const Ctl *ctl, const uint
 // set writes its object id at the subquery's offset plus the number of set
 // bits below it (coalesced, no atomics, no bitmap in memory).
 
+// Leaf of join task e and the range [sb, se) of its intersecting subqueries.
+__device__ __forceinline__ void task_range(uint32_t e, uint32_t n_leaves, const uint2 *vtask,
+                                           const uint32_t *leaf_sqoff, uint32_t *leaf,
+                                           uint32_t *sb, uint32_t *se) {
+  uint32_t l = e, c = 0;
+  if (e >= n_leaves) {
+    const uint2 v = vtask[e - n_leaves];
+    l = v.x;
+    c = v.y;
+  }
+  const uint32_t b = leaf_sqoff[l] + c * kTaskSub, end = leaf_sqoff[l + 1];
+  *leaf = l;
+  *sb = b;
+  *se = end < b + kTaskSub ? end : b + kTaskSub;
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint32_t *tasks,
+                                                       const uint2 *vtask,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
@@ -796,15 +876,15 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
                                                        const uint32_t *lstart,
                                                        const uint32_t *llevel) {
   if (!ctl->go_split) return;
-  const uint32_t nt = ctl->n_leaves;
+  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint32_t leaf = tasks[t];
-    const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
-    if (sb == se) continue;
+    uint32_t leaf, sb, se;
+    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+    if (sb >= se) continue;
     const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     float ovl = 0.0f;
@@ -830,12 +910,13 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
       }
       if (lane < nk) sq_cnt[slot] = cnt;
     }
-    if (tlog) {
+    if (tlog) {  // a leaf's record sums its tasks: mean overlap, clock ticks
       ovl = wave_sum(ovl);
       const uint64_t clk1 = __builtin_amdgcn_s_memrealtime();
       if (lane == 0) {
-        tlog[(uint64_t)leaf * 8 + 3] = ovl / (float)(se - sb);
-        tlog[(uint64_t)leaf * 8 + 4] = (float)(clk1 - clk0);
+        const float nsq = (float)(leaf_sqoff[leaf + 1] - leaf_sqoff[leaf]);
+        atomicAdd(&tlog[(uint64_t)leaf * 8 + 3], ovl / nsq);
+        atomicAdd(&tlog[(uint64_t)leaf * 8 + 4], (float)(clk1 - clk0));
       }
     }
   }
@@ -883,6 +964,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
 }
 
 __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t *tasks,
+                                                       const uint2 *vtask,
                                                        const uint32_t *leaf_beg,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
@@ -900,15 +982,15 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
     ctl->tick += 1;
   }
   if (!go) return;
-  const uint32_t nt = ctl->n_leaves;
+  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint32_t leaf = tasks[t];
-    const uint32_t sb = leaf_sqoff[leaf], se = leaf_sqoff[leaf + 1];
-    if (sb == se) continue;
+    uint32_t leaf, sb, se;
+    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+    if (sb >= se) continue;
     const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
@@ -935,7 +1017,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
       }
     }
     if (tlog && lane == 0)
-      tlog[(uint64_t)leaf * 8 + 5] = (float)(__builtin_amdgcn_s_memrealtime() - clk0);
+      atomicAdd(&tlog[(uint64_t)leaf * 8 + 5], (float)(__builtin_amdgcn_s_memrealtime() - clk0));
   }
 }
 
@@ -1057,19 +1139,24 @@ void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const flo
   const unsigned g = grid_for(m);
   LAUNCH(k_upd_stamp, g, kBlock, s, id, x, y, m, B.N, seq_off, B.ustamp, B.ctl);
   LAUNCH(k_upd_write, g, kBlock, s, id, x, y, m, B.N, seq_off, (const uint64_t *)B.ustamp,
-         (const Ctl *)B.ctl, B.px, B.py);
+         (const Ctl *)B.ctl, B.pos);
+}
+
+static Tree tree_of(const Bufs &B) {
+  return Tree{(const uint4 *)B.nodes, (const uint32_t *)B.table, (const uint32_t *)B.lstart,
+              (const uint32_t *)B.llevel, 0u};
 }
 
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
                   const uint32_t *qid, uint32_t nq, hipStream_t s) {
-  LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N,
+  LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N,
          (const Ctl *)B.ctl, B.blk, B.red);
   LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, (const uint64_t *)B.red, B.front[0],
          decision, policy, upd_total);
-  LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float *)B.px, (const float *)B.py, B.N, B.ctl,
+  LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
          (const uint32_t *)B.blk, B.keyA, B.valA, qid, nq, B.qstamp);
   radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist, B.tot, 0,
-                   32, s, B.px, B.py, B.sxy);
+                   32, s, B.pos, B.sxy, &B.ctl->sort_skip);
 }
 
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
@@ -1098,11 +1185,6 @@ void launch_leaves(const Bufs &B, hipStream_t s) {
          (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg, B.leaf_nsq);
 }
 
-static Tree tree_of(const Bufs &B) {
-  return Tree{(const uint4 *)B.nodes, (const uint32_t *)B.table, (const uint32_t *)B.lstart,
-              (const uint32_t *)B.llevel, 0u};
-}
-
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s) {
@@ -1123,18 +1205,20 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
          (const uint32_t *)B.leaf_sqoff, B.leaf_nsq, B.sq_q, B.sq_s, B.cov_leaf, covering, B.red);
 }
 
-const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, hipStream_t s) {
-  LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)B.leaf_beg,
-         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks, B.red,
-         B.tlog);
+const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
+                                hipStream_t s) {
+  LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, B.ctl, (const uint32_t *)B.leaf_beg,
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks,
+         B.vtask, B.xbase, B.TCAP, B.red, B.tlog);
   if (!reorder) return B.tasks;
-  const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_leaves,
+  if (learned) launch_schedule_mlp(B, s);
+  const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_entries,
                                     &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
   return alt ? B.tasks2 : B.tasks;
 }
 
 void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s) {
-  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, tasks,
+  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, tasks, (const uint2 *)B.vtask,
          (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
          (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
          B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel);
@@ -1151,7 +1235,8 @@ void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t
 }
 
 void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s) {
-  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, tasks, (const uint32_t *)B.leaf_beg,
+  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, tasks, (const uint2 *)B.vtask,
+         (const uint32_t *)B.leaf_beg,
          (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
          (const float4 *)B.qrect, (const float2 *)B.sxy, (const uint32_t *)B.valA,
          (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);

@@ -12,6 +12,12 @@ namespace sj {
 
 __device__ __forceinline__ bool gated(const uint32_t *gate) { return gate && *gate == 0u; }
 
+// A radix pass whose digit is zero for every key (shift >= *skip) only
+// copies its input, so that the passes still end in the same buffer.
+__device__ __forceinline__ bool copy_pass(const uint32_t *skip, int shift) {
+  return skip && (uint32_t)shift >= *skip;
+}
+
 // ---------------------------------------------------------------- scans --
 // Block b of kChunkBlocks owns the contiguous chunk [b*chunk, (b+1)*chunk)
 // of every array.  reduce: chunk sums -> part[job][b]; a single-block "top"
@@ -112,11 +118,12 @@ ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32
 //           digit order and writes each digit's run contiguously to its
 //           global offset.  The last pass can also gather the positions of
 //           the sorted values (sorted SoA of the objects).
+// A pass at or above the device value *skip only copies (see copy_pass).
 
 __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const uint32_t *n_dev,
-                                                    const uint32_t *gate, int shift,
-                                                    uint32_t *hist) {
-  if (gated(gate)) return;
+                                                    const uint32_t *gate, const uint32_t *skip,
+                                                    int shift, uint32_t *hist) {
+  if (gated(gate) || copy_pass(skip, shift)) return;
   __shared__ uint32_t lh[256];
   const uint32_t n = *n_dev;
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -130,8 +137,9 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const 
 }
 
 __global__ void __launch_bounds__(kChunkBlocks) k_rs_hscan(uint32_t *hist, const uint32_t *gate,
+                                                           const uint32_t *skip, int shift,
                                                            uint32_t *tot) {
-  if (gated(gate)) return;
+  if (gated(gate) || copy_pass(skip, shift)) return;
   __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
   uint32_t *h = hist + blockIdx.x * kChunkBlocks;
   uint32_t total;
@@ -146,9 +154,9 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
                                                        uint32_t *__restrict__ kout,
                                                        uint32_t *__restrict__ vout,
                                                        const uint32_t *n_dev, const uint32_t *gate,
-                                                       int shift, const uint32_t *hist,
-                                                       const uint32_t *tot, const float *gx,
-                                                       const float *gy, float2 *gout) {
+                                                       const uint32_t *skip, int shift,
+                                                       const uint32_t *hist, const uint32_t *tot,
+                                                       const float2 *gpos, float2 *gout) {
   if (gated(gate)) return;
   __shared__ uint32_t cnt[kSortItems * kWavesPerBlock * 256];
   __shared__ uint32_t sk[kSortTile];
@@ -161,6 +169,15 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   if (b0 >= b1) return;  // uniform per block: no barrier is skipped by part of it
+  if (copy_pass(skip, shift)) {
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+      const uint32_t v = vin[i];
+      kout[i] = kin[i];
+      vout[i] = v;
+      if (GATHER) gout[i] = gpos[v];
+    }
+    return;
+  }
   const int tid = threadIdx.x, w = tid / kWave;
   {
     uint32_t total;
@@ -223,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       const uint32_t v = sv[i];
       kout[g] = k;
       vout[g] = v;
-      if (GATHER) gout[g] = make_float2(gx[v], gy[v]);
+      if (GATHER) gout[g] = gpos[v];
     }
     __syncthreads();
     goff[tid] += tcnt[tid];
@@ -233,24 +250,25 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
 
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, const uint32_t *gate, uint32_t *hist, uint32_t *tot,
-                      int bit_begin, int bit_end, hipStream_t s, const float *gx,
-                      const float *gy, float2 *gout) {
+                      int bit_begin, int bit_end, hipStream_t s, const float2 *gpos,
+                      float2 *gout, const uint32_t *skip) {
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   bool in_alt = false;
   for (int shift = bit_begin; shift < bit_end; shift += 8) {
     const bool last = shift + 8 >= bit_end;
     hipLaunchKernelGGL(k_rs_hist, dim3(kChunkBlocks), dim3(kBlock), 0, s, (const uint32_t *)ki,
-                       n_dev, gate, shift, hist);
-    hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, tot);
+                       n_dev, gate, skip, shift, hist);
+    hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, skip, shift,
+                       tot);
     if (last && gout)
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
-                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, shift,
-                         (const uint32_t *)hist, (const uint32_t *)tot, gx, gy, gout);
+                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
+                         shift, (const uint32_t *)hist, (const uint32_t *)tot, gpos, gout);
     else
       hipLaunchKernelGGL(k_rs_scatter<false>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
-                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, shift,
-                         (const uint32_t *)hist, (const uint32_t *)tot, (const float *)nullptr,
-                         (const float *)nullptr, (float2 *)nullptr);
+                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
+                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
+                         (const float2 *)nullptr, (float2 *)nullptr);
     uint32_t *t = ki;
     ki = ko;
     ko = t;

@@ -5,8 +5,10 @@
 // from the terms of their complexity (Computational Complexity section,
 // filtering and decoding equations): per active leaf c, the MLP predicts the
 // join time of |P^c| objects against |Q_I^c| intersecting subqueries; the
-// sum over leaves is the join's work, the largest one its critical path (one
-// wave joins a leaf); the split and the leaf passes add terms linear in
+// sum over leaves is the join's work, and the prediction for a leaf of at
+// most kTaskSub subqueries (one join task, one wave) bounds its critical
+// path through the largest such value; the split and the leaf passes add
+// terms linear in
 // |Q_I|, |Q_C| and the number of leaves.  The cheapest candidate is then
 // built for the tick.  The paper fixes the threshold by hand after a sweep
 // (Experimental evaluation, S5); this replaces the sweep, and the results
@@ -48,30 +50,70 @@ __global__ void k_tune_set(Ctl *ctl, const TuneState *ts, uint32_t c, uint4 *fro
   reset_build(ctl, ts, front0, ts->cand[c]);
 }
 
-// Per-block partials of the sum and the maximum over active leaves of
-// exp(MLP(features)).  One wave per leaf: lanes average the overlap of the
-// leaf's intersecting subqueries, then lane j computes hidden unit j of both
-// layers (the first layer's outputs are broadcast lane by lane) and a wave
-// sum gives the output.  Parameters are staged in LDS as FP32 (W2 rows
-// padded to 65).
+// The network staged in LDS as FP32 for wave-cooperative inference (W2
+// rows padded to 65 so that lane i reading row i hits distinct banks).
+struct MlpLds {
+  float W2[kH][kH + 1];
+  float W1[kH][kF];
+  float b1[kH], b2[kH], w3[kH];
+  float b3;
+};
+
+// All threads of the block take part; a barrier follows.
+__device__ void stage_mlp(MlpLds &m, const uint16_t *w) {
+  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) m.W2[i / kH][i % kH] = bf2f(w[kOW2 + i]);
+  for (int i = threadIdx.x; i < kH * kF; i += blockDim.x) m.W1[i / kF][i % kF] = bf2f(w[kOW1 + i]);
+  if (threadIdx.x < kH) {
+    m.b1[threadIdx.x] = bf2f(w[kOB1 + threadIdx.x]);
+    m.b2[threadIdx.x] = bf2f(w[kOB2 + threadIdx.x]);
+    m.w3[threadIdx.x] = bf2f(w[kOW3 + threadIdx.x]);
+  }
+  if (threadIdx.x == 0) m.b3 = bf2f(w[kOB3]);
+  __syncthreads();
+}
+
+// Output of the network for one input; called by all lanes of a wave with
+// the same input: lane j computes hidden unit j of both layers (the first
+// layer's outputs are broadcast lane by lane) and a wave sum gives y.
+__device__ __forceinline__ float wave_mlp(const MlpLds &m, float x0, float x1, float x2,
+                                          float x3) {
+  const uint32_t lane = lane_id();
+  float a = m.b1[lane];
+  a = fmaf(m.W1[lane][0], x0, a);
+  a = fmaf(m.W1[lane][1], x1, a);
+  a = fmaf(m.W1[lane][2], x2, a);
+  a = fmaf(m.W1[lane][3], x3, a);
+  const float h1 = a > 0.0f ? a : 0.0f;
+  float a2 = m.b2[lane];
+  for (int j = 0; j < kH; ++j) a2 = fmaf(m.W2[lane][j], readlane_f(h1, j), a2);
+  const float h2 = a2 > 0.0f ? a2 : 0.0f;
+  return wave_sum(m.w3[lane] * h2) + m.b3;
+}
+
+// Mean over the intersecting subqueries [sb, se) of leaf t of the fraction
+// of the leaf's area their rectangle covers (whole wave).
+__device__ __forceinline__ float mean_overlap(const Ctl *ctl, const uint32_t *lstart,
+                                              const uint32_t *llevel, uint32_t t, uint32_t sb,
+                                              uint32_t se, const uint32_t *sq_q,
+                                              const float4 *qrect) {
+  float ov = 0.0f;
+  for (uint32_t i = sb + lane_id(); i < se; i += kWave)
+    ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq_q[i]]);
+  return wave_sum(ov) / (float)(se - sb);
+}
+
+// Per-block partials of the sum over active leaves of exp(MLP(features))
+// and of the maximum of exp(MLP(features of one join task)), the subquery
+// count capped at kTaskSub.  One wave per leaf.
 __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const TuneState *ts,
                                                         const uint32_t *leaf_beg,
                                                         const uint32_t *leaf_sqoff,
                                                         const uint32_t *sq_q, const float4 *qrect,
                                                         const uint32_t *lstart,
                                                         const uint32_t *llevel, uint64_t *red) {
-  __shared__ float sW2[kH][kH + 1];
-  __shared__ float sW1[kH][kF], sB1[kH], sB2[kH], sW3[kH];
+  __shared__ MlpLds m;
   __shared__ double sacc[kWavesPerBlock], smax[kWavesPerBlock];
-  for (int i = threadIdx.x; i < kH * kH; i += kBlock) sW2[i / kH][i % kH] = bf2f(ts->w[kOW2 + i]);
-  for (int i = threadIdx.x; i < kH * kF; i += kBlock) sW1[i / kF][i % kF] = bf2f(ts->w[kOW1 + i]);
-  if (threadIdx.x < kH) {
-    sB1[threadIdx.x] = bf2f(ts->w[kOB1 + threadIdx.x]);
-    sB2[threadIdx.x] = bf2f(ts->w[kOB2 + threadIdx.x]);
-    sW3[threadIdx.x] = bf2f(ts->w[kOW3 + threadIdx.x]);
-  }
-  __syncthreads();
-  const float b3 = bf2f(ts->w[kOB3]);
+  stage_mlp(m, ts->w);
   const uint32_t lane = lane_id();
   double acc = 0.0, mx = 0.0;
   if (ctl->go_split) {
@@ -83,25 +125,16 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
       const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
       const uint32_t sb = leaf_sqoff[t], se = leaf_sqoff[t + 1];
       if (cnt == 0 || sb == se) continue;
-      float ov = 0.0f;
-      for (uint32_t i = sb + lane; i < se; i += kWave)
-        ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq_q[i]]);
-      ov = wave_sum(ov) / (float)(se - sb);
-      const float x0 = log2f(1.0f + (float)cnt), x1 = log2f(1.0f + (float)(se - sb));
+      const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq_q, qrect);
+      const uint32_t nsq = se - sb;
+      const float x0 = log2f(1.0f + (float)cnt);
       const float x2 = (float)llevel[t] * (1.0f / 16.0f);
-      float a = sB1[lane];
-      a = fmaf(sW1[lane][0], x0, a);
-      a = fmaf(sW1[lane][1], x1, a);
-      a = fmaf(sW1[lane][2], x2, a);
-      a = fmaf(sW1[lane][3], ov, a);
-      const float h1 = a > 0.0f ? a : 0.0f;
-      float a2 = sB2[lane];
-      for (int j = 0; j < kH; ++j) a2 = fmaf(sW2[lane][j], readlane_f(h1, j), a2);
-      const float h2 = a2 > 0.0f ? a2 : 0.0f;
-      const float y = wave_sum(sW3[lane] * h2) + b3;
-      const double e = (double)expf(y);
+      const double e = (double)expf(wave_mlp(m, x0, log2f(1.0f + (float)nsq), x2, ov));
+      const double et =
+          nsq <= kTaskSub ? e
+                          : (double)expf(wave_mlp(m, x0, log2f(1.0f + (float)kTaskSub), x2, ov));
       acc += e;
-      mx = e > mx ? e : mx;
+      mx = et > mx ? et : mx;
     }
   }
   if (lane == 0) {
@@ -110,13 +143,62 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0, m = 0.0;
+    double s = 0.0, mm = 0.0;
     for (int w = 0; w < kWavesPerBlock; ++w) {
       s += sacc[w];
-      m = smax[w] > m ? smax[w] : m;
+      mm = smax[w] > mm ? smax[w] : mm;
     }
     red[kRedCost * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(s);
-    red[kRedCostMax * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(m);
+    red[kRedCostMax * kChunkBlocks + blockIdx.x] = (uint64_t)__double_as_longlong(mm);
+  }
+}
+
+// Learned schedule: the key of every join task of a leaf from the
+// network's prediction for that task (its subquery count is kTaskSub, or
+// what remains for the last one): 255 - min(254, 16 (ln us + 4)), so the
+// one-pass radix sort puts the longest predicted tasks first.  Keys of
+// tasks without work stay 255.
+__device__ __forceinline__ uint32_t time_key(float y) {
+  const float q = 16.0f * (y + 4.0f);
+  const uint32_t k = !(q > 0.0f) ? 0u : (q >= 254.0f ? 254u : (uint32_t)q);
+  return 255u - k;
+}
+
+__global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const TuneState *ts,
+                                                          const uint32_t *leaf_beg,
+                                                          const uint32_t *leaf_sqoff,
+                                                          const uint32_t *sq_q,
+                                                          const float4 *qrect,
+                                                          const uint32_t *lstart,
+                                                          const uint32_t *llevel,
+                                                          const uint32_t *xbase, uint32_t tcap,
+                                                          uint32_t *tkey) {
+  __shared__ MlpLds m;
+  stage_mlp(m, ts->w);
+  if (!ctl->go_split) return;
+  const uint32_t n = ctl->n_leaves;
+  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+  const uint32_t w0 =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  for (uint32_t t = w0; t < n; t += nwaves) {
+    const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
+    const uint32_t sb = leaf_sqoff[t], se = leaf_sqoff[t + 1];
+    if (cnt == 0 || sb == se) continue;
+    const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq_q, qrect);
+    const uint32_t nsq = se - sb, more = (nsq - 1u) / kTaskSub;
+    const float x0 = log2f(1.0f + (float)cnt);
+    const float x2 = (float)llevel[t] * (1.0f / 16.0f);
+    const uint32_t first = nsq < kTaskSub ? nsq : kTaskSub;
+    const uint32_t kf = time_key(wave_mlp(m, x0, log2f(1.0f + (float)first), x2, ov));
+    const uint32_t last = nsq - more * kTaskSub;
+    const uint32_t kl =
+        more == 0u ? kf : time_key(wave_mlp(m, x0, log2f(1.0f + (float)last), x2, ov));
+    if (lane_id() == 0) tkey[t] = kf;
+    // further tasks: full chunks, the last one holds what remains
+    for (uint32_t c = 1u + lane_id(); c <= more; c += kWave) {
+      const uint32_t e = xbase[t] + c - 1u;
+      if (e < tcap) tkey[e] = c == more ? kl : kf;
+    }
   }
 }
 
@@ -168,6 +250,13 @@ __global__ void k_tune_pick(Ctl *ctl, TuneState *ts, uint4 *front0) {
 }
 
 #define LAUNCH(k, g, b, s, ...) hipLaunchKernelGGL(k, dim3(g), dim3(b), 0, s, __VA_ARGS__)
+
+void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
+  LAUNCH(k_task_keys_mlp, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
+         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
+         (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel,
+         (const uint32_t *)B.xbase, B.TCAP, B.tkey);
+}
 
 void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
                  const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,

@@ -164,3 +164,25 @@ def test_tuned_ticks_equal_fixed_threshold_ticks(mode):
     info = tuned.tune_info()
     assert info["n_tunes"] >= 3  # ticks 0, 4 and 8 build (and any the policy adds)
     assert all(c in CAND for c in chosen)
+
+
+@pytest.mark.parametrize("thresh", [False, True])
+def test_learned_schedule_gives_the_same_results(thresh):
+    """Join tasks ordered by the network's predicted time (with or without
+    the learned threshold): every tick's result set equals the one of the
+    weight-ordered fixed-threshold scene."""
+    wl = workloads.make("hotspot", n=60_000, n_ticks=6)
+    nq = max(t.nq for t in wl.ticks())
+    bits, _ = work_model()
+    kw = dict(capacity_subqueries=64 * nq, capacity_covering=64 * nq, rebuild_period=4)
+    learned = Scene(wl.n, nq, th=64, th_min=4, thresh_mlp=thresh, schedule_mlp=True, **kw)
+    install(learned, bits)
+    fixed = Scene(wl.n, nq, th=64, **kw)
+    for i, t in enumerate(wl.ticks()):
+        say(f"learned schedule thresh={thresh} tick {i}")
+        gpu_tick(learned, t)
+        gpu_tick(fixed, t)
+        a, b = gpu_count_hash(learned), gpu_count_hash(fixed)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        if not thresh:  # same quadtree: same split of the pairs into tested and covered
+            assert learned.stats()["n_isect_ids"] == fixed.stats()["n_isect_ids"]

@@ -74,3 +74,20 @@ def test_cost_of_a_constant_network(k):
     assert np.allclose(sums, 3 * k)
     assert np.allclose(costs, 2 * 3 * k + 3 * 3 + 5 * 0 + 7 * 4 + 11 * k)
     assert chosen == 8  # the first of equal costs
+
+
+def test_critical_path_term_caps_the_subqueries_of_a_task():
+    """A network predicting 0.01 (1 + objects)(1 + subqueries): the sum term
+    takes a leaf's own subquery count, the maximum term at most 64 (one join
+    task)."""
+    p = np.zeros(mlp.P)
+    p[0:2] = np.log(2.0)   # W1 row 0 on log2(1 + objects), log2(1 + subqueries)
+    p[320] = 1.0           # W2[0][0]
+    p[4480] = 1.0          # w3[0]
+    p[4544] = np.log(0.01)
+    feats = np.array([[np.log2(11.0), np.log2(101.0), 0.5, 0.3],    # 10 objects, 100 subqueries
+                      [np.log2(3.0), np.log2(5.0), 0.25, 1.0]])     # 2 objects, 4 subqueries
+    c, s = costmodel.cost(p, (1.0, 0.0, 0.0, 0.0, 0.0), feats, 0, 0, 0)
+    assert np.isclose(s, 0.01 * (11 * 101 + 3 * 5)) and np.isclose(c, s)
+    c, _ = costmodel.cost(p, (0.0, 0.0, 0.0, 0.0, 1.0), feats, 0, 0, 0)
+    assert np.isclose(c, 0.01 * 11 * 65)
