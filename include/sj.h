@@ -267,19 +267,23 @@ int sj_stats(sj_scene *scene, sj_tick_stats *out);
  *   cost = coef[0] * sum over active leaves c of exp(MLP(f_c))
  *        + coef[1] |Q_I| + coef[2] |Q_C| + coef[3] * leaves
  *        + coef[4] * max over active leaves c of exp(MLP(f'_c))
+ *        + coef[5] * P(leaves) * objects
  * with f_c = (log2(1 + |P^c|), log2(1 + |Q_I^c|), level / 16, mean over the
  * intersecting subqueries of c of the fraction of c's area they cover), f'_c
  * = f_c with |Q_I^c| capped at 64 (a join task takes at most 64 subqueries
  * of a leaf), and
  * builds the cheapest (the first of equal costs; a candidate that overflows
  * a capacity is infeasible; with none feasible the threshold is kept).
- * The sum is the join's work and the maximum its critical path, since one
- * wave runs a join task.
+ * P(L) = ceil(bit length of (L - 1) / 8), the radix passes of the
+ * leaf-keyed sort of the ticks that keep the quadtree.  The sum is the
+ * join's work and the maximum its critical path, since one wave runs a
+ * join task.
  * Results do not depend on it.
  * d_w: sj_mlp_param_count() BF16 parameters (device, copied); cand: n_cand
  * (1..8) thresholds, each >= th_min.  Synchronises the scene's stream.
  * Errors: SJ_EINVAL (null pointers, bad n_cand or a candidate below th_min). */
-int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[5],
+#define SJ_COST_TERMS 6
+int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[SJ_COST_TERMS],
                       const uint32_t *cand, uint32_t n_cand);
 
 typedef struct sj_tune_info {

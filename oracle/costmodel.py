@@ -17,7 +17,11 @@ most 64 intersecting subqueries of a leaf; f'_c is f_c with |Q_I^c| capped
 at 64):
 
     cost = coef[0] sum_c exp(MLP(f_c)) + coef[1] |Q_I| + coef[2] |Q_C|
-           + coef[3] leaves + coef[4] max_c exp(MLP(f'_c)).
+           + coef[3] leaves + coef[4] max_c exp(MLP(f'_c))
+           + coef[5] P(leaves) objects,
+
+P(L) = ceil(bit length of (L - 1) / 8): the radix passes of the sort by leaf
+index on the ticks that keep the quadtree.
 
 Leaves without objects are inactive and hold no subqueries.  Float64
 throughout; shares no code with the HIP kernels.
@@ -56,9 +60,15 @@ def overlap_fraction(rect, lx, ly, side):
     return np.where((w > 0) & (h > 0), np.minimum(f, 1.0), 0.0)
 
 
+def sort_passes(n_leaves: int) -> int:
+    """8-bit radix passes that sort keys below n_leaves."""
+    return (int(n_leaves - 1).bit_length() + 7) // 8 if n_leaves > 1 else 0
+
+
 def candidate_terms(live, rects, fr, leaves: oracle.Leaves):
     """Features of the active leaves and the counts of the linear terms for
-    one quadtree: (features [n_active, 4], n_isect, n_cov, n_leaves)."""
+    one quadtree: (features [n_active, 4], n_isect, n_cov, n_leaves,
+    objects)."""
     oi, li, oc, lc = oracle.split(live, rects, fr, leaves)
     cnt = leaves.count
     q_of = np.repeat(np.arange(len(oi) - 1), np.diff(oi).astype(np.int64))
@@ -74,10 +84,10 @@ def candidate_terms(live, rects, fr, leaves: oracle.Leaves):
     a = (cnt > 0) & (nsq > 0)
     feats = np.stack([np.log2(1.0 + cnt[a]), np.log2(1.0 + nsq[a]),
                       leaves.lvl[a].astype(np.float64) / 16.0, osum[a] / nsq[a]], axis=1)
-    return feats, int(len(lj)), n_cov, L
+    return feats, int(len(lj)), n_cov, L, int(cnt.sum())
 
 
-def cost(params, coef, feats, n_isect, n_cov, n_leaves):
+def cost(params, coef, feats, n_isect, n_cov, n_leaves, n_objects=0):
     """Predicted cost and the sum of the predictions from the features and
     counts (params: the BF16-rounded MLP parameters as values)."""
     if len(feats):
@@ -88,7 +98,7 @@ def cost(params, coef, feats, n_isect, n_cov, n_leaves):
     else:
         s, m = 0.0, 0.0
     return (coef[0] * s + coef[1] * n_isect + coef[2] * n_cov + coef[3] * n_leaves +
-            coef[4] * m), s
+            coef[4] * m + coef[5] * sort_passes(n_leaves) * n_objects), s
 
 
 def choose(st: oracle.State, live, rects, params, coef, cand, l_max: int = 16,
@@ -102,8 +112,8 @@ def choose(st: oracle.State, live, rects, params, coef, cand, l_max: int = 16,
     costs, sums = [], []
     for th in cand:
         lv = oracle.quadtree(codes, th, l_max)
-        feats, n_isect, n_cov, L = candidate_terms(live, rects, fr, lv)
-        c, s = cost(params, coef, feats, n_isect, n_cov, L)
+        feats, n_isect, n_cov, L, n_obj = candidate_terms(live, rects, fr, lv)
+        c, s = cost(params, coef, feats, n_isect, n_cov, L, n_obj)
         if (cap_isect is not None and n_isect > cap_isect) or \
                 (cap_cov is not None and n_cov > cap_cov):
             c = np.inf

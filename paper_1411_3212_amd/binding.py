@@ -19,6 +19,7 @@ LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
 SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG, SJ_THRESH_MLP, SJ_SCHEDULE_MLP = \
     1, 2, 4, 8, 16, 32
+COST_TERMS = 6  # SJ_COST_TERMS
 REBUILD = {"auto": 0, "always": 1, "never": 2}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
           "join_write"]
@@ -362,12 +363,12 @@ class Scene:
 
     def set_cost_model(self, w, coef, cand):
         """Installs the cost model: w = BF16 parameters (int16/uint16 device
-        tensor of sj_mlp_param_count() values, copied), coef = 5 floats,
+        tensor of sj_mlp_param_count() values, copied), coef = COST_TERMS floats,
         cand = candidate thresholds (1..8, each >= th_min)."""
         import torch
         assert w.is_cuda and w.dtype in (torch.int16, torch.uint16) and w.is_contiguous()
-        assert len(coef) == 5
-        cf = (c_float * 5)(*[float(v) for v in coef])
+        assert len(coef) == COST_TERMS
+        cf = (c_float * COST_TERMS)(*[float(v) for v in coef])
         cd = (c_uint32 * len(cand))(*[int(v) for v in cand])
         _check(self._lib.sj_set_cost_model(self.handle, _ptr(w), cf, cd, len(cand)), self.handle)
 

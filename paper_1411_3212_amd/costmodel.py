@@ -36,9 +36,10 @@ from .binding import PHASES, Scene
 
 CAND = (32, 64, 128, 256, 512, 1024)
 MODEL_PATH = Path(__file__).resolve().parent / "data" / "cost_model.json"
-# tick phases whose time depends on the threshold (the build is amortised
-# over the rebuild period and left out)
-COST_PHASES = ("leaves", "split", "schedule", "join_count", "join_scan", "join_write")
+# tick phases whose time depends on the threshold (the sort of the ticks
+# that keep the tree through its leaf keys; the build is amortised over the
+# rebuild period and left out)
+COST_PHASES = ("index", "leaves", "split", "schedule", "join_count", "join_scan", "join_write")
 TRAIN_SETS = (("hotspot", 20), ("segments", 20))  # 2 x 6 thresholds x 17 logged ticks
 
 
@@ -57,35 +58,45 @@ def leaf_samples(rec: np.ndarray, mhz: float):
     return X, us
 
 
+def sort_passes(n_leaves: int) -> int:
+    """Radix passes of the leaf-keyed sort (8-bit digits, keys below n_leaves)."""
+    return (int(n_leaves - 1).bit_length() + 7) // 8 if n_leaves > 1 else 0
+
+
 def collect(name: str, n_ticks: int, cand=CAND, warm: int = 3, torch=None, log=print) -> list:
-    """One record per logged tick of every candidate threshold: features,
-    measured leaf times, counts and phase times (eager, profiled)."""
+    """One record per logged tick of every candidate threshold: features and
+    measured leaf times from a scene with the timing log, counts and phase
+    times (eager, profiled) from a twin scene without it, since logging
+    slows the join."""
     wl = workloads.make(name, n_ticks=n_ticks)
     ticks = serving.pack_ticks(wl, torch)
     caps = serving.scene_capacities(wl)
     nq = max(q for _, _, q in ticks)
     rows = []
+    kw = {k: caps[k] for k in ("capacity_subqueries", "capacity_covering", "capacity_results")}
     for th in cand:
-        sc = Scene(wl.n, nq, th=th, timing_log=True, profile=True,
-                   capacity_subqueries=caps["capacity_subqueries"],
-                   capacity_covering=caps["capacity_covering"],
-                   capacity_results=caps["capacity_results"])
+        logged = Scene(wl.n, nq, th=th, timing_log=True, **kw)
+        plain = Scene(wl.n, nq, th=th, profile=True, **kw)
         for i, (buf, m, q) in enumerate(ticks):
             ids, x, y, qid, xa, ya, xb, yb = serving.tick_views(buf, m, q, torch)
-            sc.apply_updates(ids, x, y)
-            sc.run_tick(qid, xa, ya, xb, yb)
-            s = sc.stats()
+            for sc in (logged, plain):
+                sc.apply_updates(ids, x, y)
+                sc.run_tick(qid, xa, ya, xb, yb)
+            s = plain.stats()
+            logged.stats()
             if i < warm:
                 continue
-            rec, mhz = sc.timing_log()
+            rec, mhz = logged.timing_log()
             X, us = leaf_samples(rec.cpu().numpy(), mhz)
-            ph = sc.phase_times()
+            ph = plain.phase_times()
             rows.append(dict(wl=name, th=th, tick=i, X=X, us=us, n_isect=s["n_isect"],
-                             n_cov=s["n_cov"], n_leaves=s["n_leaves"], rebuilt=s["rebuilt"],
-                             phase_ms={k: ph[k] for k in PHASES}))
+                             n_cov=s["n_cov"], n_leaves=s["n_leaves"], n_present=s["n_present"],
+                             rebuilt=s["rebuilt"], phase_ms={k: ph[k] for k in PHASES}))
         log(f"collected {name} th={th}: {len(ticks) - warm} ticks, "
             f"{sum(len(r['us']) for r in rows if r['th'] == th and r['wl'] == name)} leaves")
-        sc.close()
+        logged.close()
+        plain.close()
+        del logged, plain
     del ticks
     torch.cuda.empty_cache()
     return rows
@@ -202,17 +213,23 @@ def train(rows: list, torch, steps: int = 3000, batch: int = 65536, lr: float = 
 def fit_terms(rows: list, tr: Trainer, torch) -> tuple:
     """Non-negative least squares of the threshold-dependent phase time of a
     tick (microseconds) on [sum exp(prediction), |Q_I|, |Q_C|, leaves,
-    max exp(prediction)] plus one intercept per workload (constants do not
-    move the argmin).  The sum is the join's work, the maximum its critical
-    path (one wave per leaf); a linear fit of both stands for the makespan."""
+    max exp(prediction for one task), sort passes x objects] plus one
+    intercept per workload (constants do not move the argmin).  The sum is
+    the join's work, the maximum its critical path (one wave per task, at
+    most 64 subqueries); a linear fit of both stands for the makespan."""
     from scipy.optimize import nnls
     names = sorted({r["wl"] for r in rows})
     A, b = [], []
     for r in rows:
-        y = tr.predict(torch.from_numpy(r["X"]).cuda()).cpu().numpy().astype(np.float64)
-        e = np.exp(y) if len(y) else np.zeros(1)
-        r["msum"], r["mmax"] = float(e.sum()), float(e.max())
-        A.append([r["msum"], r["n_isect"], r["n_cov"], r["n_leaves"], r["mmax"]] +
+        X = r["X"]
+        y = tr.predict(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+        Xc = X.copy()
+        Xc[:, 1] = np.minimum(Xc[:, 1], np.float32(np.log2(65.0)))
+        yc = tr.predict(torch.from_numpy(Xc).cuda()).cpu().numpy().astype(np.float64)
+        r["msum"] = float(np.exp(y).sum()) if len(y) else 0.0
+        r["mmax"] = float(np.exp(yc).max()) if len(yc) else 0.0
+        A.append([r["msum"], r["n_isect"], r["n_cov"], r["n_leaves"], r["mmax"],
+                  sort_passes(r["n_leaves"]) * r["n_present"]] +
                  [1.0 if r["wl"] == nm else 0.0 for nm in names])
         b.append(1e3 * sum(r["phase_ms"][k] for k in COST_PHASES))
     A, b = np.array(A), np.array(b)
@@ -229,10 +246,10 @@ def fit_terms(rows: list, tr: Trainer, torch) -> tuple:
         for th in sorted({r["th"] for r in rows}):
             sel = [i for i, r in enumerate(rows) if r["wl"] == nm and r["th"] == th]
             meas[th] = float(b[sel].mean())
-            cost[th] = float((A[sel, :5] @ x[:5]).mean())
+            cost[th] = float((A[sel, :6] @ x[:6]).mean())
         per[nm] = dict(measured_us=meas, predicted_us=cost,
                        best_measured=min(meas, key=meas.get), best_predicted=min(cost, key=cost.get))
-    return [float(v) for v in x[:5]], dict(r2=r2, intercepts=dict(zip(names, map(float, x[5:]))),
+    return [float(v) for v in x[:6]], dict(r2=r2, intercepts=dict(zip(names, map(float, x[6:]))),
                                            per_workload=per)
 
 
@@ -243,8 +260,8 @@ def save(path: Path, bits: np.ndarray, coef, cand, info: dict) -> None:
                         "mean overlap fraction of the subqueries with the leaf",
                target="ln microseconds of the leaf's join (count + write pass, one wave)",
                cost="coef0*sum exp(mlp) + coef1*|Q_I| + coef2*|Q_C| + coef3*leaves "
-                    "+ coef4*max exp(mlp) (microseconds of the threshold-dependent tick "
-                    "phases)",
+                    "+ coef4*max exp(mlp of one task) + coef5*sort passes*objects "
+                    "(microseconds of the threshold-dependent tick phases)",
                training=info)
     path.write_text(json.dumps(doc, indent=1) + "\n")
 

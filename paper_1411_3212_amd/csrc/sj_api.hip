@@ -190,6 +190,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.tkey2 = c.take<uint32_t>(T);
   b.vtask = c.take<uint2>(T - L);
   b.xbase = c.take<uint32_t>(L);
+  b.trec = c.take<uint4>(T);
+  b.tleaf = c.take<uint32_t>(T);
   b.TCAP = (uint32_t)T;
   b.qrect = c.take<float4>(Q);
   b.q_ni = c.take<uint32_t>(Q);
@@ -306,8 +308,7 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
     if (events) (void)hipEventRecord(s->ev[i], st);
   };
   if (part == 2) {
-    const uint32_t *tasks = (flags & SJ_REORDER) ? s->B.tasks2 : s->B.tasks;
-    sj::launch_join_write(s->B, tasks, nq, st);
+    sj::launch_join_write(s->B, nq, st);
     return;
   }
   rec(0);
@@ -323,15 +324,14 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
   sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   rec(4);
   const bool learned = (flags & SJ_SCHEDULE_MLP) && s->cm_set;
-  const uint32_t *tasks =
-      sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, learned, st);
+  sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, learned, st);
   rec(5);
-  sj::launch_join_count(s->B, tasks, st);
+  sj::launch_join_count(s->B, st);
   rec(6);
   sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
   rec(7);
   if (part == 1) return;
-  sj::launch_join_write(s->B, tasks, nq, st);
+  sj::launch_join_write(s->B, nq, st);
   rec(8);
   rec(9);
   s->events_valid = events;
@@ -673,7 +673,8 @@ int sj_phase_times(sj_scene *s, float *ms, int n) {
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipEventElapsedTime");
 }
 
-int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[5], const uint32_t *cand,
+int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[SJ_COST_TERMS],
+                      const uint32_t *cand,
                       uint32_t n_cand) {
   if (!s || !d_w || !coef || !cand) return SJ_EINVAL;
   if (n_cand == 0 || n_cand > (uint32_t)sj::kMaxCand)
@@ -683,14 +684,15 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[5], con
     if (cand[c] < th_min || cand[c] == 0)
       return fail(s, SJ_EINVAL, "set_cost_model: candidate below th_min");
   struct {
-    float coef[5];
+    float coef[SJ_COST_TERMS];
     uint32_t n_cand;
     uint32_t cand[sj::kMaxCand];
   } h{};
-  for (int i = 0; i < 5; ++i) h.coef[i] = coef[i];
+  for (int i = 0; i < SJ_COST_TERMS; ++i) h.coef[i] = coef[i];
   h.n_cand = n_cand;
   for (uint32_t c = 0; c < n_cand; ++c) h.cand[c] = cand[c];
-  static_assert(offsetof(sj::TuneState, n_cand) == offsetof(sj::TuneState, coef) + 20, "layout");
+  static_assert(offsetof(sj::TuneState, n_cand) ==
+                    offsetof(sj::TuneState, coef) + 4 * SJ_COST_TERMS, "layout");
   static_assert(offsetof(sj::TuneState, cand) == offsetof(sj::TuneState, n_cand) + 4, "layout");
   sj::TuneState *ts = s->B.tune;
   hipError_t e = hipMemcpyAsync(ts->w, d_w, 4545 * sizeof(uint16_t), hipMemcpyDeviceToDevice,

@@ -264,8 +264,8 @@ __device__ __forceinline__ float overlap_frac(const Ctl *ctl, const uint32_t *ls
 constexpr int kMaxCand = 8;
 struct TuneState {
   uint16_t w[4548];          // BF16 MLP parameters (4545 used)
-  float coef[5];             // cost = c0 * sum exp(mlp) + c1 |Q_I| + c2 |Q_C| + c3 leaves
-                             //        + c4 * max exp(mlp)
+  float coef[6];             // cost = c0 * sum exp(mlp) + c1 |Q_I| + c2 |Q_C| + c3 leaves
+                             //        + c4 * max exp(mlp) + c5 * sort passes * objects
   uint32_t n_cand;
   uint32_t cand[kMaxCand];   // candidate thresholds
   float cost[kMaxCand];      // predicted cost per candidate (inf: infeasible)

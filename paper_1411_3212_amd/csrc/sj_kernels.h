@@ -36,6 +36,8 @@ struct Bufs {
   uint32_t *tasks, *tkey, *tasks2, *tkey2;  // join tasks (TCAP)
   uint2 *vtask;                         // further chunks of heavy leaves: (leaf, chunk)
   uint32_t *xbase;                      // per leaf: task index of its second chunk
+  uint4 *trec;                          // tasks in run order: subquery and object ranges
+  uint32_t *tleaf;                      // tasks in run order: leaf
   // queries and subqueries
   float4 *qrect;
   uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;
@@ -64,14 +66,14 @@ void launch_leaves(const Bufs &B, hipStream_t s);
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s);
-const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
-                                hipStream_t s);
+void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
+                     hipStream_t s);
 // Task keys from the cost model's predicted task times (learned schedule).
 void launch_schedule_mlp(const Bufs &B, hipStream_t s);
-void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s);
+void launch_join_count(const Bufs &B, hipStream_t s);
 void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
                       hipStream_t s);
-void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s);
+void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s);
 // Trial builds and splits at every candidate threshold, cost prediction,
 // and the choice of the threshold that the tick's build then uses.
 void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,

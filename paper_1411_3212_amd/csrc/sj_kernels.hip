@@ -866,9 +866,25 @@ __device__ __forceinline__ void task_range(uint32_t e, uint32_t n_leaves, const 
   *se = end < b + kTaskSub ? end : b + kTaskSub;
 }
 
-__global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint32_t *tasks,
-                                                       const uint2 *vtask,
-                                                       const uint32_t *leaf_beg,
+// Task records in run order: (first subquery, end, first object, end) and
+// the leaf, so that a join wave starts a task with one load.
+__global__ void __launch_bounds__(kBlock) k_task_recs(const Ctl *ctl, const uint32_t *tasks,
+                                                      const uint2 *vtask,
+                                                      const uint32_t *leaf_sqoff,
+                                                      const uint32_t *leaf_beg, uint4 *trec,
+                                                      uint32_t *tleaf) {
+  if (!ctl->go_split) return;
+  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nt; t += gridDim.x * kBlock) {
+    uint32_t leaf, sb, se;
+    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+    trec[t] = make_uint4(sb, se, leaf_beg[leaf], leaf_beg[leaf + 1]);
+    tleaf[t] = leaf;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint4 *trec,
+                                                       const uint32_t *tleaf,
                                                        const uint32_t *leaf_sqoff,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
                                                        const float4 *qrect, const float2 *sxy,
@@ -876,16 +892,16 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
                                                        const uint32_t *lstart,
                                                        const uint32_t *llevel) {
   if (!ctl->go_split) return;
-  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
+  const uint32_t nt = ctl->n_entries;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    uint32_t leaf, sb, se;
-    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+    const uint4 tr = trec[t];
+    const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
     if (sb >= se) continue;
-    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
+    const uint32_t leaf = tlog ? tleaf[t] : 0u;
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     float ovl = 0.0f;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
@@ -963,10 +979,8 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
   ctl->want_rebuild = policy == 0u && (leaf_big || moved_out || periodic || !ctl->built);
 }
 
-__global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t *tasks,
-                                                       const uint2 *vtask,
-                                                       const uint32_t *leaf_beg,
-                                                       const uint32_t *leaf_sqoff,
+__global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
+                                                       const uint32_t *tleaf,
                                                        const uint32_t *sq_q, const uint32_t *sq_s,
                                                        const float4 *qrect, const float2 *sxy,
                                                        const uint32_t *sid,
@@ -982,16 +996,16 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint32_t 
     ctl->tick += 1;
   }
   if (!go) return;
-  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
+  const uint32_t nt = ctl->n_entries;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    uint32_t leaf, sb, se;
-    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+    const uint4 tr = trec[t];
+    const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
     if (sb >= se) continue;
-    const uint32_t ob = leaf_beg[leaf], oe = leaf_beg[leaf + 1];
+    const uint32_t leaf = tlog ? tleaf[t] : 0u;
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
@@ -1205,21 +1219,26 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
          (const uint32_t *)B.leaf_sqoff, B.leaf_nsq, B.sq_q, B.sq_s, B.cov_leaf, covering, B.red);
 }
 
-const uint32_t *launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
-                                hipStream_t s) {
+void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
+                     hipStream_t s) {
   LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, B.ctl, (const uint32_t *)B.leaf_beg,
          (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks,
          B.vtask, B.xbase, B.TCAP, B.red, B.tlog);
-  if (!reorder) return B.tasks;
-  if (learned) launch_schedule_mlp(B, s);
-  const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_entries,
-                                    &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
-  return alt ? B.tasks2 : B.tasks;
+  const uint32_t *order = B.tasks;
+  if (reorder) {
+    if (learned) launch_schedule_mlp(B, s);
+    const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_entries,
+                                      &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
+    order = alt ? B.tasks2 : B.tasks;
+  }
+  LAUNCH(k_task_recs, grid_for(B.TCAP, 4096), kBlock, s, (const Ctl *)B.ctl, order,
+         (const uint2 *)B.vtask, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.leaf_beg,
+         B.trec, B.tleaf);
 }
 
-void launch_join_count(const Bufs &B, const uint32_t *tasks, hipStream_t s) {
-  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, tasks, (const uint2 *)B.vtask,
-         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
+void launch_join_count(const Bufs &B, hipStream_t s) {
+  LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint4 *)B.trec,
+         (const uint32_t *)B.tleaf, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
          (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
          B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel);
 }
@@ -1234,10 +1253,9 @@ void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t
   mscan_down(jobs, 1, (const uint64_t *)B.part, &B.ctl->go_split, s);
 }
 
-void launch_join_write(const Bufs &B, const uint32_t *tasks, uint32_t nq, hipStream_t s) {
-  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, tasks, (const uint2 *)B.vtask,
-         (const uint32_t *)B.leaf_beg,
-         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
+void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
+  LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, (const uint4 *)B.trec,
+         (const uint32_t *)B.tleaf, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
          (const float4 *)B.qrect, (const float2 *)B.sxy, (const uint32_t *)B.valA,
          (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
 }

@@ -8,9 +8,10 @@
 // sum over leaves is the join's work, and the prediction for a leaf of at
 // most kTaskSub subqueries (one join task, one wave) bounds its critical
 // path through the largest such value; the split and the leaf passes add
-// terms linear in
-// |Q_I|, |Q_C| and the number of leaves.  The cheapest candidate is then
-// built for the tick.  The paper fixes the threshold by hand after a sweep
+// terms linear in |Q_I|, |Q_C| and the number of leaves, and the sort of
+// the ticks that keep the tree a term per radix pass over the objects (leaf
+// keys take fewer passes when there are fewer leaves).  The cheapest
+// candidate is then built for the tick.  The paper fixes the threshold by hand after a sweep
 // (Experimental evaluation, S5); this replaces the sweep, and the results
 // of a tick do not depend on it.
 //
@@ -224,9 +225,13 @@ __global__ void __launch_bounds__(kChunkBlocks) k_tune_cost(const Ctl *ctl, Tune
     m = ldm[w] > m ? ldm[w] : m;
   }
   const bool ok = ctl->go_split && !(ctl->err & kErrOverflow);
+  // radix passes of the leaf-keyed sort on the ticks that keep this tree
+  const uint32_t nl = ctl->n_leaves;
+  const uint32_t passes = nl > 1u ? (32u - (uint32_t)__clz((int)(nl - 1u)) + 7u) / 8u : 0u;
   const double cost = (double)ts->coef[0] * s + (double)ts->coef[1] * (double)ctl->n_isect +
-                      (double)ts->coef[2] * (double)ctl->n_cov +
-                      (double)ts->coef[3] * (double)ctl->n_leaves + (double)ts->coef[4] * m;
+                      (double)ts->coef[2] * (double)ctl->n_cov + (double)ts->coef[3] * (double)nl +
+                      (double)ts->coef[4] * m +
+                      (double)ts->coef[5] * (double)passes * (double)ctl->n_present;
   ts->cost[c] = ok ? (float)cost : INFINITY;
   ts->msum[c] = (float)s;
   ts->mmax[c] = (float)m;

@@ -11,7 +11,7 @@ def test_committed_model_is_well_formed():
     assert bits.dtype == np.uint16 and len(bits) == 4545
     vals = (bits.astype(np.uint32) << 16).view(np.float32)
     assert np.isfinite(vals).all() and np.abs(vals).max() < 1e3
-    assert len(m["coef"]) == 5 and all(c >= 0 for c in m["coef"]) and any(m["coef"])
+    assert len(m["coef"]) == 6 and all(c >= 0 for c in m["coef"]) and any(m["coef"])
     assert 1 <= len(m["cand"]) <= 8 and all(c >= 1 for c in m["cand"])
     assert m["cand"] == sorted(m["cand"])
     tr = m["doc"]["training"]

@@ -16,7 +16,7 @@ from gpu_util import (gpu_count_hash, gpu_tick, oracle_apply, oracle_count_hash,
 pytestmark = pytest.mark.gpu
 
 CAND = [4, 8, 16, 32, 64, 128, 256]
-COEF = (1.0, 0.02, 0.01, 0.05, 3.0)
+COEF = (1.0, 0.02, 0.01, 0.05, 3.0, 1e-4)
 
 
 @pytest.fixture(scope="module", autouse=True)

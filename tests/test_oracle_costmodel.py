@@ -52,10 +52,10 @@ def test_features_of_a_hand_built_scene():
     codes, _ = oracle.sorted_codes(st, fr)
     lv = oracle.quadtree(codes, 2, 16)
     assert list(lv.lvl) == [1, 1, 1, 1] and list(lv.count) == [2, 1, 0, 2]
-    feats, n_isect, n_cov, L = costmodel.candidate_terms(live, rects, fr, lv)
+    feats, n_isect, n_cov, L, n_obj = costmodel.candidate_terms(live, rects, fr, lv)
     # the query's y range ends on the first cell row of the top leaves: it
     # intersects TL (empty, inactive) and TR with zero area
-    assert (n_isect, n_cov, L) == (3, 0, 4)
+    assert (n_isect, n_cov, L, n_obj) == (3, 0, 4, 5)
     want = np.array([[np.log2(3), 1.0, 1 / 16, 0.5],    # BL: half its width, full height
                      [1.0, 1.0, 1 / 16, 0.5],           # BR
                      [np.log2(3), 1.0, 1 / 16, 0.0]])   # TR: touches along an edge
@@ -68,11 +68,12 @@ def test_cost_of_a_constant_network(k):
     st, live, rects = hand_scene()
     p = np.zeros(mlp.P)
     p[-1] = np.log(k)
-    coef = (2.0, 3.0, 5.0, 7.0, 11.0)
+    coef = (2.0, 3.0, 5.0, 7.0, 11.0, 13.0)
     costs, sums, chosen = costmodel.choose(st, live, rects, p, coef, [8, 2])
     # th 2: the hand scene; th 8: the same tree, since the root is always split
     assert np.allclose(sums, 3 * k)
-    assert np.allclose(costs, 2 * 3 * k + 3 * 3 + 5 * 0 + 7 * 4 + 11 * k)
+    # 4 leaves: keys below 4 take one radix pass over the 5 objects
+    assert np.allclose(costs, 2 * 3 * k + 3 * 3 + 5 * 0 + 7 * 4 + 11 * k + 13 * 1 * 5)
     assert chosen == 8  # the first of equal costs
 
 
@@ -87,7 +88,13 @@ def test_critical_path_term_caps_the_subqueries_of_a_task():
     p[4544] = np.log(0.01)
     feats = np.array([[np.log2(11.0), np.log2(101.0), 0.5, 0.3],    # 10 objects, 100 subqueries
                       [np.log2(3.0), np.log2(5.0), 0.25, 1.0]])     # 2 objects, 4 subqueries
-    c, s = costmodel.cost(p, (1.0, 0.0, 0.0, 0.0, 0.0), feats, 0, 0, 0)
+    c, s = costmodel.cost(p, (1.0, 0.0, 0.0, 0.0, 0.0, 0.0), feats, 0, 0, 0)
     assert np.isclose(s, 0.01 * (11 * 101 + 3 * 5)) and np.isclose(c, s)
-    c, _ = costmodel.cost(p, (0.0, 0.0, 0.0, 0.0, 1.0), feats, 0, 0, 0)
+    c, _ = costmodel.cost(p, (0.0, 0.0, 0.0, 0.0, 1.0, 0.0), feats, 0, 0, 0)
     assert np.isclose(c, 0.01 * 11 * 65)
+
+
+@pytest.mark.parametrize("leaves,passes", [(0, 0), (1, 0), (2, 1), (256, 1), (257, 2),
+                                           (65536, 2), (65537, 3), (1 << 24, 3), ((1 << 24) + 1, 4)])
+def test_sort_passes(leaves, passes):
+    assert costmodel.sort_passes(leaves) == passes
