@@ -182,6 +182,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.leaf_beg = c.take<uint32_t>(L + 1);
   b.leaf_nsq = c.take<uint32_t>(L);
   b.leaf_sqoff = c.take<uint32_t>(L + 1);
+  b.leaf_ovf = c.take<uint32_t>(L);
+  b.leaf_ovfc = c.take<uint32_t>(L);
   // join tasks: one per leaf and one per further kTaskSub subqueries of a leaf
   const uint64_t T = (uint64_t)L + d.S / sj::kTaskSub + 1u;
   b.tasks = c.take<uint32_t>(T);
@@ -200,8 +202,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.q_coff = c.take<uint32_t>(Q + 1);
   b.q_roff = c.take<uint64_t>(Q + 1);
   b.qlist = c.take<uint32_t>(Q * d.slots);
-  b.sq_q = c.take<uint32_t>(d.S);
-  b.sq_s = c.take<uint32_t>(d.S);
+  b.qpos = c.take<uint32_t>(Q * d.slots);
+  b.sq = c.take<uint2>(d.S);
   b.sq_cnt = c.take<uint32_t>(d.S);
   b.res_off = c.take<uint64_t>(d.S + 1);
   b.cov_leaf = c.take<uint32_t>(d.C);

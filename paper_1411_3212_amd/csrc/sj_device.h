@@ -218,6 +218,7 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *a, uint32_t 
 constexpr int kMaxScanJobs = 3;
 struct ScanJob {
   const uint32_t *in;
+  const uint32_t *in2;    // optional second input, added element-wise
   void *out;
   const uint32_t *n_dev;  // element count in device memory, or
   uint32_t n_host;        // this value when n_dev is null
@@ -228,6 +229,9 @@ struct ScanJobs {
 };
 
 __device__ __forceinline__ uint32_t job_n(const ScanJob &j) { return j.n_dev ? *j.n_dev : j.n_host; }
+__device__ __forceinline__ uint32_t job_in(const ScanJob &j, uint64_t i) {
+  return j.in2 ? j.in[i] + j.in2[i] : j.in[i];
+}
 __device__ __forceinline__ void job_store(const ScanJob &j, uint64_t i, uint64_t v) {
   if (j.out64)
     ((uint64_t *)j.out)[i] = v;

@@ -8,7 +8,8 @@
 
 namespace sj {
 
-ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host);
+ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host,
+                const uint32_t *in2 = nullptr);
 ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32_t n_host);
 
 // Exclusive scans of up to kMaxScanJobs arrays (out[n] = total).  The full

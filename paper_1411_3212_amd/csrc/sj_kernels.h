@@ -32,6 +32,7 @@ struct Bufs {
   uint4 *nodes;
   uint32_t *table;                      // start table (4^tcap entries)
   uint32_t *leaf_beg, *leaf_nsq, *leaf_sqoff;
+  uint32_t *leaf_ovf, *leaf_ovfc;       // subqueries past a query's list: count, cursor
   // schedule
   uint32_t *tasks, *tkey, *tasks2, *tkey2;  // join tasks (TCAP)
   uint2 *vtask;                         // further chunks of heavy leaves: (leaf, chunk)
@@ -43,7 +44,9 @@ struct Bufs {
   uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;
   uint64_t *q_roff;
   uint32_t *qlist;                      // visited leaves per query (slots each)
-  uint32_t *sq_q, *sq_s, *sq_cnt;
+  uint32_t *qpos;                       // their positions in the leaves' groups
+  uint2 *sq;                            // subqueries grouped by leaf: (query, slot)
+  uint32_t *sq_cnt;
   uint64_t *res_off;
   uint32_t *cov_leaf, *res_ids;
   float *tlog;                          // per-leaf timing log (or null)

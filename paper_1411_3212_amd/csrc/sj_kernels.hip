@@ -497,12 +497,15 @@ __global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const ui
 // (first code >= the leaf's start), leaf indices otherwise.
 __global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const uint32_t *keys,
                                                         const uint32_t *lstart, uint32_t *leaf_beg,
-                                                        uint32_t *leaf_nsq) {
+                                                        uint32_t *leaf_nsq, uint32_t *leaf_ovf,
+                                                        uint32_t *leaf_ovfc) {
   const uint32_t n = ctl->n_leaves, np = ctl->n_present;
   const bool by_code = ctl->rebuild != 0;
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
     leaf_beg[t] = lower_bound_u32(keys, 0u, np, by_code ? lstart[t] : t);
     leaf_nsq[t] = 0u;
+    leaf_ovf[t] = 0u;
+    leaf_ovfc[t] = 0u;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) leaf_beg[n] = np;
 }
@@ -638,7 +641,7 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const uint32_t *qid, const float *xa, const float *ya, const float *xb,
     const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *leaf_nsq,
-    uint32_t *qlist, uint32_t slots, uint32_t covering) {
+    uint32_t *leaf_ovf, uint32_t *qlist, uint32_t *qpos, uint32_t slots, uint32_t covering) {
   __shared__ uint32_t stack[kFine * kBlock];
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
@@ -648,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     bool bad_rect = false;
     if (k < nq) {
       uint32_t ni = 0, nc = 0, nl = 0;
-      uint32_t *lst = qlist + (uint64_t)k * slots;
+      uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
       const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
       qrect[k] = r;
       QBox q;
@@ -660,12 +663,28 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
             ++nc;
           } else {
             ++ni;
-            atomicAdd(&leaf_nsq[leaf], 1u);
+            // subqueries past the list get a position after the leaf's other
+            // subqueries in the write pass
+            if (nl >= slots) atomicAdd(&leaf_ovf[leaf], 1u);
           }
           if (nl < slots) lst[nl] = leaf | (c ? kLeafBit : 0u);
           ++nl;
         };
         for_each_leaf(tr, stack + threadIdx.x, q, visit);
+        // positions of the listed subqueries in their leaves' groups, eight
+        // independent atomics in flight at a time
+        const uint32_t m = nl < slots ? nl : slots;
+        for (uint32_t i0 = 0; i0 < m; i0 += 8u) {
+          uint32_t e[8], r[8];
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j) e[j] = i0 + j < m ? lst[i0 + j] : kLeafBit;
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j)
+            r[j] = (e[j] & kLeafBit) ? 0u : atomicAdd(&leaf_nsq[e[j]], 1u);
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j)
+            if (!(e[j] & kLeafBit)) pos[i0 + j] = r[j];
+        }
       }
       q_ni[k] = ni;
       q_nc[k] = nc;
@@ -705,9 +724,9 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
 __global__ void __launch_bounds__(kBlock) k_q_write(
     Ctl *ctl, const uint32_t *qid, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
-    const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, uint32_t slots,
-    const uint32_t *leaf_sqoff, uint32_t *leaf_nsq, uint32_t *sq_q, uint32_t *sq_s,
-    uint32_t *cov_leaf, uint32_t covering, uint64_t *red) {
+    const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, const uint32_t *qpos,
+    uint32_t slots, const uint32_t *leaf_sqoff, const uint32_t *leaf_nsq, uint32_t *leaf_ovfc,
+    uint2 *sq, uint32_t *cov_leaf, uint32_t covering, uint64_t *red) {
   __shared__ uint32_t stack[kFine * kBlock];
   __shared__ uint64_t lds[kWavesPerBlock];
   uint64_t covp = 0;
@@ -717,22 +736,44 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
       const uint32_t n = q_ni[k] + q_nc[k];
       if (n == 0) continue;
-      uint32_t wi = q_ioff[k], wc = q_coff[k];
+      uint32_t wi = q_ioff[k], wc = q_coff[k], i = 0;
+      const uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      // i-th leaf of the query's walk (the count pass walked in the same order)
       auto emit = [&](uint32_t leaf, bool c) {
         if (c) {
           cov_leaf[wc++] = leaf;
           covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
         } else {
-          const uint32_t slot = leaf_sqoff[leaf] + atomicSub(&leaf_nsq[leaf], 1u) - 1u;
-          sq_q[slot] = k;
-          sq_s[slot] = wi++;
+          const uint32_t p =
+              i < slots ? pos[i] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
+          sq[leaf_sqoff[leaf] + p] = make_uint2(k, wi++);
         }
+        ++i;
       };
       if (n <= slots) {
-        const uint32_t *lst = qlist + (uint64_t)k * slots;
-        for (uint32_t i = 0; i < n; ++i) {
-          const uint32_t e = lst[i];
-          emit(e & ~kLeafBit, (e & kLeafBit) != 0);
+        // eight entries at a time: their loads are independent
+        for (uint32_t j0 = 0; j0 < n; j0 += 8u) {
+          uint32_t e[8], p[8], off[8];
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j) {
+            const bool v = j0 + j < n;
+            e[j] = v ? lst[j0 + j] : kLeafBit;
+            p[j] = v ? pos[j0 + j] : 0u;
+          }
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j)
+            off[j] = (e[j] & kLeafBit) ? 0u : leaf_sqoff[e[j]];
+#pragma unroll
+          for (uint32_t j = 0; j < 8u; ++j) {
+            if (j0 + j >= n) continue;
+            const uint32_t leaf = e[j] & ~kLeafBit;
+            if (e[j] & kLeafBit) {
+              cov_leaf[wc++] = leaf;
+              covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
+            } else {
+              sq[off[j] + p[j]] = make_uint2(k, wi++);
+            }
+          }
         }
       } else {
         QBox q;
@@ -885,8 +926,7 @@ __global__ void __launch_bounds__(kBlock) k_task_recs(const Ctl *ctl, const uint
 
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint4 *trec,
                                                        const uint32_t *tleaf,
-                                                       const uint32_t *leaf_sqoff,
-                                                       const uint32_t *sq_q, const uint32_t *sq_s,
+                                                       const uint32_t *leaf_sqoff, const uint2 *sq,
                                                        const float4 *qrect, const float2 *sxy,
                                                        uint32_t *sq_cnt, float *tlog,
                                                        const uint32_t *lstart,
@@ -909,8 +949,9 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
       uint32_t slot = 0, cnt = 0;
       if (lane < nk) {
-        slot = sq_s[sc + lane];
-        r = qrect[sq_q[sc + lane]];
+        const uint2 e = sq[sc + lane];
+        slot = e.y;
+        r = qrect[e.x];
         if (tlog) ovl += overlap_frac(ctl, lstart, llevel, leaf, r);
       }
       for (uint32_t o = ob; o < oe; o += kWave) {
@@ -980,8 +1021,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
 }
 
 __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
-                                                       const uint32_t *tleaf,
-                                                       const uint32_t *sq_q, const uint32_t *sq_s,
+                                                       const uint32_t *tleaf, const uint2 *sq,
                                                        const float4 *qrect, const float2 *sxy,
                                                        const uint32_t *sid,
                                                        const uint64_t *res_off, uint32_t *res_ids,
@@ -1012,8 +1052,9 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
       float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
       uint64_t off = 0;
       if (lane < nk) {
-        off = res_off[sq_s[sc + lane]];
-        r = qrect[sq_q[sc + lane]];
+        const uint2 e = sq[sc + lane];
+        off = res_off[e.y];
+        r = qrect[e.x];
       }
       for (uint32_t o = ob; o < oe; o += kWave) {
         const bool has = o + lane < oe;
@@ -1196,7 +1237,8 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
 
 void launch_leaves(const Bufs &B, hipStream_t s) {
   LAUNCH(k_leaf_ranges, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
-         (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg, B.leaf_nsq);
+         (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg, B.leaf_nsq, B.leaf_ovf,
+         B.leaf_ovfc);
 }
 
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
@@ -1204,19 +1246,20 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
                   hipStream_t s) {
   LAUNCH(k_q_count, grid_for(nq, 4096), kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
          (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
-         B.q_nc, B.leaf_nsq, B.qlist, B.slots, covering);
+         B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering);
   ScanJobs jobs{};
   jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
   jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
-  jobs.j[2] = job_u32(B.leaf_nsq, B.leaf_sqoff, &B.ctl->n_leaves, 0);
+  jobs.j[2] = job_u32(B.leaf_nsq, B.leaf_sqoff, &B.ctl->n_leaves, 0, B.leaf_ovf);
   mscan_reduce(jobs, 3, B.part, nullptr, s);
   LAUNCH(k_split_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, B.S, B.C);
   mscan_down(jobs, 3, (const uint64_t *)B.part, nullptr, s);
   LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, qid, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
-         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots,
-         (const uint32_t *)B.leaf_sqoff, B.leaf_nsq, B.sq_q, B.sq_s, B.cov_leaf, covering, B.red);
+         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, (const uint32_t *)B.qpos, B.slots,
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.leaf_nsq, B.leaf_ovfc, B.sq,
+         B.cov_leaf, covering, B.red);
 }
 
 void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
@@ -1238,8 +1281,8 @@ void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learn
 
 void launch_join_count(const Bufs &B, hipStream_t s) {
   LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint4 *)B.trec,
-         (const uint32_t *)B.tleaf, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
-         (const uint32_t *)B.sq_s, (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
+         (const uint32_t *)B.tleaf, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
+         (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
          B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel);
 }
 
@@ -1255,8 +1298,8 @@ void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t
 
 void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
   LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, (const uint4 *)B.trec,
-         (const uint32_t *)B.tleaf, (const uint32_t *)B.sq_q, (const uint32_t *)B.sq_s,
-         (const float4 *)B.qrect, (const float2 *)B.sxy, (const uint32_t *)B.valA,
+         (const uint32_t *)B.tleaf, (const uint2 *)B.sq, (const float4 *)B.qrect,
+         (const float2 *)B.sxy, (const uint32_t *)B.valA,
          (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
 }
 

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kBlock) k_mscan_reduce(ScanJobs jobs, uint64_t
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   uint64_t s = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += j.in[i];
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += job_in(j, i);
   s = wave_sum(s);
   if (lane_id() == 0) lds[threadIdx.x / kWave] = s;
   __syncthreads();
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_mscan_down(ScanJobs jobs, const uint
   uint64_t run = part[blockIdx.y * kChunkBlocks + blockIdx.x];
   for (uint64_t t0 = b0; t0 < b1; t0 += kBlock) {
     const uint64_t i = t0 + threadIdx.x;
-    const uint64_t v = i < b1 ? j.in[i] : 0;
+    const uint64_t v = i < b1 ? job_in(j, i) : 0;
     uint64_t tot;
     const uint64_t ex = block_excl_scan<uint64_t, kBlock>(v, lds, &tot);
     if (i < b1) job_store(j, i, run + ex);
@@ -102,11 +102,12 @@ void mscan(const ScanJobs &jobs, int njobs, uint64_t *part, const uint32_t *gate
   mscan_down(jobs, njobs, part, gate, s);
 }
 
-ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host) {
-  return ScanJob{in, out, n_dev, n_host, 0u};
+ScanJob job_u32(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint32_t n_host,
+                const uint32_t *in2) {
+  return ScanJob{in, in2, out, n_dev, n_host, 0u};
 }
 ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32_t n_host) {
-  return ScanJob{in, out, n_dev, n_host, 1u};
+  return ScanJob{in, nullptr, out, n_dev, n_host, 1u};
 }
 
 // ----------------------------------------------------------- radix sort --

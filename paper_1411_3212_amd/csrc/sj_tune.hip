@@ -95,11 +95,11 @@ __device__ __forceinline__ float wave_mlp(const MlpLds &m, float x0, float x1, f
 // of the leaf's area their rectangle covers (whole wave).
 __device__ __forceinline__ float mean_overlap(const Ctl *ctl, const uint32_t *lstart,
                                               const uint32_t *llevel, uint32_t t, uint32_t sb,
-                                              uint32_t se, const uint32_t *sq_q,
+                                              uint32_t se, const uint2 *sq,
                                               const float4 *qrect) {
   float ov = 0.0f;
   for (uint32_t i = sb + lane_id(); i < se; i += kWave)
-    ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq_q[i]]);
+    ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq[i].x]);
   return wave_sum(ov) / (float)(se - sb);
 }
 
@@ -109,7 +109,7 @@ __device__ __forceinline__ float mean_overlap(const Ctl *ctl, const uint32_t *ls
 __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const TuneState *ts,
                                                         const uint32_t *leaf_beg,
                                                         const uint32_t *leaf_sqoff,
-                                                        const uint32_t *sq_q, const float4 *qrect,
+                                                        const uint2 *sq, const float4 *qrect,
                                                         const uint32_t *lstart,
                                                         const uint32_t *llevel, uint64_t *red) {
   __shared__ MlpLds m;
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
       const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
       const uint32_t sb = leaf_sqoff[t], se = leaf_sqoff[t + 1];
       if (cnt == 0 || sb == se) continue;
-      const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq_q, qrect);
+      const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq, qrect);
       const uint32_t nsq = se - sb;
       const float x0 = log2f(1.0f + (float)cnt);
       const float x2 = (float)llevel[t] * (1.0f / 16.0f);
@@ -168,7 +168,7 @@ __device__ __forceinline__ uint32_t time_key(float y) {
 __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const TuneState *ts,
                                                           const uint32_t *leaf_beg,
                                                           const uint32_t *leaf_sqoff,
-                                                          const uint32_t *sq_q,
+                                                          const uint2 *sq,
                                                           const float4 *qrect,
                                                           const uint32_t *lstart,
                                                           const uint32_t *llevel,
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const 
     const uint32_t cnt = leaf_beg[t + 1] - leaf_beg[t];
     const uint32_t sb = leaf_sqoff[t], se = leaf_sqoff[t + 1];
     if (cnt == 0 || sb == se) continue;
-    const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq_q, qrect);
+    const float ov = mean_overlap(ctl, lstart, llevel, t, sb, se, sq, qrect);
     const uint32_t nsq = se - sb, more = (nsq - 1u) / kTaskSub;
     const float x0 = log2f(1.0f + (float)cnt);
     const float x2 = (float)llevel[t] * (1.0f / 16.0f);
@@ -258,7 +258,7 @@ __global__ void k_tune_pick(Ctl *ctl, TuneState *ts, uint4 *front0) {
 
 void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
   LAUNCH(k_task_keys_mlp, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
-         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
+         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
          (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel,
          (const uint32_t *)B.xbase, B.TCAP, B.tkey);
 }
@@ -273,7 +273,7 @@ void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t 
     launch_leaves(B, s);
     launch_split(B, qid, xa, ya, xb, yb, nq, covering, s);
     LAUNCH(k_cost_leaves, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
-           (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq_q,
+           (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
            (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.red);
     LAUNCH(k_tune_cost, 1, kChunkBlocks, s, (const Ctl *)B.ctl, B.tune, c,
            (const uint64_t *)B.red);
