@@ -365,8 +365,9 @@ typedef struct sj_served {
   uint32_t scene_id;
   int32_t status;               /* SJ_OK or the tick's error */
   uint32_t nq;
-  const uint64_t *d_count;      /* [nq] result sizes        (valid until the */
-  const uint64_t *d_hash;       /* [nq] pair-set hashes      scene's next tick */
+  const uint64_t *d_count;      /* [nq] result sizes        (SJ_SERVE_DIGEST, else */
+  const uint64_t *d_hash;       /* [nq] pair-set hashes      NULL; valid until the
+                                   scene's next tick */
   const uint64_t *d_counters;   /* [8] as sj_tick_counters   after this one is */
 } sj_served;                    /*                           retired by a poll) */
 
@@ -394,13 +395,17 @@ int sj_server_retire(sj_server *server, uint32_t scene_id);
 /* Queues a tick for a scene: device inputs as sj_apply_updates + sj_run_tick
  * (they must stay valid until the tick is retired); tags must be unique per
  * scene.  d_record (device, 10 u64, may be NULL) receives the tick's record
- * when it finishes: the 8 counters of sj_tick_counters, then the sum of the
- * per-query pair-set hashes and the sum of the result sizes (mod 2^64).
- * Non-blocking. */
+ * when it finishes: the 8 counters of sj_tick_counters, then (with
+ * SJ_SERVE_DIGEST, else 0, 0) the sum of the per-query pair-set hashes and
+ * the sum of the result sizes (mod 2^64).  SJ_SERVE_DIGEST also makes the
+ * per-query counts and hashes of sj_served available; it reads every result,
+ * so it is for checking, not for serving.  Non-blocking. */
+#define SJ_SERVE_DIGEST 1u
 int sj_server_submit(sj_server *server, uint32_t scene_id, const uint32_t *d_id,
                      const float *d_x, const float *d_y, uint32_t m, const uint32_t *d_qid,
                      const float *d_xa, const float *d_ya, const float *d_xb,
-                     const float *d_yb, uint32_t nq, uint64_t tag, uint64_t *d_record);
+                     const float *d_yb, uint32_t nq, uint64_t tag, uint64_t *d_record,
+                     uint32_t flags);
 
 /* Retires finished ticks (at most cap, written to done[0 .. *n_done)) and
  * starts queued ticks in submission order.  Non-blocking. */

@@ -114,7 +114,7 @@ EXPORTS = {
     "sj_server_retire": (c_int, [c_void_p, c_uint32]),
     "sj_server_submit": (c_int, [c_void_p, c_uint32, c_void_p, c_void_p, c_void_p, c_uint32,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
-                                 c_uint64, c_void_p]),
+                                 c_uint64, c_void_p, c_uint32]),
     "sj_server_poll": (c_int, [c_void_p, POINTER(SjServed), c_uint32, POINTER(c_uint32)]),
     "sj_server_info": (c_int, [c_void_p, POINTER(SjServerStats)]),
     "sj_server_scene": (c_int, [c_void_p, c_uint32, POINTER(c_void_p)]),
@@ -443,13 +443,15 @@ class Server:
         self._check(self._lib.sj_server_retire(self.handle, sid))
         self._keep.pop(sid, None)
 
-    def submit(self, sid: int, tag: int, ids, x, y, qid, xa, ya, xb, yb, record=None):
+    def submit(self, sid: int, tag: int, ids, x, y, qid, xa, ya, xb, yb, record=None,
+               digest: bool = False):
         """record: optional int64 CUDA tensor view of 10 elements receiving
-        the tick's counters and result digest."""
+        the tick's counters and (with digest) the result digest."""
         m, nq = ids.numel(), qid.numel()
         self._check(self._lib.sj_server_submit(self.handle, sid, _ptr(ids), _ptr(x), _ptr(y), m,
                                                _ptr(qid), _ptr(xa), _ptr(ya), _ptr(xb),
-                                               _ptr(yb), nq, tag, _ptr(record)))
+                                               _ptr(yb), nq, tag, _ptr(record),
+                                               1 if digest else 0))
 
     def poll(self):
         """Finished ticks: list of (scene, tag, status, nq, count_ptr,

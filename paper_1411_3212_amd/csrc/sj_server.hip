@@ -84,6 +84,7 @@ struct PoolAlloc {
 struct Request {
   uint64_t tag;
   uint64_t *record;
+  bool digest;
   const uint32_t *id;
   const float *x, *y;
   uint32_t m;
@@ -291,7 +292,7 @@ int sj_server_retire(sj_server *s, uint32_t id) {
 int sj_server_submit(sj_server *s, uint32_t id, const uint32_t *d_id, const float *d_x,
                      const float *d_y, uint32_t m, const uint32_t *d_qid, const float *d_xa,
                      const float *d_ya, const float *d_xb, const float *d_yb, uint32_t nq,
-                     uint64_t tag, uint64_t *d_record) {
+                     uint64_t tag, uint64_t *d_record, uint32_t flags) {
   if (!s || id >= s->scenes.size() || !s->scenes[id].live) return SJ_EINVAL;
   ServedScene &sc = s->scenes[id];
   if (m > sc.max_updates || nq > sc.max_queries)
@@ -299,7 +300,10 @@ int sj_server_submit(sj_server *s, uint32_t id, const uint32_t *d_id, const floa
   if ((m && (!d_id || !d_x || !d_y)) || (nq && (!d_qid || !d_xa || !d_ya || !d_xb || !d_yb)))
     return srv_fail(s, SJ_EINVAL, "submit: null input");
   if ((uintptr_t)d_record & 7u) return srv_fail(s, SJ_EINVAL, "submit: misaligned record");
-  sc.queue.push_back(Request{tag, d_record, d_id, d_x, d_y, m, d_qid, d_xa, d_ya, d_xb, d_yb, nq});
+  if (flags & ~(uint32_t)SJ_SERVE_DIGEST) return srv_fail(s, SJ_EINVAL, "submit: unknown flags");
+  const bool digest = (flags & SJ_SERVE_DIGEST) != 0;
+  sc.queue.push_back(
+      Request{tag, d_record, digest, d_id, d_x, d_y, m, d_qid, d_xa, d_ya, d_xb, d_yb, nq});
   s->order.emplace_back(id, tag);
   return SJ_OK;
 }
@@ -326,15 +330,17 @@ static int start_tick(sj_server *s, uint32_t id) {
   int rc = sj_tick_graph(sc.scene, sc.s_id, sc.s_x, sc.s_y, r.m, sc.s_qid, sc.s_xa, sc.s_ya,
                          sc.s_xb, sc.s_yb, r.nq);
   const uint32_t b = sc.parity;
-  if (rc == SJ_OK) rc = sj_result_hashes(sc.scene, sc.o_cnt[b], sc.o_hash[b]);
+  if (rc == SJ_OK && r.digest) rc = sj_result_hashes(sc.scene, sc.o_cnt[b], sc.o_hash[b]);
   if (rc == SJ_OK) rc = sj_tick_counters(sc.scene, sc.o_counters[b]);
   if (rc == SJ_OK && r.record) {
     hipLaunchKernelGGL(k_record_init, dim3(1), dim3(1), 0, sc.stream,
                        (const uint64_t *)sc.o_counters[b], r.record);
-    const unsigned g = (unsigned)((r.nq + 1023) / 1024 < 256 ? (r.nq + 1023) / 1024 : 256);
-    hipLaunchKernelGGL(k_record_digest, dim3(g ? g : 1), dim3(256), 0, sc.stream,
-                       (const uint64_t *)sc.o_cnt[b], (const uint64_t *)sc.o_hash[b], r.nq,
-                       r.record);
+    if (r.digest) {
+      const unsigned g = (unsigned)((r.nq + 1023) / 1024 < 256 ? (r.nq + 1023) / 1024 : 256);
+      hipLaunchKernelGGL(k_record_digest, dim3(g ? g : 1), dim3(256), 0, sc.stream,
+                         (const uint64_t *)sc.o_cnt[b], (const uint64_t *)sc.o_hash[b], r.nq,
+                         r.record);
+    }
   }
   if (rc == SJ_OK) rc = sj_scene_ctl_to_host_async(sc.scene, sc.h_ctl);
   hipError_t e = hipEventRecord(sc.done, sc.stream);
@@ -369,8 +375,8 @@ int sj_server_poll(sj_server *s, sj_served *done, uint32_t cap, uint32_t *n_done
     d.scene_id = id;
     d.status = st;
     d.nq = sc.cur.nq;
-    d.d_count = sc.o_cnt[sc.parity];
-    d.d_hash = sc.o_hash[sc.parity];
+    d.d_count = sc.cur.digest ? sc.o_cnt[sc.parity] : nullptr;
+    d.d_hash = sc.cur.digest ? sc.o_hash[sc.parity] : nullptr;
     d.d_counters = sc.o_counters[sc.parity];
     sc.parity ^= 1u;
   }

@@ -119,10 +119,13 @@ def poisson_requests(n_scenes: int, n_requests: int, rate_per_scene: float, n_ti
 
 
 def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
-          keep_arrays: bool = False) -> dict:
+          keep_arrays: bool = False, digest: bool = False) -> dict:
     """Runs the requests in real time through a server.  Returns latencies,
-    per-request digests (pair count, sum of per-query pair-set hashes mod
-    2^64) and, with keep_arrays, the per-query count and hash arrays."""
+    per-request counters and, with digest (implied by keep_arrays),
+    per-request digests (sum of per-query pair-set hashes mod 2^64, pair
+    count) and, with keep_arrays, the per-query count and hash arrays.  The
+    digest reads every result, so it is for checking runs."""
+    digest = digest or keep_arrays
     srv = Server(pool_bytes, max_running)
     for s_ in {s for _, s, _ in requests}:
         need = srv.scene_bytes(specs[s_].cfg, specs[s_].max_updates)
@@ -166,7 +169,8 @@ def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
             while dq:
                 tag, k = dq.popleft()
                 buf, m, nq = specs[s].ticks[k]
-                srv.submit(sid_of[s], tag, *tick_views(buf, m, nq, torch), record=history[tag])
+                srv.submit(sid_of[s], tag, *tick_views(buf, m, nq, torch), record=history[tag],
+                           digest=digest)
         fin = srv.poll()
         tnow = time.perf_counter() - t0
         for sid, tag, status, nq, pc, ph, pk in fin:
@@ -255,6 +259,8 @@ def main(argv=None) -> int:
                     help="pool = this fraction of the free HBM (capped at --budget-gib)")
     ap.add_argument("--budget-gib", type=float, default=0.0)
     ap.add_argument("--max-running", type=int, default=4)
+    ap.add_argument("--digest", action="store_true",
+                    help="also hash every tick's result set (a checking run: reads all results)")
     args = ap.parse_args(argv)
     import torch
     specs = make_specs(args.scenes, nmin=args.nmin, nmax=args.nmax)
@@ -272,7 +278,7 @@ def main(argv=None) -> int:
     srv_probe = Server(1 << 20)
     need = [srv_probe.scene_bytes(sp.cfg, sp.max_updates) for sp in specs]
     srv_probe.close()
-    r = serve(specs, reqs, pool, args.max_running, torch)
+    r = serve(specs, reqs, pool, args.max_running, torch, digest=args.digest)
     lat = r["latency_ms"]
     out = {
         "metric": "tick serving: p50/p99 tick latency, ticks/s, result pairs/s",
@@ -283,7 +289,7 @@ def main(argv=None) -> int:
         "mean_tick_ms": float(lat.mean()),
         "ticks_per_s": len(reqs) / r["makespan_s"], "pairs_per_s": r["pairs"] / r["makespan_s"],
         "pool_gib": pool / 2**30, "scene_gib_total": sum(need) / 2**30,
-        "max_running": args.max_running, "generation_s": gen_s,
+        "max_running": args.max_running, "digest": args.digest, "generation_s": gen_s,
     }
     print(json.dumps(out), flush=True)
     return 0
