@@ -937,8 +937,10 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint4 tr = trec[t];
+    const uint4 tr = next;  // this task's record, loaded during the previous one
+    if (t + nwaves < nt) next = trec[t + nwaves];
     const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
     if (sb >= se) continue;
     const uint32_t leaf = tlog ? tleaf[t] : 0u;
@@ -1028,21 +1030,28 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
                                                        uint32_t nq, const uint32_t *q_ioff,
                                                        uint64_t *q_roff, float *tlog) {
   const bool go = ctl->go_join != 0;
-  // per-query offsets of the intersecting results
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
-    q_roff[k] = go ? res_off[k < nq ? q_ioff[k] : ctl->n32[0]] : 0ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->qry_seq += nq;
     ctl->tick += 1;
   }
-  if (!go) return;
+  // per-query offsets of the intersecting results, after this wave's tasks
+  auto query_offsets = [&]() {
+    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
+      q_roff[k] = go ? res_off[k < nq ? q_ioff[k] : ctl->n32[0]] : 0ull;
+  };
+  if (!go) {
+    query_offsets();
+    return;
+  }
   const uint32_t nt = ctl->n_entries;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
   for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint4 tr = trec[t];
+    const uint4 tr = next;  // this task's record, loaded during the previous one
+    if (t + nwaves < nt) next = trec[t + nwaves];
     const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
     if (sb >= se) continue;
     const uint32_t leaf = tlog ? tleaf[t] : 0u;
@@ -1074,6 +1083,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     if (tlog && lane == 0)
       atomicAdd(&tlog[(uint64_t)leaf * 8 + 5], (float)(__builtin_amdgcn_s_memrealtime() - clk0));
   }
+  query_offsets();
 }
 
 // --------------------------------------------------------------- results --
