@@ -342,9 +342,38 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
 // ----------------------------------------------------------------- build --
 // Algorithm 1 on the device: the frontier of level l-1 holds the quadrants
 // to split as intervals of the sorted codes; each is cut into its four
-// level-l children by binary search; a child with more than th objects
-// below l_max joins the next frontier, every other child (empty ones
-// included) becomes a leaf.
+// level-l children (one wave per quadrant); a child with more than th
+// objects below l_max joins the next frontier, every other child (empty
+// ones included) becomes a leaf.
+
+// First index in [lo, hi) whose code is >= key (hi if none), by the whole
+// wave: 63 lanes probe evenly spaced positions and a ballot keeps the
+// interval that holds the answer, so a range of n codes takes about
+// log64(n) dependent loads.  Every lane returns the same value.
+__device__ __forceinline__ uint32_t wave_lower_bound(const uint32_t *codes, uint32_t lo,
+                                                     uint32_t hi, uint32_t key) {
+  const uint32_t lane = lane_id();
+  while (hi - lo > (uint32_t)kWave) {
+    const uint64_t span = hi - lo;
+    const uint32_t p = lo + (uint32_t)((span * (lane + 1u)) >> 6);  // lo < p < hi for lane < 63
+    const bool ge = lane < (uint32_t)kWave - 1u && codes[p] >= key;
+    const uint64_t m = ballot(ge);
+    const uint32_t f = m ? (uint32_t)__ffsll((unsigned long long)m) - 1u : (uint32_t)kWave - 1u;
+    const uint32_t pf = (uint32_t)readlane_i((int)p, (int)f);
+    const uint32_t pb = f ? (uint32_t)readlane_i((int)p, (int)f - 1) : 0u;
+    const uint32_t nlo = f ? pb + 1u : lo;
+    hi = f < (uint32_t)kWave - 1u ? pf : hi;
+    lo = nlo;
+  }
+  const bool ge = lo + lane < hi && codes[lo + lane] >= key;
+  const uint64_t m = ballot(ge);
+  return m ? lo + (uint32_t)__ffsll((unsigned long long)m) - 1u : hi;
+}
+
+// Quadrants per level up to which a whole wave splits each quadrant (the top
+// levels: few quadrants over long code ranges); below it a lane per quadrant
+// (many short ranges, one append per wave).
+constexpr uint32_t kWaveSplitMax = 1024;
 
 __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uint32_t l_max,
                                                        const uint32_t *codes, const uint4 *fin,
@@ -356,51 +385,107 @@ __global__ void __launch_bounds__(kBlock) k_tree_level(Ctl *ctl, uint32_t l, uin
   if (F == 0) return;
   const uint32_t th = ctl->th_cur;
   const uint32_t shift = 2u * (kFine - l);
-  const uint32_t nthreads = gridDim.x * kBlock;
-  const uint32_t Fr = (F + kWave - 1) / kWave * kWave;
-  for (uint32_t f = blockIdx.x * kBlock + threadIdx.x; f < Fr; f += nthreads) {
-    const bool valid = f < F;
-    uint32_t zp = 0, bnd[5] = {0, 0, 0, 0, 0}, nsplit = 0, nleaf = 0, splitm = 0;
-    if (valid) {
+  const uint32_t lane = lane_id();
+  bool ovf = false;
+  uint32_t deep = 0;
+  if (F <= kWaveSplitMax) {
+    const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+    const uint32_t w0 =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+    for (uint32_t f = w0; f < F; f += nwaves) {
       const uint4 e = fin[f];
-      zp = e.x;
-      bnd[0] = e.y;
-      bnd[4] = e.z;
-      for (uint32_t k = 1; k < 4; ++k)
-        bnd[k] = lower_bound_u32(codes, bnd[k - 1], bnd[4], (zp * 4u + k) << shift);
-      for (uint32_t k = 0; k < 4; ++k) {
-        const bool sp = bnd[k + 1] - bnd[k] > th && l < l_max;
-        splitm |= (sp ? 1u : 0u) << k;
-        nsplit += sp;
-        nleaf += !sp;
+      const uint32_t zp = e.x, b0 = e.y, b4 = e.z;
+      // boundaries of the four children: one ballot round when the quadrant
+      // holds at most a wave of codes, else three wave searches
+      uint32_t bnd[5];
+      bnd[0] = b0;
+      bnd[4] = b4;
+      if (b4 - b0 <= (uint32_t)kWave) {
+        const bool v = b0 + lane < b4;
+        const uint32_t d = v ? (codes[b0 + lane] >> shift) & 3u : 4u;
+#pragma unroll
+        for (uint32_t k = 1; k < 4; ++k) bnd[k] = b0 + (uint32_t)__popcll(ballot(d < k));
+      } else {
+#pragma unroll
+        for (uint32_t k = 1; k < 4; ++k)
+          bnd[k] = wave_lower_bound(codes, bnd[k - 1], b4, (zp * 4u + k) << shift);
       }
-    }
-    uint32_t fb = wave_append(&ctl->fcount[l], nsplit);
-    uint32_t lb = wave_append(&ctl->n_leaves, nleaf);
-    bool ovf = false;
-    if (valid) {
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t cz = zp * 4u + k;
-        if ((splitm >> k) & 1u) {
-          if (fb < fcap)
-            fout[fb] = make_uint4(cz, bnd[k], bnd[k + 1], 0u);
-          else
-            ovf = true;
-          ++fb;
+      // lane k < 4 decides child k
+      const bool child = lane < 4u;
+      uint32_t lo = 0, hi = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k)
+        if (lane == k) {
+          lo = bnd[k];
+          hi = bnd[k + 1];
+        }
+      const bool sp = child && hi - lo > th && l < l_max;
+      const bool lf = child && !sp;
+      const uint32_t fb = wave_append(&ctl->fcount[l], sp ? 1u : 0u);
+      const uint32_t lb = wave_append(&ctl->n_leaves, lf ? 1u : 0u);
+      const uint32_t cz = zp * 4u + lane;
+      if (sp) {
+        if (fb < fcap)
+          fout[fb] = make_uint4(cz, lo, hi, 0u);
+        else
+          ovf = true;
+      } else if (lf) {
+        if (lb < lcap) {
+          lstart[lb] = cz << shift;
+          llevel[lb] = l;
         } else {
-          if (lb < lcap) {
-            lstart[lb] = cz << shift;
-            llevel[lb] = l;
-          } else {
-            ovf = true;
-          }
-          ++lb;
+          ovf = true;
         }
       }
+      if (ballot(lf)) deep = l;
     }
-    flag_error(ctl, kErrOvfTree, ovf);
-    if (ballot(nleaf != 0) && lane_id() == 0) atomicMax(&ctl->l_deep, l);
+  } else {
+    const uint32_t nthreads = gridDim.x * kBlock;
+    const uint32_t Fr = (F + kWave - 1) / kWave * kWave;
+    for (uint32_t f = blockIdx.x * kBlock + threadIdx.x; f < Fr; f += nthreads) {
+      const bool valid = f < F;
+      uint32_t zp = 0, bnd[5] = {0, 0, 0, 0, 0}, nsplit = 0, nleaf = 0, splitm = 0;
+      if (valid) {
+        const uint4 e = fin[f];
+        zp = e.x;
+        bnd[0] = e.y;
+        bnd[4] = e.z;
+        for (uint32_t k = 1; k < 4; ++k)
+          bnd[k] = lower_bound_u32(codes, bnd[k - 1], bnd[4], (zp * 4u + k) << shift);
+        for (uint32_t k = 0; k < 4; ++k) {
+          const bool sp = bnd[k + 1] - bnd[k] > th && l < l_max;
+          splitm |= (sp ? 1u : 0u) << k;
+          nsplit += sp;
+          nleaf += !sp;
+        }
+      }
+      uint32_t fb = wave_append(&ctl->fcount[l], nsplit);
+      uint32_t lb = wave_append(&ctl->n_leaves, nleaf);
+      if (valid) {
+        for (uint32_t k = 0; k < 4; ++k) {
+          const uint32_t cz = zp * 4u + k;
+          if ((splitm >> k) & 1u) {
+            if (fb < fcap)
+              fout[fb] = make_uint4(cz, bnd[k], bnd[k + 1], 0u);
+            else
+              ovf = true;
+            ++fb;
+          } else {
+            if (lb < lcap) {
+              lstart[lb] = cz << shift;
+              llevel[lb] = l;
+            } else {
+              ovf = true;
+            }
+            ++lb;
+          }
+        }
+      }
+      if (ballot(nleaf != 0)) deep = l;
+    }
   }
+  flag_error(ctl, kErrOvfTree, ovf);
+  if (deep && lane == 0) atomicMax(&ctl->l_deep, deep);
 }
 
 // The leaf table is sized for the worst case of the smallest threshold, so
@@ -480,11 +565,24 @@ __global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const ui
   if (!ctl->rebuild || (ctl->err & kErrOvfTree)) return;
   const uint32_t T = ctl->tlev, n = ctl->n_leaves;
   const uint32_t ncell = 1u << (2 * T), sh = 2u * (kFine - T);
-  for (uint32_t z = blockIdx.x * kBlock + threadIdx.x; z < ncell; z += gridDim.x * kBlock) {
+  const uint32_t lane = lane_id();
+  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
+  const uint32_t w0 =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  // a wave takes 64 consecutive cells: the leaves holding its first and last
+  // cell (the last leaf whose start is <= the cell's code) bound the search
+  // of every lane
+  for (uint32_t z0 = w0 * (uint32_t)kWave; z0 < ncell; z0 += nwaves * (uint32_t)kWave) {
+    const uint32_t zl = min(z0 + (uint32_t)kWave, ncell) - 1u;
+    uint32_t ua = wave_lower_bound(lstart, 0u, n, z0 << sh);
+    if (ua == n || lstart[ua] != (z0 << sh)) --ua;
+    uint32_t ub = wave_lower_bound(lstart, ua, n, zl << sh);
+    if (ub == n || lstart[ub] != (zl << sh)) --ub;
+    const uint32_t z = z0 + lane;
+    if (z >= ncell) continue;
     const uint32_t code = T == kFine ? z : z << sh;
-    // leaf containing code: the last leaf whose start is <= code
-    uint32_t u = lower_bound_u32(lstart, 0u, n, code);
-    if (u == n || lstart[u] != code) --u;
+    uint32_t u = lower_bound_u32(lstart, ua, ub + 1u, code);
+    if (u == ub + 1u || lstart[u] != code) --u;
     const uint32_t l = llevel[u];
     table[z] = l <= T ? (kLeafBit | ((l - 1u) << kLeafIdxBits) | u)
                       : node_off[u] + (T - open_level(code));
@@ -1226,7 +1324,10 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
 
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
   for (uint32_t l = 1; l <= l_max; ++l) {
-    LAUNCH(k_tree_level, grid_for(B.FCAP), kBlock, s, B.ctl, l, l_max, (const uint32_t *)B.keyA,
+    // enough waves for a wave per quadrant on the top levels, enough lanes
+    // for a lane per quadrant below
+    LAUNCH(k_tree_level, grid_for(B.FCAP > kWaveSplitMax * kWave ? B.FCAP : kWaveSplitMax * kWave),
+           kBlock, s, B.ctl, l, l_max, (const uint32_t *)B.keyA,
            (const uint4 *)B.front[(l - 1) & 1], B.front[l & 1], B.FCAP, B.lstart, B.llevel,
            B.LCAP);
   }
