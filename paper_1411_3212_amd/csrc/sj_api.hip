@@ -21,7 +21,7 @@ struct GraphSlot {
   hipGraphExec_t exec;   // the whole tick, or its part before the join write pass
   hipGraphExec_t exec2;  // the join write pass (profiled scenes only)
   bool valid;
-  uint32_t m, nq;
+  uint32_t m, nq, key_bits;
   const void *ptrs[8];
 };
 
@@ -282,6 +282,16 @@ uint32_t host_decision(const sj_scene *s) {
   return r ? 1u : 0u;
 }
 
+// Width of the leaf keys of a tick that keeps the quadtree, when the host
+// has read the scene's state (0: the device decides).
+uint32_t key_bits(const sj_scene *s, uint32_t decision) {
+  if (decision != 0u || !s->known) return 0u;
+  const uint32_t nl = s->host_ctl.n_leaves;
+  uint32_t bits = 0;
+  while (bits < 32u && (nl - 1u) >> bits) ++bits;
+  return bits < 8u ? 8u : bits;
+}
+
 // Whether a tick with this rebuild decision tunes the threshold first: the
 // first build decided on the host and every tune_every-th after it.
 bool want_tune(const sj_scene *s, uint32_t decision) {
@@ -314,7 +324,7 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
     return;
   }
   rec(0);
-  sj::launch_index(s->B, decision, policy, upd_total, d_qid, nq, st);
+  sj::launch_index(s->B, decision, policy, upd_total, d_qid, nq, key_bits(s, decision), st);
   rec(1);
   if (tune)
     sj::launch_tune(s->B, s->n_cand, s->l_max, d_qid, d_xa, d_ya, d_xb, d_yb, nq,
@@ -495,7 +505,8 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
   const bool tune = want_tune(s, decision);
   GraphSlot &g = s->graphs[tune ? 3u : decision];
   const void *ptrs[8] = {d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
-  bool same = g.valid && g.m == m && g.nq == nq;
+  const uint32_t kb = key_bits(s, decision);
+  bool same = g.valid && g.m == m && g.nq == nq && g.key_bits == kb;
   for (int i = 0; same && i < 8; ++i) same = g.ptrs[i] == ptrs[i];
   if (!same) {
     if (g.valid) {
@@ -538,6 +549,7 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     g.valid = true;
     g.m = m;
     g.nq = nq;
+    g.key_bits = kb;
     for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
   }
   hipError_t e = hipGraphLaunch(g.exec, s->stream);

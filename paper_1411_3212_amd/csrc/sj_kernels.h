@@ -62,8 +62,10 @@ void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const float *y, uint32_t m,
                     uint64_t seq_off, hipStream_t s);
+// key_bits: with decision 0, the width of the leaf keys if the host knows
+// it (then exactly the passes it needs run), else 0.
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
-                  const uint32_t *qid, uint32_t nq, hipStream_t s);
+                  const uint32_t *qid, uint32_t nq, uint32_t key_bits, hipStream_t s);
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s);
 void launch_leaves(const Bufs &B, hipStream_t s);
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,

@@ -262,11 +262,12 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   ctl->rebuild = r ? 1u : 0u;
   if (!r) {
     ctl->since_build += 1;
-    // leaf keys are below n_leaves: digits from the first zero one on are
-    // passes that only copy
+    // leaf keys are below n_leaves: the radix passes above their width
+    // have nothing to sort (at least one pass gathers the positions)
     const uint32_t nl = ctl->n_leaves;
     const uint32_t bits = nl > 1u ? 32u - (uint32_t)__clz((int)(nl - 1u)) : 0u;
-    ctl->sort_skip = (bits + 7u) / 8u * 8u;
+    const uint32_t w = (bits + 7u) / 8u * 8u;
+    ctl->sort_skip = w < 8u ? 8u : w;
     return;
   }
   ctl->sort_skip = 32u;
@@ -1311,11 +1312,27 @@ static Tree tree_of(const Bufs &B) {
 }
 
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
-                  const uint32_t *qid, uint32_t nq, hipStream_t s) {
+                  const uint32_t *qid, uint32_t nq, uint32_t key_bits, hipStream_t s) {
   LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N,
          (const Ctl *)B.ctl, B.blk, B.red);
   LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, (const uint64_t *)B.red, B.front[0],
          decision, policy, upd_total);
+  if (decision == 0u && key_bits) {
+    // the tree is kept and the host knows the leaf-key width: exactly the
+    // passes it needs, starting from the buffer that makes them end in A
+    const int passes = (int)((key_bits + 7u) / 8u);
+    const bool odd = passes & 1;
+    LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
+           (const uint32_t *)B.blk, odd ? B.keyB : B.keyA, odd ? B.valB : B.valA, qid, nq,
+           B.qstamp);
+    if (odd)
+      radix_sort_pairs(B.keyB, B.valB, B.keyA, B.valA, &B.ctl->n_present, nullptr, B.hist,
+                       B.tot, 0, 8 * passes, s, B.pos, B.sxy);
+    else
+      radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist,
+                       B.tot, 0, 8 * passes, s, B.pos, B.sxy);
+    return;
+  }
   LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
          (const uint32_t *)B.blk, B.keyA, B.valA, qid, nq, B.qstamp);
   radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist, B.tot, 0,

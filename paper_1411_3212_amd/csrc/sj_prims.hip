@@ -12,10 +12,22 @@ namespace sj {
 
 __device__ __forceinline__ bool gated(const uint32_t *gate) { return gate && *gate == 0u; }
 
-// A radix pass whose digit is zero for every key (shift >= *skip) only
-// copies its input, so that the passes still end in the same buffer.
-__device__ __forceinline__ bool copy_pass(const uint32_t *skip, int shift) {
-  return skip && (uint32_t)shift >= *skip;
+// Role of a radix pass when the keys fit in *skip bits (a multiple of 8,
+// at least 8): the passes below sort; the passes above have a zero digit
+// for every key and are identities.  Identities run in pairs as nothing (the
+// data returns to the same buffer), and one left over runs as a copy.  The
+// positions are gathered by the last pass that writes.
+enum : int { kPassSort = 0, kPassCopy = 1, kPassNone = 2 };
+__device__ __forceinline__ int pass_role(const uint32_t *skip, int shift) {
+  if (!skip) return kPassSort;
+  const uint32_t np = *skip / 8u, p = (uint32_t)shift / 8u;
+  if (p < np) return kPassSort;
+  return (p == np && (np & 1u)) ? kPassCopy : kPassNone;
+}
+__device__ __forceinline__ bool gather_pass(const uint32_t *skip, int shift, int last_shift) {
+  if (!skip) return shift == last_shift;
+  const uint32_t np = *skip / 8u;
+  return (uint32_t)shift / 8u == ((np & 1u) ? np : np - 1u);
 }
 
 // ---------------------------------------------------------------- scans --
@@ -119,12 +131,12 @@ ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32
 //           digit order and writes each digit's run contiguously to its
 //           global offset.  The last pass can also gather the positions of
 //           the sorted values (sorted SoA of the objects).
-// A pass at or above the device value *skip only copies (see copy_pass).
+// Passes above the device value *skip only copy or do nothing (pass_role).
 
 __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const uint32_t *n_dev,
                                                     const uint32_t *gate, const uint32_t *skip,
                                                     int shift, uint32_t *hist) {
-  if (gated(gate) || copy_pass(skip, shift)) return;
+  if (gated(gate) || pass_role(skip, shift) != kPassSort) return;
   __shared__ uint32_t lh[256];
   const uint32_t n = *n_dev;
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -140,7 +152,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const 
 __global__ void __launch_bounds__(kChunkBlocks) k_rs_hscan(uint32_t *hist, const uint32_t *gate,
                                                            const uint32_t *skip, int shift,
                                                            uint32_t *tot) {
-  if (gated(gate) || copy_pass(skip, shift)) return;
+  if (gated(gate) || pass_role(skip, shift) != kPassSort) return;
   __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
   uint32_t *h = hist + blockIdx.x * kChunkBlocks;
   uint32_t total;
@@ -156,9 +168,13 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
                                                        uint32_t *__restrict__ vout,
                                                        const uint32_t *n_dev, const uint32_t *gate,
                                                        const uint32_t *skip, int shift,
-                                                       const uint32_t *hist, const uint32_t *tot,
-                                                       const float2 *gpos, float2 *gout) {
+                                                       int last_shift, const uint32_t *hist,
+                                                       const uint32_t *tot, const float2 *gpos,
+                                                       float2 *gout) {
   if (gated(gate)) return;
+  const int role = pass_role(skip, shift);
+  if (role == kPassNone) return;
+  const bool gather = GATHER && gather_pass(skip, shift, last_shift);
   __shared__ uint32_t cnt[kSortItems * kWavesPerBlock * 256];
   __shared__ uint32_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
@@ -170,12 +186,12 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   if (b0 >= b1) return;  // uniform per block: no barrier is skipped by part of it
-  if (copy_pass(skip, shift)) {
+  if (role == kPassCopy) {
     for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
       const uint32_t v = vin[i];
       kout[i] = kin[i];
       vout[i] = v;
-      if (GATHER) gout[i] = gpos[v];
+      if (gather) gout[i] = gpos[v];
     }
     return;
   }
@@ -241,7 +257,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       const uint32_t v = sv[i];
       kout[g] = k;
       vout[g] = v;
-      if (GATHER) gout[g] = gpos[v];
+      if (gather) gout[g] = gpos[v];
     }
     __syncthreads();
     goff[tid] += tcnt[tid];
@@ -255,20 +271,23 @@ bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       float2 *gout, const uint32_t *skip) {
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   bool in_alt = false;
+  const int last_shift = bit_end - 8;
   for (int shift = bit_begin; shift < bit_end; shift += 8) {
-    const bool last = shift + 8 >= bit_end;
+    // with a device key width any pass may be the one that gathers
+    const bool may_gather = gout && (skip || shift == last_shift);
     hipLaunchKernelGGL(k_rs_hist, dim3(kChunkBlocks), dim3(kBlock), 0, s, (const uint32_t *)ki,
                        n_dev, gate, skip, shift, hist);
     hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, skip, shift,
                        tot);
-    if (last && gout)
+    if (may_gather)
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, (const uint32_t *)hist, (const uint32_t *)tot, gpos, gout);
+                         shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot, gpos,
+                         gout);
     else
       hipLaunchKernelGGL(k_rs_scatter<false>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
+                         shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot,
                          (const float2 *)nullptr, (float2 *)nullptr);
     uint32_t *t = ki;
     ki = ko;
@@ -278,7 +297,8 @@ bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
     vo = t;
     in_alt = !in_alt;
   }
-  return in_alt;
+  // with a key width the writing passes are even in number: back in k0
+  return skip ? false : in_alt;
 }
 
 }  // namespace sj
