@@ -733,6 +733,13 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
   return true;
 }
 
+// List slot j of query k lives at list_base(k) + j * 64: the queries of
+// one wave keep their j-th entries side by side, so the wave's stores and
+// loads of a slot share cache lines.
+__device__ __forceinline__ uint64_t list_base(uint32_t k, uint32_t slots) {
+  return (uint64_t)(k & ~(uint32_t)(kWave - 1)) * slots + (k & (uint32_t)(kWave - 1));
+}
+
 // Count pass: per query the numbers of intersecting and covering
 // subqueries, per leaf the number of intersecting subqueries; the visited
 // leaves are kept in the query's list slots for the write pass.
@@ -750,7 +757,8 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     bool bad_rect = false;
     if (k < nq) {
       uint32_t ni = 0, nc = 0, nl = 0;
-      uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      const uint64_t lb = list_base(k, slots);
+      uint32_t *lst = qlist + lb, *pos = qpos + lb;
       const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
       qrect[k] = r;
       QBox q;
@@ -766,7 +774,7 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
             // subqueries in the write pass
             if (nl >= slots) atomicAdd(&leaf_ovf[leaf], 1u);
           }
-          if (nl < slots) lst[nl] = leaf | (c ? kLeafBit : 0u);
+          if (nl < slots) lst[nl * kWave] = leaf | (c ? kLeafBit : 0u);
           ++nl;
         };
         for_each_leaf(tr, stack + threadIdx.x, q, visit);
@@ -776,13 +784,13 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
         for (uint32_t i0 = 0; i0 < m; i0 += 8u) {
           uint32_t e[8], r[8];
 #pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j) e[j] = i0 + j < m ? lst[i0 + j] : kLeafBit;
+          for (uint32_t j = 0; j < 8u; ++j) e[j] = i0 + j < m ? lst[(i0 + j) * kWave] : kLeafBit;
 #pragma unroll
           for (uint32_t j = 0; j < 8u; ++j)
             r[j] = (e[j] & kLeafBit) ? 0u : atomicAdd(&leaf_nsq[e[j]], 1u);
 #pragma unroll
           for (uint32_t j = 0; j < 8u; ++j)
-            if (!(e[j] & kLeafBit)) pos[i0 + j] = r[j];
+            if (!(e[j] & kLeafBit)) pos[(i0 + j) * kWave] = r[j];
         }
       }
       q_ni[k] = ni;
@@ -836,7 +844,8 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
       const uint32_t n = q_ni[k] + q_nc[k];
       if (n == 0) continue;
       uint32_t wi = q_ioff[k], wc = q_coff[k], i = 0;
-      const uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      const uint64_t lb = list_base(k, slots);
+      const uint32_t *lst = qlist + lb, *pos = qpos + lb;
       // i-th leaf of the query's walk (the count pass walked in the same order)
       auto emit = [&](uint32_t leaf, bool c) {
         if (c) {
@@ -844,7 +853,7 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
           covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
         } else {
           const uint32_t p =
-              i < slots ? pos[i] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
+              i < slots ? pos[i * kWave] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
           sq[leaf_sqoff[leaf] + p] = make_uint2(k, wi++);
         }
         ++i;
@@ -856,8 +865,8 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 #pragma unroll
           for (uint32_t j = 0; j < 8u; ++j) {
             const bool v = j0 + j < n;
-            e[j] = v ? lst[j0 + j] : kLeafBit;
-            p[j] = v ? pos[j0 + j] : 0u;
+            e[j] = v ? lst[(j0 + j) * kWave] : kLeafBit;
+            p[j] = v ? pos[(j0 + j) * kWave] : 0u;
           }
 #pragma unroll
           for (uint32_t j = 0; j < 8u; ++j)
