@@ -1032,19 +1032,80 @@ __global__ void __launch_bounds__(kBlock) k_task_recs(const Ctl *ctl, const uint
   }
 }
 
+// A task is joined by one wave, 64 subqueries at a time.  Their
+// rectangles (and, in the write pass, their result offsets) are staged in
+// the wave's LDS slice, so each lane reads subquery kk's with one broadcast
+// load; the leaf's objects are held in registers, 64 x NCH at a time, one
+// per lane and chunk.  The containment tests of a subquery against a chunk
+// are one ballot: the count pass adds its popcount, the write pass compacts
+// the hits with each lane's rank among them.
+constexpr uint32_t kJoinRegChunks = 8;  // object chunks of 64 in registers
+
+// Orders a wave's LDS stores before its later loads of other lanes' slots
+// (and the loads before the next stores).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t chunk_count(uint32_t o0, uint32_t oe) {
+  return min(kJoinRegChunks, (oe - o0 + (uint32_t)kWave - 1u) / (uint32_t)kWave);
+}
+
+// Chunk c of a block: lane l holds object o0 + 64 c + l when it is below
+// oe (mask h[c]); the other lanes hold a copy of the last object, which
+// the mask excludes.
+template <uint32_t NCH>
+__device__ __forceinline__ void load_chunks(const float2 *__restrict__ sxy, uint32_t o0,
+                                            uint32_t oe, uint32_t lane, float2 *p, uint64_t *h) {
+#pragma unroll
+  for (uint32_t c = 0; c < NCH; ++c) {
+    const uint32_t i = o0 + c * (uint32_t)kWave + lane;
+    h[c] = ballot(i < oe);
+    p[c] = sxy[min(i, oe - 1u)];
+  }
+}
+
+// Lanes whose object lies in the closed rectangle r: one ballot per bound,
+// so the four comparisons stay lane masks.
+__device__ __forceinline__ uint64_t hits(const float4 r, const float2 p, uint64_t h) {
+  return ballot(r.x <= p.x) & ballot(p.x <= r.z) & ballot(r.y <= p.y) & ballot(p.y <= r.w) & h;
+}
+
+template <uint32_t NCH>
+__device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk,
+                                                const float2 *__restrict__ sxy, uint32_t o0,
+                                                uint32_t oe, uint32_t lane) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
+  uint32_t blk = 0;  // lane kk: hits of subquery kk in this block
+  for (uint32_t kk = 0; kk < nk; ++kk) {
+    const float4 r = wrect[kk];
+    uint32_t tot = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < NCH; ++c) tot += (uint32_t)__popcll(hits(r, p[c], h[c]));
+    blk = lane == kk ? tot : blk;
+  }
+  return blk;
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint4 *trec,
                                                        const uint32_t *tleaf,
                                                        const uint32_t *leaf_sqoff, const uint2 *sq,
-                                                       const float4 *qrect, const float2 *sxy,
+                                                       const float4 *qrect,
+                                                       const float2 *__restrict__ sxy,
                                                        uint32_t *sq_cnt, float *tlog,
                                                        const uint32_t *lstart,
                                                        const uint32_t *llevel) {
+  __shared__ float4 lrect[kBlock];
   if (!ctl->go_split) return;
   const uint32_t nt = ctl->n_entries;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
   for (uint32_t t = w0; t < nt; t += nwaves) {
     const uint4 tr = next;  // this task's record, loaded during the previous one
@@ -1056,24 +1117,22 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
     float ovl = 0.0f;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
-      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
       uint32_t slot = 0, cnt = 0;
+      wave_lds_fence();
       if (lane < nk) {
         const uint2 e = sq[sc + lane];
         slot = e.y;
-        r = qrect[e.x];
+        const float4 r = qrect[e.x];
+        wrect[lane] = r;
         if (tlog) ovl += overlap_frac(ctl, lstart, llevel, leaf, r);
       }
-      for (uint32_t o = ob; o < oe; o += kWave) {
-        const bool has = o + lane < oe;
-        const float2 p = has ? sxy[o + lane] : make_float2(0.f, 0.f);
-        for (uint32_t kk = 0; kk < nk; ++kk) {
-          const float qxa = readlane_f(r.x, kk), qya = readlane_f(r.y, kk);
-          const float qxb = readlane_f(r.z, kk), qyb = readlane_f(r.w, kk);
-          const bool in = has && qxa <= p.x && p.x <= qxb && qya <= p.y && p.y <= qyb;
-          const uint32_t c = (uint32_t)__popcll(ballot(in));
-          if (lane == kk) cnt += c;
-        }
+      wave_lds_fence();
+      for (uint32_t o0 = ob; o0 < oe; o0 += (uint32_t)kWave * kJoinRegChunks) {
+        const uint32_t nch = chunk_count(o0, oe);
+        cnt += nch <= 1u   ? count_block<1>(wrect, nk, sxy, o0, oe, lane)
+               : nch <= 2u ? count_block<2>(wrect, nk, sxy, o0, oe, lane)
+               : nch <= 4u ? count_block<4>(wrect, nk, sxy, o0, oe, lane)
+                           : count_block<8>(wrect, nk, sxy, o0, oe, lane);
       }
       if (lane < nk) sq_cnt[slot] = cnt;
     }
@@ -1130,13 +1189,42 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
   ctl->want_rebuild = policy == 0u && (leaf_big || moved_out || periodic || !ctl->built);
 }
 
+template <uint32_t NCH>
+__device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff, uint32_t nk,
+                                            const float2 *__restrict__ sxy,
+                                            const uint32_t *__restrict__ sid, uint32_t o0,
+                                            uint32_t oe, uint32_t lane,
+                                            uint32_t *__restrict__ res_ids, bool more) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  uint32_t id[NCH];
+  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
+#pragma unroll
+  for (uint32_t c = 0; c < NCH; ++c) id[c] = sid[min(o0 + c * (uint32_t)kWave + lane, oe - 1u)];
+  for (uint32_t kk = 0; kk < nk; ++kk) {
+    const float4 r = wrect[kk];
+    uint64_t base = woff[kk];  // next free result slot of subquery kk
+#pragma unroll
+    for (uint32_t c = 0; c < NCH; ++c) {
+      const uint64_t m = hits(r, p[c], h[c]);
+      if (__builtin_amdgcn_inverse_ballot_w64(m)) res_ids[base + mbcnt(m)] = id[c];
+      base += (uint64_t)__popcll(m);
+    }
+    if (more) woff[kk] = base;  // every lane stores the same value
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
                                                        const uint32_t *tleaf, const uint2 *sq,
-                                                       const float4 *qrect, const float2 *sxy,
-                                                       const uint32_t *sid,
-                                                       const uint64_t *res_off, uint32_t *res_ids,
+                                                       const float4 *qrect,
+                                                       const float2 *__restrict__ sxy,
+                                                       const uint32_t *__restrict__ sid,
+                                                       const uint64_t *res_off,
+                                                       uint32_t *__restrict__ res_ids,
                                                        uint32_t nq, const uint32_t *q_ioff,
                                                        uint64_t *q_roff, float *tlog) {
+  __shared__ float4 lrect[kBlock];
+  __shared__ uint64_t loff[kBlock];
   const bool go = ctl->go_join != 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->qry_seq += nq;
@@ -1156,6 +1244,8 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  uint64_t *woff = loff + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
   for (uint32_t t = w0; t < nt; t += nwaves) {
     const uint4 tr = next;  // this task's record, loaded during the previous one
@@ -1166,26 +1256,25 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     for (uint32_t sc = sb; sc < se; sc += kWave) {
       const uint32_t nk = min((uint32_t)kWave, se - sc);
-      float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-      uint64_t off = 0;
+      wave_lds_fence();
       if (lane < nk) {
         const uint2 e = sq[sc + lane];
-        off = res_off[e.y];
-        r = qrect[e.x];
+        woff[lane] = res_off[e.y];
+        wrect[lane] = qrect[e.x];
       }
-      for (uint32_t o = ob; o < oe; o += kWave) {
-        const bool has = o + lane < oe;
-        const float2 p = has ? sxy[o + lane] : make_float2(0.f, 0.f);
-        const uint32_t id = has ? sid[o + lane] : 0u;
-        for (uint32_t kk = 0; kk < nk; ++kk) {
-          const float qxa = readlane_f(r.x, kk), qya = readlane_f(r.y, kk);
-          const float qxb = readlane_f(r.z, kk), qyb = readlane_f(r.w, kk);
-          const bool in = has && qxa <= p.x && p.x <= qxb && qya <= p.y && p.y <= qyb;
-          const uint64_t m = ballot(in);
-          const uint64_t base = readlane_u64(off, kk);
-          if (in) res_ids[base + mbcnt(m)] = id;
-          if (lane == kk) off += (uint64_t)__popcll(m);
-        }
+      wave_lds_fence();
+      for (uint32_t o0 = ob; o0 < oe; o0 += (uint32_t)kWave * kJoinRegChunks) {
+        const uint32_t nch = chunk_count(o0, oe);
+        const bool more = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
+        if (nch <= 1u)
+          write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
+        else if (nch <= 2u)
+          write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
+        else if (nch <= 4u)
+          write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
+        else
+          write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
+        wave_lds_fence();
       }
     }
     if (tlog && lane == 0)
