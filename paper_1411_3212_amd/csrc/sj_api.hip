@@ -201,8 +201,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.q_ioff = c.take<uint32_t>(Q + 1);
   b.q_coff = c.take<uint32_t>(Q + 1);
   b.q_roff = c.take<uint64_t>(Q + 1);
-  b.qlist = c.take<uint32_t>((Q + 63) / 64 * 64 * d.slots);  // whole waves of queries
-  b.qpos = c.take<uint32_t>((Q + 63) / 64 * 64 * d.slots);
+  b.qlist = c.take<uint32_t>(Q * d.slots);
+  b.qpos = c.take<uint32_t>(Q * d.slots);
   b.sq = c.take<uint2>(d.S);
   b.sq_cnt = c.take<uint32_t>(d.S);
   b.res_off = c.take<uint64_t>(d.S + 1);

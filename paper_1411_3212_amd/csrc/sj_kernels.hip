@@ -676,47 +676,6 @@ __device__ __forceinline__ void walk_from(const uint4 *__restrict__ nodes, uint3
   }
 }
 
-// Leaves overlapping a query: the query's cells of the start table are
-// read in batches; a leaf entry is visited at the cell with minimal
-// coordinates among the query's cells of that leaf, an internal node is
-// walked.  Queries over more than kTableScanMax cells walk from the root.
-template <typename Visit>
-__device__ __forceinline__ void for_each_leaf(const Tree &tr, uint32_t *stack, const QBox q,
-                                              Visit &visit) {
-  const uint32_t T = tr.tlev, sh = (uint32_t)kFine - T;
-  const uint32_t ti0 = q.i0 >> sh, ti1 = q.i1 >> sh, tj0 = q.j0 >> sh, tj1 = q.j1 >> sh;
-  const uint32_t w = ti1 - ti0 + 1, ncell = w * (tj1 - tj0 + 1);
-  if (ncell > kTableScanMax) {
-    walk_from(tr.nodes, stack, 0u, 0u, 0u, 0u, q, visit);
-    return;
-  }
-  constexpr uint32_t kB = 4;
-  for (uint32_t c0 = 0; c0 < ncell; c0 += kB) {
-    uint32_t ent[kB];
-#pragma unroll
-    for (uint32_t b = 0; b < kB; ++b) {
-      const uint32_t c = c0 + b;
-      ent[b] = c < ncell ? tr.table[morton2(ti0 + c % w, tj0 + c / w)] : 0u;
-    }
-#pragma unroll
-    for (uint32_t b = 0; b < kB; ++b) {
-      const uint32_t c = c0 + b;
-      if (c >= ncell) break;
-      const uint32_t ci = ti0 + c % w, cj = tj0 + c / w, e = ent[b];
-      if (!(e & kLeafBit)) {
-        walk_from(tr.nodes, stack, e, T, ci, cj, q, visit);
-        continue;
-      }
-      const uint32_t l = ((e >> kLeafIdxBits) & 15u) + 1u, m = T - l;
-      const uint32_t li0 = (ci >> m) << m, lj0 = (cj >> m) << m;
-      if (ci != (ti0 > li0 ? ti0 : li0) || cj != (tj0 > lj0 ? tj0 : lj0)) continue;
-      const uint32_t ilo = li0 << sh, jlo = lj0 << sh, span = (1u << (kFine - l)) - 1u;
-      visit(e & kLeafIdxMask,
-            q.i0 < ilo && ilo + span < q.i1 && q.j0 < jlo && jlo + span < q.j1);
-    }
-  }
-}
-
 __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o, uint32_t N,
                                           const uint64_t *qstamp, uint64_t seq, float4 r,
                                           QBox *q, bool *bad_rect) {
@@ -733,16 +692,95 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
   return true;
 }
 
-// List slot j of query k lives at list_base(k) + j * 64: the queries of
-// one wave keep their j-th entries side by side, so the wave's stores and
-// loads of a slot share cache lines.
-__device__ __forceinline__ uint64_t list_base(uint32_t k, uint32_t slots) {
-  return (uint64_t)(k & ~(uint32_t)(kWave - 1)) * slots + (k & (uint32_t)(kWave - 1));
+// Leaves overlapping a query, enumerated by a group of kSplitGroup lanes
+// in an order that both split passes reproduce.  The query's cells of the
+// start table are taken kSplitGroup at a time (one per lane); in a round,
+// first the leaf entries (a leaf is kept at the cell with minimal
+// coordinates among the query's cells of that leaf), in cell order, then
+// the internal nodes of the round one after the other, each walked by its
+// lane.  Queries over more than kTableScanMax cells are walked from the
+// root by the group's first lane.  visit(leaf, covering, idx, ri, rc)
+// receives the leaf's index in the query's list and its rank among the
+// intersecting (ri) or covering (rc) entries.  Inactive leaves are skipped.
+constexpr uint32_t kSplitGroup = 16;
+
+struct LeafCounts {
+  uint32_t n, ni, nc;
+};
+
+template <typename Visit>
+__device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *stack, const QBox q,
+                                                   const uint32_t *leaf_beg, uint32_t covering,
+                                                   uint32_t lane, uint64_t gm, Visit &visit) {
+  const uint32_t gl = lane & (kSplitGroup - 1u);
+  const uint32_t T = tr.tlev, sh = (uint32_t)kFine - T;
+  const uint32_t ti0 = q.i0 >> sh, ti1 = q.i1 >> sh, tj0 = q.j0 >> sh, tj1 = q.j1 >> sh;
+  const uint32_t w = ti1 - ti0 + 1, ncell = w * (tj1 - tj0 + 1);
+  const bool from_root = ncell > kTableScanMax;
+  const uint32_t rounds = from_root ? 1u : (ncell + kSplitGroup - 1u) / kSplitGroup;
+  uint32_t nl = 0, ni = 0, nc = 0;  // the same on every lane of the group
+  for (uint32_t rd = 0; rd < rounds; ++rd) {
+    const uint32_t c = rd * kSplitGroup + gl;
+    bool a = false, b = false, cv = false;
+    uint32_t leaf = 0, node = 0, ci = 0, cj = 0, depth = T;
+    if (from_root) {
+      b = gl == 0;
+      depth = 0;
+    } else if (c < ncell) {
+      ci = ti0 + c % w;
+      cj = tj0 + c / w;
+      const uint32_t e = tr.table[morton2(ci, cj)];
+      if (!(e & kLeafBit)) {
+        b = true;
+        node = e;
+      } else {
+        const uint32_t l = ((e >> kLeafIdxBits) & 15u) + 1u, m = T - l;
+        const uint32_t li0 = (ci >> m) << m, lj0 = (cj >> m) << m;
+        if (ci == (ti0 > li0 ? ti0 : li0) && cj == (tj0 > lj0 ? tj0 : lj0)) {
+          leaf = e & kLeafIdxMask;
+          a = leaf_beg[leaf + 1] != leaf_beg[leaf];
+          const uint32_t ilo = li0 << sh, jlo = lj0 << sh, span = (1u << (kFine - l)) - 1u;
+          cv = a && covering &&
+               (q.i0 < ilo && ilo + span < q.i1 && q.j0 < jlo && jlo + span < q.j1);
+        }
+      }
+    }
+    const uint64_t ma = ballot(a) & gm, mc = ballot(cv) & gm, mi = ma & ~mc;
+    if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc));
+    nl += (uint32_t)__popcll(ma);
+    ni += (uint32_t)__popcll(mi);
+    nc += (uint32_t)__popcll(mc);
+    uint64_t mb = ballot(b) & gm;
+    while (mb) {
+      const uint32_t bl = (uint32_t)__ffsll((unsigned long long)mb) - 1u;
+      mb &= mb - 1u;
+      uint32_t dl = 0, di = 0, dc = 0;
+      if (lane == bl) {
+        auto v = [&](uint32_t lf, bool cov0) {
+          if (leaf_beg[lf + 1] == leaf_beg[lf]) return;
+          const bool cc = cov0 && covering;
+          visit(lf, cc, nl + dl, ni + di, nc + dc);
+          ++dl;
+          if (cc)
+            ++dc;
+          else
+            ++di;
+        };
+        walk_from(tr.nodes, stack, node, depth, ci, cj, q, v);
+      }
+      nl += (uint32_t)__shfl((int)dl, (int)bl);
+      ni += (uint32_t)__shfl((int)di, (int)bl);
+      nc += (uint32_t)__shfl((int)dc, (int)bl);
+    }
+  }
+  return LeafCounts{nl, ni, nc};
 }
 
-// Count pass: per query the numbers of intersecting and covering
-// subqueries, per leaf the number of intersecting subqueries; the visited
-// leaves are kept in the query's list slots for the write pass.
+// Count pass, one query per group of kSplitGroup lanes: the numbers of
+// intersecting and covering subqueries per query and of intersecting
+// subqueries per leaf; the first `slots` entries of a query's list (leaf,
+// covering flag) and the positions of its intersecting entries in their
+// leaves' groups are kept for the write pass.
 __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const uint32_t *qid, const float *xa, const float *ya, const float *xb,
     const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
@@ -752,47 +790,33 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
   tr.tlev = ctl->tlev;
-  const uint32_t nr = (nq + kWave - 1) / kWave * kWave;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nr; k += gridDim.x * kBlock) {
+  const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
+  const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
+  const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
+  for (uint32_t k = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; k < nq; k += ngroups) {
     bool bad_rect = false;
-    if (k < nq) {
-      uint32_t ni = 0, nc = 0, nl = 0;
-      const uint64_t lb = list_base(k, slots);
-      uint32_t *lst = qlist + lb, *pos = qpos + lb;
-      const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
+    uint32_t ni = 0, nc = 0;
+    const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
+    QBox q;
+    if (query_box(ctl, k, qid[k], N, qstamp, seq, r, &q, &bad_rect) && tree_ok) {
+      uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t, uint32_t) {
+        if (i < slots) lst[i] = leaf | (c ? kLeafBit : 0u);
+        if (c) return;
+        // subqueries past the list get a position after the leaf's other
+        // subqueries in the write pass
+        if (i < slots)
+          pos[i] = atomicAdd(&leaf_nsq[leaf], 1u);
+        else
+          atomicAdd(&leaf_ovf[leaf], 1u);
+      };
+      const LeafCounts n = group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm,
+                                        visit);
+      ni = n.ni;
+      nc = n.nc;
+    }
+    if (gl == 0) {
       qrect[k] = r;
-      QBox q;
-      if (query_box(ctl, k, qid[k], N, qstamp, seq, r, &q, &bad_rect) && tree_ok) {
-        auto visit = [&](uint32_t leaf, bool cov) {
-          if (leaf_beg[leaf + 1] == leaf_beg[leaf]) return;
-          const bool c = cov && covering;
-          if (c) {
-            ++nc;
-          } else {
-            ++ni;
-            // subqueries past the list get a position after the leaf's other
-            // subqueries in the write pass
-            if (nl >= slots) atomicAdd(&leaf_ovf[leaf], 1u);
-          }
-          if (nl < slots) lst[nl * kWave] = leaf | (c ? kLeafBit : 0u);
-          ++nl;
-        };
-        for_each_leaf(tr, stack + threadIdx.x, q, visit);
-        // positions of the listed subqueries in their leaves' groups, eight
-        // independent atomics in flight at a time
-        const uint32_t m = nl < slots ? nl : slots;
-        for (uint32_t i0 = 0; i0 < m; i0 += 8u) {
-          uint32_t e[8], r[8];
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j) e[j] = i0 + j < m ? lst[(i0 + j) * kWave] : kLeafBit;
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j)
-            r[j] = (e[j] & kLeafBit) ? 0u : atomicAdd(&leaf_nsq[e[j]], 1u);
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j)
-            if (!(e[j] & kLeafBit)) pos[(i0 + j) * kWave] = r[j];
-        }
-      }
       q_ni[k] = ni;
       q_nc[k] = nc;
     }
@@ -824,8 +848,10 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
   ctl->n32[1] = err ? 0u : (uint32_t)tot[1];
 }
 
-// Write pass: intersecting subqueries grouped by leaf (record: query,
-// slot of the subquery in query order), covering leaves per query.  The
+// Write pass, one query per group: intersecting subqueries grouped by leaf
+// (record: query, slot of the subquery in query order), covering leaves per
+// query.  A query whose list fit reads it back, kSplitGroup entries at a
+// time; a longer one enumerates its leaves again in the same order.  The
 // order inside a leaf's group does not matter: a subquery's results go to
 // the offset of its query-order slot.
 __global__ void __launch_bounds__(kBlock) k_q_write(
@@ -840,58 +866,46 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
   if (ctl->go_split) {
     const uint64_t seq = ctl->qry_seq;
     tr.tlev = ctl->tlev;
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
+    const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
+    const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
+    const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
+    for (uint32_t k = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; k < nq; k += ngroups) {
       const uint32_t n = q_ni[k] + q_nc[k];
       if (n == 0) continue;
-      uint32_t wi = q_ioff[k], wc = q_coff[k], i = 0;
-      const uint64_t lb = list_base(k, slots);
-      const uint32_t *lst = qlist + lb, *pos = qpos + lb;
-      // i-th leaf of the query's walk (the count pass walked in the same order)
-      auto emit = [&](uint32_t leaf, bool c) {
-        if (c) {
-          cov_leaf[wc++] = leaf;
-          covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
-        } else {
-          const uint32_t p =
-              i < slots ? pos[i * kWave] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
-          sq[leaf_sqoff[leaf] + p] = make_uint2(k, wi++);
-        }
-        ++i;
-      };
+      const uint32_t wi = q_ioff[k], wc = q_coff[k];
+      const uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
       if (n <= slots) {
-        // eight entries at a time: their loads are independent
-        for (uint32_t j0 = 0; j0 < n; j0 += 8u) {
-          uint32_t e[8], p[8], off[8];
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j) {
-            const bool v = j0 + j < n;
-            e[j] = v ? lst[(j0 + j) * kWave] : kLeafBit;
-            p[j] = v ? pos[(j0 + j) * kWave] : 0u;
+        uint32_t ri = 0, rc = 0;
+        for (uint32_t i0 = 0; i0 < n; i0 += kSplitGroup) {
+          const uint32_t i = i0 + gl;
+          const bool v = i < n;
+          const uint32_t e = v ? lst[i] : 0u;
+          const bool c = v && (e & kLeafBit), x = v && !(e & kLeafBit);
+          const uint32_t leaf = e & ~kLeafBit;
+          const uint64_t mi = ballot(x) & gm, mc = ballot(c) & gm;
+          if (x) sq[leaf_sqoff[leaf] + pos[i]] = make_uint2(k, wi + ri + mbcnt(mi));
+          if (c) {
+            cov_leaf[wc + rc + mbcnt(mc)] = leaf;
+            covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
           }
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j)
-            off[j] = (e[j] & kLeafBit) ? 0u : leaf_sqoff[e[j]];
-#pragma unroll
-          for (uint32_t j = 0; j < 8u; ++j) {
-            if (j0 + j >= n) continue;
-            const uint32_t leaf = e[j] & ~kLeafBit;
-            if (e[j] & kLeafBit) {
-              cov_leaf[wc++] = leaf;
-              covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
-            } else {
-              sq[off[j] + p[j]] = make_uint2(k, wi++);
-            }
-          }
+          ri += (uint32_t)__popcll(mi);
+          rc += (uint32_t)__popcll(mc);
         }
       } else {
         QBox q;
         bool bad_rect;
         query_box(ctl, k, qid[k], N, qstamp, seq, qrect[k], &q, &bad_rect);
-        auto visit = [&](uint32_t leaf, bool cov) {
-          if (leaf_beg[leaf + 1] == leaf_beg[leaf]) return;
-          emit(leaf, cov && covering);
+        auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t ri, uint32_t rc) {
+          if (c) {
+            cov_leaf[wc + rc] = leaf;
+            covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
+            return;
+          }
+          const uint32_t p =
+              i < slots ? pos[i] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
+          sq[leaf_sqoff[leaf] + p] = make_uint2(k, wi + ri);
         };
-        for_each_leaf(tr, stack + threadIdx.x, q, visit);
+        group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm, visit);
       }
     }
   }
@@ -1470,7 +1484,7 @@ void launch_leaves(const Bufs &B, hipStream_t s) {
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s) {
-  LAUNCH(k_q_count, grid_for(nq, 4096), kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
+  LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
          (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
          B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering);
   ScanJobs jobs{};
