@@ -1046,14 +1046,20 @@ __global__ void __launch_bounds__(kBlock) k_task_recs(const Ctl *ctl, const uint
   }
 }
 
-// A task is joined by one wave, 64 subqueries at a time.  Their
-// rectangles (and, in the write pass, their result offsets) are staged in
-// the wave's LDS slice, so each lane reads subquery kk's with one broadcast
-// load; the leaf's objects are held in registers, 64 x NCH at a time, one
-// per lane and chunk.  The containment tests of a subquery against a chunk
-// are one ballot: the count pass adds its popcount, the write pass compacts
-// the hits with each lane's rank among them.
+// A task (at most kTaskSub = 64 intersecting subqueries of one leaf) is
+// joined by one wave.  The subqueries' rectangles (and, in the write pass,
+// their first result offsets) are staged in the wave's LDS slice, so each
+// lane reads subquery kk's with one broadcast load; the leaf's objects are
+// held in registers, 64 x NCH at a time, one per lane and chunk.  A wave
+// reads the record of its next task and that task's subquery entries
+// while it joins the current one, and issues a task's object loads
+// together with the gathers of its rectangles (and offsets), so a task
+// waits for one round of loads.  The containment tests of a subquery
+// against a chunk are one ballot per rectangle bound: the count pass adds
+// their popcount, the write pass compacts the hits with each lane's rank
+// among them.
 constexpr uint32_t kJoinRegChunks = 8;  // object chunks of 64 in registers
+static_assert(kTaskSub <= (uint32_t)kWave, "a task's subqueries fit one wave");
 
 // Orders a wave's LDS stores before its later loads of other lanes' slots
 // (and the loads before the next stores).
@@ -1066,9 +1072,32 @@ __device__ __forceinline__ uint32_t chunk_count(uint32_t o0, uint32_t oe) {
   return min(kJoinRegChunks, (oe - o0 + (uint32_t)kWave - 1u) / (uint32_t)kWave);
 }
 
-// Chunk c of a block: lane l holds object o0 + 64 c + l when it is below
-// oe (mask h[c]); the other lanes hold a copy of the last object, which
-// the mask excludes.
+// Task records are read one task ahead with lane l holding component
+// l & 3, so the load stays in flight until the components are read out.
+// The loads made ahead are issued on every path, at an in-range index, so
+// that the count of loads in flight is fixed and waiting for the oldest
+// does not wait for the others.
+__device__ __forceinline__ uint32_t rec_load(const uint32_t *trec32, uint32_t t, uint32_t nt,
+                                             uint32_t lane) {
+  return trec32[(uint64_t)(t < nt ? t : 0u) * 4u + (lane & 3u)];
+}
+// Past the last task (t >= nt): an empty record.
+__device__ __forceinline__ uint4 rec_read(uint32_t v, uint32_t t, uint32_t nt) {
+  const uint4 r = make_uint4((uint32_t)__builtin_amdgcn_readlane((int)v, 0),
+                             (uint32_t)__builtin_amdgcn_readlane((int)v, 1),
+                             (uint32_t)__builtin_amdgcn_readlane((int)v, 2),
+                             (uint32_t)__builtin_amdgcn_readlane((int)v, 3));
+  return t < nt ? r : make_uint4(0u, 0u, 0u, 0u);
+}
+// Lane l's subquery entry (query, slot) of a task (l < its count).
+__device__ __forceinline__ uint2 sq_entry(const uint2 *__restrict__ sq, const uint4 rec,
+                                          uint32_t lane) {
+  return sq[rec.x < rec.y ? min(rec.x + lane, rec.y - 1u) : 0u];
+}
+
+// Chunk c of a block at o0: lane l holds object o0 + 64 c + l when it is
+// below oe (mask h[c]); the other lanes hold a copy of the last object,
+// which the mask excludes.
 template <uint32_t NCH>
 __device__ __forceinline__ void load_chunks(const float2 *__restrict__ sxy, uint32_t o0,
                                             uint32_t oe, uint32_t lane, float2 *p, uint64_t *h) {
@@ -1080,20 +1109,26 @@ __device__ __forceinline__ void load_chunks(const float2 *__restrict__ sxy, uint
   }
 }
 
+template <uint32_t NCH>
+__device__ __forceinline__ void load_ids(const uint32_t *__restrict__ sid, uint32_t o0,
+                                         uint32_t oe, uint32_t lane, uint32_t *id) {
+#pragma unroll
+  for (uint32_t c = 0; c < NCH; ++c) id[c] = sid[min(o0 + c * (uint32_t)kWave + lane, oe - 1u)];
+}
+
 // Lanes whose object lies in the closed rectangle r: one ballot per bound,
 // so the four comparisons stay lane masks.
 __device__ __forceinline__ uint64_t hits(const float4 r, const float2 p, uint64_t h) {
   return ballot(r.x <= p.x) & ballot(p.x <= r.z) & ballot(r.y <= p.y) & ballot(p.y <= r.w) & h;
 }
 
+// Hits of subqueries 0..nk-1 against NCH chunks; lane kk returns subquery
+// kk's.
 template <uint32_t NCH>
-__device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk,
-                                                const float2 *__restrict__ sxy, uint32_t o0,
-                                                uint32_t oe, uint32_t lane) {
-  float2 p[NCH];
-  uint64_t h[NCH];
-  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
-  uint32_t blk = 0;  // lane kk: hits of subquery kk in this block
+__device__ __forceinline__ uint32_t count_rounds(const float4 *wrect, uint32_t nk,
+                                                 const float2 *p, const uint64_t *h,
+                                                 uint32_t lane) {
+  uint32_t blk = 0;
   for (uint32_t kk = 0; kk < nk; ++kk) {
     const float4 r = wrect[kk];
     uint32_t tot = 0;
@@ -1104,10 +1139,40 @@ __device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk
   return blk;
 }
 
+// First block of a task: its object loads go out with the gathers of the
+// subquery rectangles (lane kk < nk: subquery kk's, returned in *r).
+template <uint32_t NCH>
+__device__ __forceinline__ uint32_t count_first(float4 *wrect, uint32_t nk,
+                                                const float2 *__restrict__ sxy, uint32_t ob,
+                                                uint32_t oe, const float4 *__restrict__ qrect,
+                                                uint2 e, uint32_t lane, float4 *r) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  load_chunks<NCH>(sxy, ob, oe, lane, p, h);
+  if (lane < nk) {
+    *r = qrect[e.x];
+    wrect[lane] = *r;
+  }
+  wave_lds_fence();
+  return count_rounds<NCH>(wrect, nk, p, h, lane);
+}
+
+// A further block of a long leaf.
+template <uint32_t NCH>
+__device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk,
+                                                const float2 *__restrict__ sxy, uint32_t o0,
+                                                uint32_t oe, uint32_t lane) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
+  return count_rounds<NCH>(wrect, nk, p, h, lane);
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint4 *trec,
                                                        const uint32_t *tleaf,
-                                                       const uint32_t *leaf_sqoff, const uint2 *sq,
-                                                       const float4 *qrect,
+                                                       const uint32_t *leaf_sqoff,
+                                                       const uint2 *__restrict__ sq,
+                                                       const float4 *__restrict__ qrect,
                                                        const float2 *__restrict__ sxy,
                                                        uint32_t *sq_cnt, float *tlog,
                                                        const uint32_t *lstart,
@@ -1119,39 +1184,52 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  if (w0 >= nt) return;
   float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
-  uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
-  for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint4 tr = next;  // this task's record, loaded during the previous one
-    if (t + nwaves < nt) next = trec[t + nwaves];
-    const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
-    if (sb >= se) continue;
+  const uint32_t *trec32 = (const uint32_t *)trec;
+  uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
+  uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
+  uint2 ea = sq_entry(sq, rec, lane), eb;
+  // one step per task: the next task's entries and the record after it are
+  // loaded first; the record is read out after this task's own loads have
+  // been waited for, so no wait is spent on it.  The entry registers
+  // alternate roles, so none is copied (a copy would wait for its load).
+  auto step = [&](uint32_t t, const uint2 e, uint2 &enx) {
+    enx = sq_entry(sq, rn, lane);
+    const uint32_t recv = rec_load(trec32, t + 2u * nwaves, nt, lane);
+    const uint32_t sb = rec.x, se = rec.y, ob = rec.z, oe = rec.w;
+    rec = rn;
+    if (sb >= se) {
+      rn = rec_read(recv, t + 2u * nwaves, nt);
+      return;
+    }
     const uint32_t leaf = tlog ? tleaf[t] : 0u;
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
-    float ovl = 0.0f;
-    for (uint32_t sc = sb; sc < se; sc += kWave) {
-      const uint32_t nk = min((uint32_t)kWave, se - sc);
-      uint32_t slot = 0, cnt = 0;
-      wave_lds_fence();
-      if (lane < nk) {
-        const uint2 e = sq[sc + lane];
-        slot = e.y;
-        const float4 r = qrect[e.x];
-        wrect[lane] = r;
-        if (tlog) ovl += overlap_frac(ctl, lstart, llevel, leaf, r);
-      }
-      wave_lds_fence();
-      for (uint32_t o0 = ob; o0 < oe; o0 += (uint32_t)kWave * kJoinRegChunks) {
-        const uint32_t nch = chunk_count(o0, oe);
-        cnt += nch <= 1u   ? count_block<1>(wrect, nk, sxy, o0, oe, lane)
-               : nch <= 2u ? count_block<2>(wrect, nk, sxy, o0, oe, lane)
-               : nch <= 4u ? count_block<4>(wrect, nk, sxy, o0, oe, lane)
+    const uint32_t nk = se - sb;  // at most kTaskSub
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t cnt = 0;
+    wave_lds_fence();
+    if (ob < oe) {
+      const uint32_t nch = chunk_count(ob, oe);
+      cnt = nch <= 1u   ? count_first<1>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
+            : nch <= 2u ? count_first<2>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
+            : nch <= 4u ? count_first<4>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
+                        : count_first<8>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r);
+      for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
+           o0 += (uint32_t)kWave * kJoinRegChunks) {
+        const uint32_t nc2 = chunk_count(o0, oe);
+        cnt += nc2 <= 1u   ? count_block<1>(wrect, nk, sxy, o0, oe, lane)
+               : nc2 <= 2u ? count_block<2>(wrect, nk, sxy, o0, oe, lane)
+               : nc2 <= 4u ? count_block<4>(wrect, nk, sxy, o0, oe, lane)
                            : count_block<8>(wrect, nk, sxy, o0, oe, lane);
       }
-      if (lane < nk) sq_cnt[slot] = cnt;
+    } else if (tlog && lane < nk) {
+      r = qrect[e.x];
     }
+    rn = rec_read(recv, t + 2u * nwaves, nt);
+    if (lane < nk) sq_cnt[e.y] = cnt;
     if (tlog) {  // a leaf's record sums its tasks: mean overlap, clock ticks
-      ovl = wave_sum(ovl);
+      const float ovl = wave_sum(lane < nk ? overlap_frac(ctl, lstart, llevel, leaf, r) : 0.0f);
       const uint64_t clk1 = __builtin_amdgcn_s_memrealtime();
       if (lane == 0) {
         const float nsq = (float)(leaf_sqoff[leaf + 1] - leaf_sqoff[leaf]);
@@ -1159,6 +1237,11 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
         atomicAdd(&tlog[(uint64_t)leaf * 8 + 4], (float)(clk1 - clk0));
       }
     }
+  };
+  for (uint32_t t = w0; t < nt; t += 2u * nwaves) {
+    step(t, ea, eb);
+    if (t + nwaves >= nt) break;
+    step(t + nwaves, eb, ea);
   }
 }
 
@@ -1203,21 +1286,16 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
   ctl->want_rebuild = policy == 0u && (leaf_big || moved_out || periodic || !ctl->built);
 }
 
+// Subqueries 0..nk-1 against NCH chunks: each hit goes to its subquery's
+// next free result slot (woff, advanced in LDS when more objects follow).
 template <uint32_t NCH>
-__device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff, uint32_t nk,
-                                            const float2 *__restrict__ sxy,
-                                            const uint32_t *__restrict__ sid, uint32_t o0,
-                                            uint32_t oe, uint32_t lane,
-                                            uint32_t *__restrict__ res_ids, bool more) {
-  float2 p[NCH];
-  uint64_t h[NCH];
-  uint32_t id[NCH];
-  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
-#pragma unroll
-  for (uint32_t c = 0; c < NCH; ++c) id[c] = sid[min(o0 + c * (uint32_t)kWave + lane, oe - 1u)];
+__device__ __forceinline__ void write_rounds(const float4 *wrect, uint64_t *woff, uint32_t nk,
+                                             const float2 *p, const uint64_t *h,
+                                             const uint32_t *id, uint32_t *__restrict__ res_ids,
+                                             bool more) {
   for (uint32_t kk = 0; kk < nk; ++kk) {
     const float4 r = wrect[kk];
-    uint64_t base = woff[kk];  // next free result slot of subquery kk
+    uint64_t base = woff[kk];
 #pragma unroll
     for (uint32_t c = 0; c < NCH; ++c) {
       const uint64_t m = hits(r, p[c], h[c]);
@@ -1228,12 +1306,51 @@ __device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff,
   }
 }
 
+// First block of a task: object loads and the gathers of the subqueries'
+// rectangles and result offsets go out together.
+template <uint32_t NCH>
+__device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint32_t nk,
+                                            const float2 *__restrict__ sxy,
+                                            const uint32_t *__restrict__ sid, uint32_t ob,
+                                            uint32_t oe, const float4 *__restrict__ qrect,
+                                            const uint64_t *__restrict__ res_off, uint2 e,
+                                            uint32_t lane, uint32_t *__restrict__ res_ids,
+                                            bool more) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  uint32_t id[NCH];
+  load_chunks<NCH>(sxy, ob, oe, lane, p, h);
+  load_ids<NCH>(sid, ob, oe, lane, id);
+  if (lane < nk) {
+    const float4 r = qrect[e.x];
+    woff[lane] = res_off[e.y];
+    wrect[lane] = r;
+  }
+  wave_lds_fence();
+  write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
+}
+
+template <uint32_t NCH>
+__device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff, uint32_t nk,
+                                            const float2 *__restrict__ sxy,
+                                            const uint32_t *__restrict__ sid, uint32_t o0,
+                                            uint32_t oe, uint32_t lane,
+                                            uint32_t *__restrict__ res_ids, bool more) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  uint32_t id[NCH];
+  load_chunks<NCH>(sxy, o0, oe, lane, p, h);
+  load_ids<NCH>(sid, o0, oe, lane, id);
+  write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
+}
+
 __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
-                                                       const uint32_t *tleaf, const uint2 *sq,
-                                                       const float4 *qrect,
+                                                       const uint32_t *tleaf,
+                                                       const uint2 *__restrict__ sq,
+                                                       const float4 *__restrict__ qrect,
                                                        const float2 *__restrict__ sxy,
                                                        const uint32_t *__restrict__ sid,
-                                                       const uint64_t *res_off,
+                                                       const uint64_t *__restrict__ res_off,
                                                        uint32_t *__restrict__ res_ids,
                                                        uint32_t nq, const uint32_t *q_ioff,
                                                        uint64_t *q_roff, float *tlog) {
@@ -1260,39 +1377,58 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint64_t *woff = loff + (threadIdx.x & ~(uint32_t)(kWave - 1));
-  uint4 next = w0 < nt ? trec[w0] : make_uint4(0u, 0u, 0u, 0u);
-  for (uint32_t t = w0; t < nt; t += nwaves) {
-    const uint4 tr = next;  // this task's record, loaded during the previous one
-    if (t + nwaves < nt) next = trec[t + nwaves];
-    const uint32_t sb = tr.x, se = tr.y, ob = tr.z, oe = tr.w;
-    if (sb >= se) continue;
-    const uint32_t leaf = tlog ? tleaf[t] : 0u;
-    const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
-    for (uint32_t sc = sb; sc < se; sc += kWave) {
-      const uint32_t nk = min((uint32_t)kWave, se - sc);
-      wave_lds_fence();
-      if (lane < nk) {
-        const uint2 e = sq[sc + lane];
-        woff[lane] = res_off[e.y];
-        wrect[lane] = qrect[e.x];
+  if (w0 < nt) {
+    const uint32_t *trec32 = (const uint32_t *)trec;
+    uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
+    uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
+    uint2 ea = sq_entry(sq, rec, lane), eb;
+    auto step = [&](uint32_t t, const uint2 e, uint2 &enx) {
+      enx = sq_entry(sq, rn, lane);
+      const uint32_t recv = rec_load(trec32, t + 2u * nwaves, nt, lane);
+      const uint32_t sb = rec.x, se = rec.y, ob = rec.z, oe = rec.w;
+      rec = rn;
+      if (sb >= se || ob >= oe) {
+        rn = rec_read(recv, t + 2u * nwaves, nt);
+        return;
       }
+      const uint32_t leaf = tlog ? tleaf[t] : 0u;
+      const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
+      const uint32_t nk = se - sb;  // at most kTaskSub
+      const uint32_t nch = chunk_count(ob, oe);
+      const bool more = ob + (uint32_t)kWave * kJoinRegChunks < oe;
       wave_lds_fence();
-      for (uint32_t o0 = ob; o0 < oe; o0 += (uint32_t)kWave * kJoinRegChunks) {
-        const uint32_t nch = chunk_count(o0, oe);
-        const bool more = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
-        if (nch <= 1u)
-          write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
-        else if (nch <= 2u)
-          write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
-        else if (nch <= 4u)
-          write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
-        else
-          write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more);
+      if (nch <= 1u)
+        write_first<1>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
+      else if (nch <= 2u)
+        write_first<2>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
+      else if (nch <= 4u)
+        write_first<4>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
+      else
+        write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
+      rn = rec_read(recv, t + 2u * nwaves, nt);
+      for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
+           o0 += (uint32_t)kWave * kJoinRegChunks) {
+        const uint32_t nc2 = chunk_count(o0, oe);
+        const bool more2 = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
         wave_lds_fence();
+        if (nc2 <= 1u)
+          write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+        else if (nc2 <= 2u)
+          write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+        else if (nc2 <= 4u)
+          write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+        else
+          write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
       }
+      if (tlog && lane == 0)
+        atomicAdd(&tlog[(uint64_t)leaf * 8 + 5],
+                  (float)(__builtin_amdgcn_s_memrealtime() - clk0));
+    };
+    for (uint32_t t = w0; t < nt; t += 2u * nwaves) {
+      step(t, ea, eb);
+      if (t + nwaves >= nt) break;
+      step(t + nwaves, eb, ea);
     }
-    if (tlog && lane == 0)
-      atomicAdd(&tlog[(uint64_t)leaf * 8 + 5], (float)(__builtin_amdgcn_s_memrealtime() - clk0));
   }
   query_offsets();
 }
