@@ -186,10 +186,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.leaf_ovfc = c.take<uint32_t>(L);
   // join tasks: one per leaf and one per further kTaskSub subqueries of a leaf
   const uint64_t T = (uint64_t)L + d.S / sj::kTaskSub + 1u;
-  b.tasks = c.take<uint32_t>(T);
   b.tkey = c.take<uint32_t>(T);
-  b.tasks2 = c.take<uint32_t>(T);
-  b.tkey2 = c.take<uint32_t>(T);
+  b.tkhist = c.take<uint32_t>(512);
   b.vtask = c.take<uint2>(T - L);
   b.xbase = c.take<uint32_t>(L);
   b.trec = c.take<uint4>(T);

@@ -34,7 +34,8 @@ struct Bufs {
   uint32_t *leaf_beg, *leaf_nsq, *leaf_sqoff;
   uint32_t *leaf_ovf, *leaf_ovfc;       // subqueries past a query's list: count, cursor
   // schedule
-  uint32_t *tasks, *tkey, *tasks2, *tkey2;  // join tasks (TCAP)
+  uint32_t *tkey;                       // order key of every join task (TCAP)
+  uint32_t *tkhist;                     // 256 task-key totals, 256 placement cursors
   uint2 *vtask;                         // further chunks of heavy leaves: (leaf, chunk)
   uint32_t *xbase;                      // per leaf: task index of its second chunk
   uint4 *trec;                          // tasks in run order: subquery and object ranges

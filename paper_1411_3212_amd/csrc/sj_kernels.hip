@@ -226,10 +226,11 @@ __device__ __forceinline__ uint32_t block_minmax_1024(uint32_t v, uint32_t *lds)
 // and 2; they do nothing unless ctl->rebuild is set).
 __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk,
                                                          const uint64_t *red, uint4 *front0,
-                                                         uint32_t decision, uint32_t policy,
-                                                         uint64_t upd_total) {
+                                                         uint32_t *tkhist, uint32_t decision,
+                                                         uint32_t policy, uint64_t upd_total) {
   __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
   const int t = threadIdx.x;
+  if (t < 512) tkhist[t] = 0;  // task-order totals and cursors of this tick
   const uint32_t mnx = block_minmax_1024<false>((uint32_t)red[kRedMinX * kChunkBlocks + t], lds);
   const uint32_t mny = block_minmax_1024<false>((uint32_t)red[kRedMinY * kChunkBlocks + t], lds);
   const uint32_t mxx = block_minmax_1024<true>((uint32_t)red[kRedMaxX * kChunkBlocks + t], lds);
@@ -251,6 +252,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   ctl->n_isect = ctl->n_cov = ctl->n_res = ctl->cov_pairs = ctl->tests = 0;
   ctl->n32[0] = ctl->n32[1] = 0;
   ctl->n_tasks = 0;
+  ctl->n_run = 0;
   ctl->max_leaf = 0;
   bool r;
   if (decision == 0u)
@@ -925,9 +927,12 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 // Task e < n_leaves is the first chunk of leaf e; the further chunks of
 // heavy leaves are appended (vtask: leaf, chunk).  Key of a task: 255 - bit
 // length of its weight |subqueries of the chunk| x |objects| (ascending =
-// heaviest first; weight 0 last); a one-pass radix sort of the keys gives
-// the order.  Which task joins which subquery does not depend on the order,
-// so neither do the results.  Also the per-block partials of the
+// heaviest first; 255: no work), or 0 for every task with work when the
+// order is not wanted.  A counting sort over the 256 keys gives the run
+// order: the keys are counted per block as they are made, and one kernel
+// places the tasks with work (tasks of one key in any order) and writes
+// their records.  Which task joins which subquery does not depend on the
+// order, so neither do the results.  Also the per-block partials of the
 // containment-test count, the largest leaf above l_max and the number of
 // leaves with work.
 __device__ __forceinline__ uint32_t task_key(uint64_t w) {
@@ -937,11 +942,18 @@ __device__ __forceinline__ uint32_t task_key(uint64_t w) {
 __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *leaf_beg,
                                                       const uint32_t *leaf_sqoff,
                                                       const uint32_t *llevel, uint32_t l_max,
-                                                      uint32_t *tkey, uint32_t *tasks,
-                                                      uint2 *vtask, uint32_t *xbase,
-                                                      uint32_t tcap, uint64_t *red, float *tlog) {
+                                                      uint32_t *tkey, uint2 *vtask,
+                                                      uint32_t *xbase, uint32_t tcap,
+                                                      uint64_t *red, float *tlog,
+                                                      uint32_t *tkhist, uint32_t reorder,
+                                                      uint32_t count) {
   __shared__ uint64_t s_tests[kWavesPerBlock];
   __shared__ uint32_t s_max[kWavesPerBlock], s_tasks[kWavesPerBlock];
+  __shared__ uint32_t lh[256];  // block-local key counts, added to the totals at the end
+  static_assert(kBlock == 256, "one key count per thread");
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+  auto key_of = [&](uint64_t w) { return reorder ? task_key(w) : (w ? 0u : 255u); };
   const uint32_t n = ctl->n_leaves;
   const bool ok = ctl->go_split != 0;
   uint64_t tests = 0;
@@ -959,8 +971,9 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *
     tests += w;
     nt += w != 0;
     if (llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
-    tkey[t] = task_key((uint64_t)(nsq < kTaskSub ? nsq : kTaskSub) * cnt);
-    tasks[t] = t;
+    const uint32_t k0 = key_of((uint64_t)(nsq < kTaskSub ? nsq : kTaskSub) * cnt);
+    tkey[t] = k0;
+    if (count && k0 < 255u) atomicAdd(&lh[k0], 1u);
     if (more) xbase[t] = base;
     for (uint32_t c = 1; c <= more; ++c) {
       const uint32_t e = base + c - 1u;
@@ -970,8 +983,9 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *
       }
       const uint32_t sub = nsq - c * kTaskSub;
       vtask[e - n] = make_uint2(t, c);
-      tkey[e] = task_key((uint64_t)(sub < kTaskSub ? sub : kTaskSub) * cnt);
-      tasks[e] = e;
+      const uint32_t ke = key_of((uint64_t)(sub < kTaskSub ? sub : kTaskSub) * cnt);
+      tkey[e] = ke;
+      if (count && ke < 255u) atomicAdd(&lh[ke], 1u);
     }
     if (tlog) {
       float *rec = tlog + (uint64_t)t * 8;
@@ -982,6 +996,8 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *
     }
   }
   flag_error(ctl, kErrOvfSubq, ovf);  // unreachable: entries <= leaves + subqueries / kTaskSub
+  __syncthreads();
+  if (lh[threadIdx.x]) atomicAdd(&tkhist[threadIdx.x], lh[threadIdx.x]);
   tests = wave_sum(tests);
   nt = wave_sum(nt);
   mx = wave_max(mx);
@@ -1030,19 +1046,42 @@ __device__ __forceinline__ void task_range(uint32_t e, uint32_t n_leaves, const 
 }
 
 // Task records in run order: (first subquery, end, first object, end) and
-// the leaf, so that a join wave starts a task with one load.
-__global__ void __launch_bounds__(kBlock) k_task_recs(const Ctl *ctl, const uint32_t *tasks,
-                                                      const uint2 *vtask,
-                                                      const uint32_t *leaf_sqoff,
-                                                      const uint32_t *leaf_beg, uint4 *trec,
-                                                      uint32_t *tleaf) {
+// the leaf, so that a join wave starts a task with one load.  Every block
+// scans the 256 key totals to the start of each key's run; the tasks of a
+// block round are counted per key in LDS, and one atomic per key and round
+// reserves their places in the key's run.
+__global__ void __launch_bounds__(kBlock) k_task_place(Ctl *ctl, const uint32_t *tkey,
+                                                       const uint2 *vtask,
+                                                       const uint32_t *leaf_sqoff,
+                                                       const uint32_t *leaf_beg,
+                                                       uint32_t *tkhist, uint4 *trec,
+                                                       uint32_t *tleaf) {
+  __shared__ uint32_t kbase[256], lcnt[256], lres[256];
+  __shared__ uint32_t lds[kWavesPerBlock + 1];
+  static_assert(kBlock == 256, "one key per thread");
   if (!ctl->go_split) return;
-  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nt; t += gridDim.x * kBlock) {
-    uint32_t leaf, sb, se;
-    task_range(tasks[t], nl, vtask, leaf_sqoff, &leaf, &sb, &se);
-    trec[t] = make_uint4(sb, se, leaf_beg[leaf], leaf_beg[leaf + 1]);
-    tleaf[t] = leaf;
+  const uint32_t nt = ctl->n_entries, nl = ctl->n_leaves, tid = threadIdx.x;
+  uint32_t total;
+  kbase[tid] = block_excl_scan<uint32_t, kBlock>(tid < 255u ? tkhist[tid] : 0u, lds, &total);
+  if (blockIdx.x == 0 && tid == 0) ctl->n_run = total;
+  for (uint32_t e0 = blockIdx.x * kBlock; e0 < nt; e0 += gridDim.x * kBlock) {
+    lcnt[tid] = 0;
+    __syncthreads();
+    const uint32_t e = e0 + tid;
+    const uint32_t key = e < nt ? tkey[e] : 255u;
+    uint32_t r = 0;
+    if (key < 255u) r = atomicAdd(&lcnt[key], 1u);
+    __syncthreads();
+    if (lcnt[tid]) lres[tid] = atomicAdd(&tkhist[256 + tid], lcnt[tid]);
+    __syncthreads();
+    if (key < 255u) {
+      const uint32_t pos = kbase[key] + lres[key] + r;
+      uint32_t leaf, sb, se;
+      task_range(e, nl, vtask, leaf_sqoff, &leaf, &sb, &se);
+      trec[pos] = make_uint4(sb, se, leaf_beg[leaf], leaf_beg[leaf + 1]);
+      tleaf[pos] = leaf;
+    }
+    __syncthreads();
   }
 }
 
@@ -1179,7 +1218,7 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
                                                        const uint32_t *llevel) {
   __shared__ float4 lrect[kBlock];
   if (!ctl->go_split) return;
-  const uint32_t nt = ctl->n_entries;
+  const uint32_t nt = ctl->n_run;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
@@ -1370,7 +1409,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     query_offsets();
     return;
   }
-  const uint32_t nt = ctl->n_entries;
+  const uint32_t nt = ctl->n_run;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
@@ -1564,7 +1603,7 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
   LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N,
          (const Ctl *)B.ctl, B.blk, B.red);
   LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, (const uint64_t *)B.red, B.front[0],
-         decision, policy, upd_total);
+         B.tkhist, decision, policy, upd_total);
   if (decision == 0u && key_bits) {
     // the tree is kept and the host knows the leaf-key width: exactly the
     // passes it needs, starting from the buffer that makes them end in A
@@ -1640,19 +1679,14 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
 
 void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
                      hipStream_t s) {
+  const bool mlp = reorder && learned;  // the network's keys replace the weight keys
   LAUNCH(k_task_keys, kChunkBlocks, kBlock, s, B.ctl, (const uint32_t *)B.leaf_beg,
-         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.tasks,
-         B.vtask, B.xbase, B.TCAP, B.red, B.tlog);
-  const uint32_t *order = B.tasks;
-  if (reorder) {
-    if (learned) launch_schedule_mlp(B, s);
-    const bool alt = radix_sort_pairs(B.tkey, B.tasks, B.tkey2, B.tasks2, &B.ctl->n_entries,
-                                      &B.ctl->go_split, B.hist, B.tot, 0, 8, s);
-    order = alt ? B.tasks2 : B.tasks;
-  }
-  LAUNCH(k_task_recs, grid_for(B.TCAP, 4096), kBlock, s, (const Ctl *)B.ctl, order,
+         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.llevel, l_max, B.tkey, B.vtask,
+         B.xbase, B.TCAP, B.red, B.tlog, B.tkhist, reorder, mlp ? 0u : 1u);
+  if (mlp) launch_schedule_mlp(B, s);
+  LAUNCH(k_task_place, grid_for(B.TCAP, 2048), kBlock, s, B.ctl, (const uint32_t *)B.tkey,
          (const uint2 *)B.vtask, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.leaf_beg,
-         B.trec, B.tleaf);
+         B.tkhist, B.trec, B.tleaf);
 }
 
 void launch_join_count(const Bufs &B, hipStream_t s) {

@@ -156,13 +156,13 @@ __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const Tu
 
 // Learned schedule: the key of every join task of a leaf from the
 // network's prediction for that task (its subquery count is kTaskSub, or
-// what remains for the last one): 255 - min(254, 16 (ln us + 4)), so the
-// one-pass radix sort puts the longest predicted tasks first.  Keys of
-// tasks without work stay 255.
+// what remains for the last one): 254 - min(254, 16 (ln us + 4)), so the
+// counting sort over the keys puts the longest predicted tasks first.
+// Keys of tasks without work stay 255 (not run).
 __device__ __forceinline__ uint32_t time_key(float y) {
   const float q = 16.0f * (y + 4.0f);
   const uint32_t k = !(q > 0.0f) ? 0u : (q >= 254.0f ? 254u : (uint32_t)q);
-  return 255u - k;
+  return 254u - k;
 }
 
 __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const TuneState *ts,
@@ -173,11 +173,14 @@ __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const 
                                                           const uint32_t *lstart,
                                                           const uint32_t *llevel,
                                                           const uint32_t *xbase, uint32_t tcap,
-                                                          uint32_t *tkey) {
+                                                          uint32_t *tkey, uint32_t *tkhist) {
   __shared__ MlpLds m;
+  __shared__ uint32_t lh[256];
+  static_assert(kBlock == 256, "one key count per thread");
   stage_mlp(m, ts->w);
-  if (!ctl->go_split) return;
-  const uint32_t n = ctl->n_leaves;
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t n = ctl->go_split ? ctl->n_leaves : 0u;
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
@@ -194,13 +197,23 @@ __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const 
     const uint32_t last = nsq - more * kTaskSub;
     const uint32_t kl =
         more == 0u ? kf : time_key(wave_mlp(m, x0, log2f(1.0f + (float)last), x2, ov));
-    if (lane_id() == 0) tkey[t] = kf;
+    if (lane_id() == 0) {
+      tkey[t] = kf;
+      atomicAdd(&lh[kf], 1u);
+    }
     // further tasks: full chunks, the last one holds what remains
     for (uint32_t c = 1u + lane_id(); c <= more; c += kWave) {
       const uint32_t e = xbase[t] + c - 1u;
-      if (e < tcap) tkey[e] = c == more ? kl : kf;
+      if (e < tcap) {
+        const uint32_t k = c == more ? kl : kf;
+        tkey[e] = k;
+        atomicAdd(&lh[k], 1u);
+      }
     }
   }
+  __syncthreads();
+  const uint32_t c = lh[threadIdx.x];
+  if (c) atomicAdd(&tkhist[threadIdx.x], c);
 }
 
 // Predicted cost of candidate c (one block of kChunkBlocks threads): the
@@ -260,7 +273,7 @@ void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
   LAUNCH(k_task_keys_mlp, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
          (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
          (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel,
-         (const uint32_t *)B.xbase, B.TCAP, B.tkey);
+         (const uint32_t *)B.xbase, B.TCAP, B.tkey, B.tkhist);
 }
 
 void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
