@@ -73,7 +73,8 @@ def collect(name: str, n_ticks: int, cand=CAND, warm: int = 3, torch=None, log=p
     caps = serving.scene_capacities(wl)
     nq = max(q for _, _, q in ticks)
     rows = []
-    kw = {k: caps[k] for k in ("capacity_subqueries", "capacity_covering", "capacity_results")}
+    kw = {k: caps[k] for k in ("capacity_subqueries", "capacity_covering", "capacity_results",
+                               "split_slots")}
     for th in cand:
         logged = Scene(wl.n, nq, th=th, timing_log=True, **kw)
         plain = Scene(wl.n, nq, th=th, profile=True, **kw)
@@ -322,7 +323,7 @@ def compare(name: str, n_ticks: int, warm: int, torch, model: dict, th_fixed: in
     nq = max(q for _, _, q in ticks)
     kw = dict(capacity_subqueries=caps["capacity_subqueries"],
               capacity_covering=caps["capacity_covering"],
-              capacity_results=caps["capacity_results"])
+              capacity_results=caps["capacity_results"], split_slots=caps["split_slots"])
     out = dict(workload=name, objects=wl.n, queries_per_tick=nq, ticks=n_ticks - warm)
     fixed = Scene(wl.n, nq, th=th_fixed, **kw)
     out["fixed"] = run_ticks(fixed, ticks, torch, warm)

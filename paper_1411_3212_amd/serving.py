@@ -45,13 +45,17 @@ def scene_capacities(wl: workloads.Workload, th: int = 64) -> dict:
     kind = wl.params.get("kind", wl.name)
     rate = float(wl.params.get("query_rate", 0.1 if kind == "hotspot" else 0.5))
     q = max(1, int(round(rate * wl.n)))
+    slots = 0  # the library's default list length
     if kind == "hotspot":  # denser hotspots hold more leaves and results per query
         per = dict(sub=48, cov=48, res=512) if wl.n <= 2_000_000 else \
             dict(sub=160, cov=160, res=2048)
+        if wl.n > 2_000_000:
+            slots = 64  # queries in the dense cores overlap more than 32 leaves
     else:
         per = dict(sub=16, cov=16, res=96)
     return dict(nq=q, th=th, capacity_subqueries=per["sub"] * q,
-                capacity_covering=per["cov"] * q, capacity_results=per["res"] * q)
+                capacity_covering=per["cov"] * q, capacity_results=per["res"] * q,
+                split_slots=slots)
 
 
 def make_specs(n_scenes: int = 16, seed: int = 5, nmin: float = 1e5, nmax: float = 8e6,
