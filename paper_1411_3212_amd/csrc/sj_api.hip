@@ -188,6 +188,10 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   const uint64_t T = (uint64_t)L + d.S / sj::kTaskSub + 1u;
   b.tkey = c.take<uint32_t>(T);
   b.tkhist = c.take<uint32_t>(512);
+  b.qkey = c.take<uint32_t>(Q);
+  b.qord = c.take<uint32_t>(Q);
+  b.qkey2 = c.take<uint32_t>(Q);
+  b.qord2 = c.take<uint32_t>(Q);
   b.vtask = c.take<uint2>(T - L);
   b.xbase = c.take<uint32_t>(L);
   b.trec = c.take<uint4>(T);

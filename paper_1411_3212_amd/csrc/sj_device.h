@@ -53,6 +53,7 @@ struct Ctl {
   uint32_t n_tasks;       // leaves with join work
   uint32_t n_entries;     // join tasks: one per leaf + one per further kTaskSub subqueries
   uint32_t n_run;         // join tasks with work, in run order in the task records
+  uint32_t n_qord;        // queries put in spatial order
   uint32_t max_leaf;
   uint32_t err_upd;       // errors of updates since the last tick
   uint32_t err;           // errors of the current tick (includes err_upd)

@@ -35,6 +35,7 @@ struct Bufs {
   uint32_t *leaf_ovf, *leaf_ovfc;       // subqueries past a query's list: count, cursor
   // schedule
   uint32_t *tkey;                       // order key of every join task (TCAP)
+  uint32_t *qkey, *qord, *qkey2, *qord2;  // spatial processing order of the queries (Q)
   uint32_t *tkhist;                     // 256 task-key totals, 256 placement cursors
   uint2 *vtask;                         // further chunks of heavy leaves: (leaf, chunk)
   uint32_t *xbase;                      // per leaf: task index of its second chunk

@@ -778,6 +778,25 @@ __device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *sta
   return LeafCounts{nl, ni, nc};
 }
 
+// Processing order of a large query batch: by the Morton code of the
+// level-8 cell of the query's lower corner (a 16-bit key, two radix
+// passes), so that the queries a wave splits together overlap nearby
+// leaves and their subquery records land close together in the leaves'
+// groups.  Which group splits which query does not change what is
+// written, so the results do not depend on the order.
+constexpr uint32_t kQueryOrderMin = 1u << 20;
+
+__global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const float *xa,
+                                                        const float *ya, uint32_t nq,
+                                                        uint32_t *qkey, uint32_t *qord) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_qord = nq;
+  const float x0 = ctl->x0, y0 = ctl->y0, sc = ctl->scale;
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
+    qkey[k] = morton2(cell_of(xa[k], x0, sc) >> 8, cell_of(ya[k], y0, sc) >> 8);
+    qord[k] = k;
+  }
+}
+
 // Count pass, one query per group of kSplitGroup lanes: the numbers of
 // intersecting and covering subqueries per query and of intersecting
 // subqueries per leaf; the first `slots` entries of a query's list (leaf,
@@ -787,7 +806,8 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const uint32_t *qid, const float *xa, const float *ya, const float *xb,
     const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *leaf_nsq,
-    uint32_t *leaf_ovf, uint32_t *qlist, uint32_t *qpos, uint32_t slots, uint32_t covering) {
+    uint32_t *leaf_ovf, uint32_t *qlist, uint32_t *qpos, uint32_t slots, uint32_t covering,
+    const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
@@ -795,7 +815,8 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
   const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
   const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
   const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
-  for (uint32_t k = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; k < nq; k += ngroups) {
+  for (uint32_t g = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; g < nq; g += ngroups) {
+    const uint32_t k = qord ? qord[g] : g;
     bool bad_rect = false;
     uint32_t ni = 0, nc = 0;
     const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
@@ -861,7 +882,7 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
     const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, const uint32_t *qpos,
     uint32_t slots, const uint32_t *leaf_sqoff, const uint32_t *leaf_nsq, uint32_t *leaf_ovfc,
-    uint2 *sq, uint32_t *cov_leaf, uint32_t covering, uint64_t *red) {
+    uint2 *sq, uint32_t *cov_leaf, uint32_t covering, uint64_t *red, const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
   __shared__ uint64_t lds[kWavesPerBlock];
   uint64_t covp = 0;
@@ -871,7 +892,8 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
     const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
     const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
-    for (uint32_t k = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; k < nq; k += ngroups) {
+    for (uint32_t g = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; g < nq; g += ngroups) {
+      const uint32_t k = qord ? qord[g] : g;
       const uint32_t n = q_ni[k] + q_nc[k];
       if (n == 0) continue;
       const uint32_t wi = q_ioff[k], wc = q_coff[k];
@@ -1659,9 +1681,17 @@ void launch_leaves(const Bufs &B, hipStream_t s) {
 void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
                   const float *xb, const float *yb, uint32_t nq, uint32_t covering,
                   hipStream_t s) {
-  LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, qid, xa, ya, xb, yb, nq, B.N,
-         (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
-         B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering);
+  const uint32_t *qord = nullptr;
+  if (nq >= kQueryOrderMin) {
+    LAUNCH(k_qorder_keys, grid_for(nq), kBlock, s, B.ctl, xa, ya, nq, B.qkey, B.qord);
+    const bool alt = radix_sort_pairs(B.qkey, B.qord, B.qkey2, B.qord2, &B.ctl->n_qord, nullptr,
+                                      B.hist, B.tot, 0, 16, s);
+    qord = alt ? B.qord2 : B.qord;
+  }
+  LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, qid, xa, ya,
+         xb, yb, nq, B.N, (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg,
+         B.qrect, B.q_ni, B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering,
+         qord);
   ScanJobs jobs{};
   jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
   jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
@@ -1674,7 +1704,7 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
          (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, (const uint32_t *)B.qpos, B.slots,
          (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.leaf_nsq, B.leaf_ovfc, B.sq,
-         B.cov_leaf, covering, B.red);
+         B.cov_leaf, covering, B.red, qord);
 }
 
 void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,

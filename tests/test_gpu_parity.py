@@ -345,6 +345,33 @@ def test_hotspot_full_size_ticks():
             assert [lists[i] for i in sample] == want
 
 
+def test_million_query_batches_in_spatial_order():
+    """Batches of at least 2^20 queries are split in the spatial order of
+    their corners: every query by count + hash against the CPU grid, over a
+    tick that builds the quadtree and one that reuses it, and 300 sampled
+    queries by literal lists against the brute force."""
+    from bench import scene_config
+    wl = workloads.make("hotspot", n=1_200_000, n_ticks=2, query_rate=0.9)
+    st = oracle.State(wl.n)
+    cfg = scene_config(wl)
+    sc = Scene(wl.n, int(0.9 * wl.n), **cfg)
+    rng = np.random.default_rng(1)
+    for k, t in enumerate(wl.ticks()):
+        say(f"hotspot 1.2M objects, {t.nq} queries, tick {k}")
+        assert t.nq >= 1 << 20
+        oracle_apply(st, t)
+        gpu_tick(sc, t)
+        cnt, h = gpu_count_hash(sc)
+        oc, oh = oracle_count_hash(st, t, grid=True)
+        assert np.array_equal(cnt, oc) and np.array_equal(h, oh)
+        if k == 1:
+            lists = sc.fetch().to_lists()
+            sample = rng.choice(t.nq, 300, replace=False)
+            sub = T(qid=t.qid[sample], rects=tuple(r[sample] for r in t.rects))
+            want = oracle_lists(st, sub)
+            assert [lists[i] for i in sample] == want
+
+
 def test_graph_ticks_equal_eager_ticks():
     """Updates + tick replayed as a captured graph give the same bytes as the
     eager calls, through quadtree builds, reuse, and buffer changes."""
