@@ -1635,17 +1635,17 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
            (const uint32_t *)B.blk, odd ? B.keyB : B.keyA, odd ? B.valB : B.valA, qid, nq,
            B.qstamp);
     if (odd)
-      radix_sort_pairs(B.keyB, B.valB, B.keyA, B.valA, &B.ctl->n_present, nullptr, B.hist,
+      radix_sort_pairs(B.keyB, B.valB, B.keyA, B.valA, &B.ctl->n_present, B.N, nullptr, B.hist,
                        B.tot, 0, 8 * passes, s, B.pos, B.sxy);
     else
-      radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist,
+      radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, B.N, nullptr, B.hist,
                        B.tot, 0, 8 * passes, s, B.pos, B.sxy);
     return;
   }
   LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
          (const uint32_t *)B.blk, B.keyA, B.valA, qid, nq, B.qstamp);
-  radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, nullptr, B.hist, B.tot, 0,
-                   32, s, B.pos, B.sxy, &B.ctl->sort_skip);
+  radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, B.N, nullptr, B.hist,
+                   B.tot, 0, 32, s, B.pos, B.sxy, &B.ctl->sort_skip);
 }
 
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
@@ -1658,8 +1658,8 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
            B.LCAP);
   }
   LAUNCH(k_tree_done, 1, 1, s, B.ctl, B.LCAP, B.tcap, B.N);
-  radix_sort_pairs(B.lstart, B.llevel, B.lstart2, B.llevel2, &B.ctl->n_leaves, &B.ctl->rebuild,
-                   B.hist, B.tot, 0, 32, s);
+  radix_sort_pairs(B.lstart, B.llevel, B.lstart2, B.llevel2, &B.ctl->n_leaves, B.LCAP,
+                   &B.ctl->rebuild, B.hist, B.tot, 0, 32, s);
   LAUNCH(k_nodes_open, grid_for(B.LCAP), kBlock, s, (const Ctl *)B.ctl,
          (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.nopen);
   ScanJobs jobs{};
@@ -1684,7 +1684,7 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
   const uint32_t *qord = nullptr;
   if (nq >= kQueryOrderMin) {
     LAUNCH(k_qorder_keys, grid_for(nq), kBlock, s, B.ctl, xa, ya, nq, B.qkey, B.qord);
-    const bool alt = radix_sort_pairs(B.qkey, B.qord, B.qkey2, B.qord2, &B.ctl->n_qord, nullptr,
+    const bool alt = radix_sort_pairs(B.qkey, B.qord, B.qkey2, B.qord2, &B.ctl->n_qord, nq, nullptr,
                                       B.hist, B.tot, 0, 16, s);
     qord = alt ? B.qord2 : B.qord;
   }

@@ -151,13 +151,14 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const 
 
 __global__ void __launch_bounds__(kChunkBlocks) k_rs_hscan(uint32_t *hist, const uint32_t *gate,
                                                            const uint32_t *skip, int shift,
-                                                           uint32_t *tot) {
+                                                           uint32_t *tot, uint32_t nblk) {
   if (gated(gate) || pass_role(skip, shift) != kPassSort) return;
   __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
   uint32_t *h = hist + blockIdx.x * kChunkBlocks;
   uint32_t total;
-  uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(h[threadIdx.x], lds, &total);
-  h[threadIdx.x] = ex;
+  const bool mine = threadIdx.x < nblk;  // histograms of the grid's blocks only
+  uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(mine ? h[threadIdx.x] : 0u, lds, &total);
+  if (mine) h[threadIdx.x] = ex;
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
@@ -266,26 +267,29 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
 }
 
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                      const uint32_t *n_dev, const uint32_t *gate, uint32_t *hist, uint32_t *tot,
-                      int bit_begin, int bit_end, hipStream_t s, const float2 *gpos,
-                      float2 *gout, const uint32_t *skip) {
+                      const uint32_t *n_dev, uint64_t n_cap, const uint32_t *gate,
+                      uint32_t *hist, uint32_t *tot, int bit_begin, int bit_end, hipStream_t s,
+                      const float2 *gpos, float2 *gout, const uint32_t *skip) {
+  // about one tile per block when the count reaches its bound
+  uint64_t g = (n_cap + kSortTile - 1) / kSortTile;
+  const unsigned nblk = (unsigned)(g < 1 ? 1 : (g > kChunkBlocks ? kChunkBlocks : g));
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
   bool in_alt = false;
   const int last_shift = bit_end - 8;
   for (int shift = bit_begin; shift < bit_end; shift += 8) {
     // with a device key width any pass may be the one that gathers
     const bool may_gather = gout && (skip || shift == last_shift);
-    hipLaunchKernelGGL(k_rs_hist, dim3(kChunkBlocks), dim3(kBlock), 0, s, (const uint32_t *)ki,
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, (const uint32_t *)ki,
                        n_dev, gate, skip, shift, hist);
     hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, skip, shift,
-                       tot);
+                       tot, nblk);
     if (may_gather)
-      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nblk), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
                          shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot, gpos,
                          gout);
     else
-      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(kChunkBlocks), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nblk), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
                          shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot,
                          (const float2 *)nullptr, (float2 *)nullptr);
