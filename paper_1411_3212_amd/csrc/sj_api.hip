@@ -48,6 +48,7 @@ struct sj_scene {
   hipEvent_t ev[SJ_PH_COUNT + 2];
   hipEvent_t ev_u0, ev_u1;
   Ctl host_ctl;
+  Ctl *pin_ctl = nullptr;  // pinned landing buffer of its copies from the device
   bool cm_set;          // a cost model is installed (sj_set_cost_model)
   uint32_t n_cand;      // its candidate thresholds
   uint32_t tune_every;  // host-decided builds between two tunings
@@ -253,11 +254,12 @@ int status_of(sj_scene *s, uint32_t bits) {
 }
 
 int sync_ctl(sj_scene *s) {
-  hipError_t e = hipMemcpyAsync(&s->host_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
+  hipError_t e = hipMemcpyAsync(s->pin_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
                                 s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+  s->host_ctl = *s->pin_ctl;
   s->known = true;
   return SJ_OK;
 }
@@ -402,6 +404,11 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   s->tune_every = d.tune_every;
   s->known = true;  // host_ctl is zero: not built, the first tick builds
   (void)hipGetDevice(&s->device);
+  if (hipHostMalloc((void **)&s->pin_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    snprintf(g_create_err, sizeof g_create_err, "hipHostMalloc failed");
+    delete s;
+    return SJ_EDEVICE;
+  }
   carve(d, s->ws, &s->B);
   if (s->prof) {
     bool ok = true;
@@ -410,6 +417,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
     ok = ok && hipEventCreate(&s->ev_u1) == hipSuccess;
     if (!ok) {
       snprintf(g_create_err, sizeof g_create_err, "hipEventCreate failed");
+      (void)hipHostFree(s->pin_ctl);
       delete s;
       return SJ_EDEVICE;
     }
@@ -422,6 +430,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     snprintf(g_create_err, sizeof g_create_err, "kernel launch: %s", hipGetErrorString(e));
+    (void)hipHostFree(s->pin_ctl);
     delete s;
     return SJ_EDEVICE;
   }
@@ -442,6 +451,7 @@ int sj_scene_destroy(sj_scene *s) {
     (void)hipEventDestroy(s->ev_u0);
     (void)hipEventDestroy(s->ev_u1);
   }
+  (void)hipHostFree(s->pin_ctl);
   delete s;
   return SJ_OK;
 }
