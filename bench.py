@@ -149,7 +149,7 @@ def learned_run(args, wl, ticks, slot, nq, cfg, c_fixed, lat_fixed, wall_fixed, 
     kw = {k: v for k, v in cfg.items() if k != "th"}
     sc = Scene(wl.n, nq, th=args.th, th_min=min(model["cand"]), thresh_mlp=True, **kw)
     costmodel.install(sc, model, torch)
-    counters = torch.zeros((args.warmup + args.steps, 8), dtype=torch.int64, device="cuda")
+    counters = np.zeros((args.warmup + args.steps, 8), dtype=np.int64)
     lat = []
     for i in range(args.warmup + args.steps):
         if i == args.warmup:
@@ -165,13 +165,12 @@ def learned_run(args, wl, ticks, slot, nq, cfg, c_fixed, lat_fixed, wall_fixed, 
             d = views(buf, m, q, torch)
             sc.apply_updates(d["ids"], d["x"], d["y"])
             sc.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
-        sc.counters_into(counters[i])
-        sc.fetch()
+        counters[i] = sc.fetch().counters()
         if i >= args.warmup:
             lat.append((time.perf_counter() - h0) * 1e3)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    c = counters.cpu().numpy()[args.warmup:]
+    c = counters[args.warmup:]
     info = sc.tune_info()
     K = args.steps
     pairs = int(c[:, 0].sum())
@@ -209,7 +208,7 @@ def main():
     slot = torch.empty(max(b.numel() for b, _, _ in ticks), dtype=torch.int32, device="cuda")
     cfg = scene_config(wl, args.th)
     scene = Scene(wl.n, nq, profile=True, **cfg)
-    counters = torch.zeros((n_ticks, 8), dtype=torch.int64, device="cuda")
+    counters = np.zeros((n_ticks, 8), dtype=np.int64)
     phase_sum = {k: 0.0 for k in PHASES}
     lat = []
     start_ev = torch.cuda.Event(enable_timing=True)
@@ -226,8 +225,8 @@ def main():
             d = views(buf, m, q, torch)
             scene.apply_updates(d["ids"], d["x"], d["y"])
             scene.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
-        scene.counters_into(counters[i])
-        scene.fetch()  # synchronises: the tick's results are available
+        # synchronises: the tick's results and counters are available
+        counters[i] = scene.fetch().counters()
         h1 = time.perf_counter()
         if timed:
             lat.append((h1 - h0) * 1e3)
@@ -250,7 +249,7 @@ def main():
     eager_phase = {k: 0.0 for k in PHASES}
     for i in range(args.warmup + args.steps, n_ticks):
         one_tick(i, False, mode="eager", phases=eager_phase)
-    c = counters.cpu().numpy()[args.warmup:args.warmup + args.steps]
+    c = counters[args.warmup:args.warmup + args.steps]
     assert (c[:, 7] == 0).all(), f"device error bits {np.unique(c[:, 7])}"
     pairs = int(c[:, 0].sum())
     K = args.steps

@@ -142,6 +142,15 @@ typedef struct sj_results {
   const uint32_t *d_cov_leaf;
   const uint32_t *d_leaf_beg;  /* [n_leaves + 1] */
   const uint32_t *d_sorted_id; /* [n_present] object ids in Morton order */
+  /* Counters of the tick, from the same read-back (0 for the result
+   * counts when the tick's results overflowed): */
+  uint32_t n_present;         /* objects with a position (= d_leaf_beg[n_leaves]) */
+  uint32_t n_tasks;           /* leaves with at least one intersecting subquery */
+  uint64_t n_subqueries;      /* intersecting subqueries on leaves with objects */
+  uint64_t cov_pairs;         /* result pairs given by covering leaves */
+  uint64_t tests;             /* containment tests of the filtering */
+  uint32_t error_bits;        /* SJ_ERR_* bits of the tick */
+  uint32_t reserved;
 } sj_results;
 
 /* Counters of the last tick (read back by sj_stats, which synchronises). */

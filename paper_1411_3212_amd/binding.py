@@ -45,7 +45,10 @@ class SjResults(Structure):
     _fields_ = [("nq", c_uint32), ("n_leaves", c_uint32), ("n_isect_ids", c_uint64),
                 ("n_cov_entries", c_uint64), ("total_pairs", c_uint64),
                 ("d_isect_off", c_void_p), ("d_isect_id", c_void_p), ("d_cov_off", c_void_p),
-                ("d_cov_leaf", c_void_p), ("d_leaf_beg", c_void_p), ("d_sorted_id", c_void_p)]
+                ("d_cov_leaf", c_void_p), ("d_leaf_beg", c_void_p), ("d_sorted_id", c_void_p),
+                ("n_present", c_uint32), ("n_tasks", c_uint32), ("n_subqueries", c_uint64),
+                ("cov_pairs", c_uint64), ("tests", c_uint64), ("error_bits", c_uint32),
+                ("reserved", c_uint32)]
 
 
 class SjTickStats(Structure):
@@ -183,14 +186,24 @@ class Results:
         self.n_isect_ids = int(r.n_isect_ids)
         self.n_cov_entries = int(r.n_cov_entries)
         self.total_pairs = int(r.total_pairs)
+        self.n_present = int(r.n_present)
+        self.n_tasks = int(r.n_tasks)
+        self.n_subqueries = int(r.n_subqueries)
+        self.cov_pairs = int(r.cov_pairs)
+        self.tests = int(r.tests)
+        self.error_bits = int(r.error_bits)
         v = scene._view
         self.isect_off = v(r.d_isect_off, self.nq + 1, torch.int64)
         self.isect_id = v(r.d_isect_id, self.n_isect_ids, torch.int32)
         self.cov_off = v(r.d_cov_off, self.nq + 1, torch.int32)
         self.cov_leaf = v(r.d_cov_leaf, self.n_cov_entries, torch.int32)
         self.leaf_beg = v(r.d_leaf_beg, self.n_leaves + 1, torch.int32)
-        n_present = int(self.leaf_beg[-1].item()) if self.n_leaves else 0
-        self.sorted_id = v(r.d_sorted_id, n_present, torch.int32)
+        self.sorted_id = v(r.d_sorted_id, self.n_present if self.n_leaves else 0, torch.int32)
+
+    def counters(self):
+        """The tick's counters in the order of Scene.counters_into."""
+        return [self.total_pairs, self.n_isect_ids, self.cov_pairs, self.n_subqueries,
+                self.n_cov_entries, self.tests, self.n_tasks, self.error_bits]
 
     def to_lists(self):
         """Per-query result lists (ascending ids), computed on the host from

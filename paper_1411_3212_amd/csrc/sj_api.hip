@@ -19,8 +19,9 @@ using sj::Ctl;
 
 struct GraphSlot {
   hipGraphExec_t exec;   // the whole tick, or its part before the join write pass
-  hipGraphExec_t exec2;  // the join write pass (profiled scenes only)
+  hipGraphExec_t exec2;  // the join write pass, when a profiled tick is two launches
   bool valid;
+  bool split;            // exec2 is launched after exec, between the timing events
   uint32_t m, nq, key_bits;
   const void *ptrs[8];
 };
@@ -443,7 +444,7 @@ int sj_scene_destroy(sj_scene *s) {
   for (auto &g : s->graphs) {
     if (!g.valid) continue;
     (void)hipGraphExecDestroy(g.exec);
-    if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+    if (g.split) (void)hipGraphExecDestroy(g.exec2);
   }
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->prof) {
@@ -523,40 +524,72 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
   if (!same) {
     if (g.valid) {
       (void)hipGraphExecDestroy(g.exec);
-      if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+      if (g.split) (void)hipGraphExecDestroy(g.exec2);
       g.valid = false;
     }
     // capture on a private stream (the caller's may be the null stream,
     // which cannot be captured); the graph is launched on the scene's stream.
     // Profiled scenes capture the join write pass as a graph of its own and
-    // time it with events recorded between the two launches.
+    // time it with events recorded around it.
     if (!s->cap_stream) {
       hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_fail(s, e, "hipStreamCreate");
     }
     const hipStream_t user = s->stream;
-    auto capture = [&](int part, hipGraphExec_t *out) -> int {
-      hipGraph_t graph;
+    auto capture = [&](int part, hipGraph_t *out) -> int {
       hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
       s->stream = s->cap_stream;
       if (part != 2 && m) sj::launch_updates(s->B, d_id, d_x, d_y, m, 0, s->stream);
       enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, m, false, part, tune);
       s->stream = user;
-      e = hipStreamEndCapture(s->cap_stream, &graph);
-      if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
+      e = hipStreamEndCapture(s->cap_stream, out);
+      return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipStreamEndCapture");
+    };
+    auto instantiate = [&](hipGraph_t graph, hipGraphExec_t *out) -> int {
+      hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
       return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipGraphInstantiate");
     };
-    rc = capture(s->prof ? 1 : 0, &g.exec);
-    if (rc != SJ_OK) return rc;
-    if (s->prof) {
-      rc = capture(2, &g.exec2);
+    g.split = false;
+    if (!s->prof) {
+      hipGraph_t graph;
+      rc = capture(0, &graph);
+      if (rc != SJ_OK) return rc;
+      rc = instantiate(graph, &g.exec);
+      (void)hipGraphDestroy(graph);
+      if (rc != SJ_OK) return rc;
+    } else {
+      // one launch: the tick up to the join write pass, an event, the join
+      // write pass, an event; two launches with the events between them if
+      // the runtime does not take event nodes
+      hipGraph_t g1, g2, top = nullptr;
+      rc = capture(1, &g1);
+      if (rc != SJ_OK) return rc;
+      rc = capture(2, &g2);
       if (rc != SJ_OK) {
-        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g1);
         return rc;
       }
+      hipGraphNode_t n1, e1, n2, e2;
+      bool ok = hipGraphCreate(&top, 0) == hipSuccess;
+      ok = ok && hipGraphAddChildGraphNode(&n1, top, nullptr, 0, g1) == hipSuccess;
+      ok = ok && hipGraphAddEventRecordNode(&e1, top, &n1, 1, s->ev[7]) == hipSuccess;
+      ok = ok && hipGraphAddChildGraphNode(&n2, top, &e1, 1, g2) == hipSuccess;
+      ok = ok && hipGraphAddEventRecordNode(&e2, top, &n2, 1, s->ev[8]) == hipSuccess;
+      ok = ok && hipGraphInstantiate(&g.exec, top, nullptr, nullptr, 0) == hipSuccess;
+      if (top) (void)hipGraphDestroy(top);
+      (void)hipGetLastError();  // a refused node is not an error of the tick
+      if (!ok) {
+        g.split = true;
+        rc = instantiate(g1, &g.exec);
+        if (rc == SJ_OK) {
+          rc = instantiate(g2, &g.exec2);
+          if (rc != SJ_OK) (void)hipGraphExecDestroy(g.exec);
+        }
+      }
+      (void)hipGraphDestroy(g1);
+      (void)hipGraphDestroy(g2);
+      if (rc != SJ_OK) return rc;
     }
     g.valid = true;
     g.m = m;
@@ -565,7 +598,7 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
   }
   hipError_t e = hipGraphLaunch(g.exec, s->stream);
-  if (e == hipSuccess && s->prof) {
+  if (e == hipSuccess && g.split) {
     e = hipEventRecord(s->ev[7], s->stream);
     if (e == hipSuccess) e = hipGraphLaunch(g.exec2, s->stream);
     if (e == hipSuccess) e = hipEventRecord(s->ev[8], s->stream);
@@ -629,6 +662,12 @@ int sj_fetch_results(sj_scene *s, sj_results *out) {
   out->d_cov_leaf = s->B.cov_leaf;
   out->d_leaf_beg = s->B.leaf_beg;
   out->d_sorted_id = s->B.valA;
+  out->n_present = c.n_present;
+  out->n_tasks = c.n_tasks;
+  out->n_subqueries = c.n_isect;
+  out->cov_pairs = ok ? c.cov_pairs : 0;
+  out->tests = c.tests;
+  out->error_bits = c.err;
   return status_of(s, c.err);
 }
 
@@ -734,7 +773,7 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[SJ_COST
   for (GraphSlot &g : s->graphs) {  // captured with the previous model state
     if (!g.valid) continue;
     (void)hipGraphExecDestroy(g.exec);
-    if (s->prof) (void)hipGraphExecDestroy(g.exec2);
+    if (g.split) (void)hipGraphExecDestroy(g.exec2);
     g.valid = false;
   }
   return SJ_OK;
