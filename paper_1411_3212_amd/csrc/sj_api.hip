@@ -39,6 +39,7 @@ struct sj_scene {
   bool ticked;
   bool prof;
   bool known;          // host_ctl reflects the device state after the last tick
+  bool mirror;         // the last enqueued work ends with a tick's copy of ctl to pin_ctl
   bool events_valid;   // phase events were recorded for the last tick
   bool join_events;    // only the join write pass was timed (graph tick)
   GraphSlot graphs[4]; // captured ticks per decision (keep, build, device, build + tune)
@@ -255,9 +256,11 @@ int status_of(sj_scene *s, uint32_t bits) {
 }
 
 int sync_ctl(sj_scene *s) {
-  hipError_t e = hipMemcpyAsync(s->pin_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost,
-                                s->stream);
-  if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync");
+  hipError_t e = hipSuccess;
+  if (!s->mirror) {
+    e = hipMemcpyAsync(s->pin_ctl, s->B.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync");
+  }
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
   s->host_ctl = *s->pin_ctl;
@@ -326,6 +329,7 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
   };
   if (part == 2) {
     sj::launch_join_write(s->B, nq, st);
+    sj::launch_ctl_out(s->B, s->pin_ctl, st);
     return;
   }
   rec(0);
@@ -351,6 +355,7 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
   sj::launch_join_write(s->B, nq, st);
   rec(8);
   rec(9);
+  sj::launch_ctl_out(s->B, s->pin_ctl, st);
   s->events_valid = events;
   s->join_events = false;
 }
@@ -359,6 +364,7 @@ void after_tick(sj_scene *s, const uint32_t *d_qid, uint32_t nq) {
   s->upd_pending = 0;
   s->force_pending = false;
   s->known = false;
+  s->mirror = true;
   s->last_nq = nq;
   s->last_qid = d_qid;
   s->ticked = true;
@@ -468,6 +474,7 @@ int sj_apply_updates(sj_scene *s, const uint32_t *d_id, const float *d_x, const 
     (void)hipEventRecord(s->ev_u0, s->stream);
     s->upd_open = true;
   }
+  s->mirror = false;  // the control block changes after the last tick's copy
   sj::launch_updates(s->B, d_id, d_x, d_y, m, s->upd_pending, s->stream);
   s->upd_pending += m;
   if (s->prof) (void)hipEventRecord(s->ev_u1, s->stream);
@@ -479,6 +486,7 @@ int sj_build_index(sj_scene *s, uint32_t th) {
   if (!s) return SJ_EINVAL;
   const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
   if (th && th < th_min) return fail(s, SJ_EINVAL, "build_index: th below th_min");
+  s->mirror = false;
   sj::launch_request_build(s->B.ctl, th, s->stream);
   s->force_pending = true;
   hipError_t e = hipGetLastError();

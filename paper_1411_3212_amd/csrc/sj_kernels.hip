@@ -1496,6 +1496,15 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
 
 // --------------------------------------------------------------- results --
 
+// End of a tick: the control block to the host's pinned mirror (one wave,
+// a word per lane), so reading the tick's counters needs no copy command.
+__global__ void k_ctl_out(const Ctl *ctl, Ctl *host) {
+  static_assert(sizeof(Ctl) % 4 == 0, "word copy");
+  const uint32_t *src = (const uint32_t *)ctl;
+  uint32_t *dst = (uint32_t *)host;
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) dst[i] = src[i];
+}
+
 __global__ void k_counters(const Ctl *ctl, uint64_t *out) {
   const bool ok = ctl->go_join != 0;
   out[0] = ok ? ctl->n_res + ctl->cov_pairs : 0ull;
@@ -1741,6 +1750,10 @@ void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
          (const uint32_t *)B.tleaf, (const uint2 *)B.sq, (const float4 *)B.qrect,
          (const float2 *)B.sxy, (const uint32_t *)B.valA,
          (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
+}
+
+void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s) {
+  LAUNCH(k_ctl_out, 1, kWave, s, (const Ctl *)B.ctl, host);
 }
 
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s) {
