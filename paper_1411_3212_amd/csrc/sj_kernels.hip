@@ -1218,6 +1218,34 @@ __device__ __forceinline__ uint32_t count_first(float4 *wrect, uint32_t nk,
   return count_rounds<NCH>(wrect, nk, p, h, lane);
 }
 
+// A leaf of at most 32 objects: both half-waves hold its objects (lane l
+// and l + 32 the same one), and a round tests two subqueries, kk on the
+// low half and kk + 1 on the high half.
+constexpr uint64_t kLowHalf = 0xffffffffull;
+
+__device__ __forceinline__ uint32_t count_half(float4 *wrect, uint32_t nk,
+                                               const float2 *__restrict__ sxy, uint32_t ob,
+                                               uint32_t oe, const float4 *__restrict__ qrect,
+                                               uint2 e, uint32_t lane, float4 *r) {
+  const uint32_t half = lane >> 5, i = ob + (lane & 31u);
+  const uint64_t h = ballot(i < oe);
+  const float2 p = sxy[min(i, oe - 1u)];
+  if (lane < nk) {
+    *r = qrect[e.x];
+    wrect[lane] = *r;
+  }
+  wave_lds_fence();
+  uint32_t blk = 0;
+  for (uint32_t kk = 0; kk < nk; kk += 2) {
+    const float4 rk = wrect[min(kk + half, nk - 1u)];
+    uint64_t m = hits(rk, p, h);
+    if (kk + 1u >= nk) m &= kLowHalf;  // no second subquery
+    const uint32_t lo = (uint32_t)__popcll(m & kLowHalf), hi = (uint32_t)__popcll(m >> 32);
+    blk = lane == kk ? lo : (lane == kk + 1u ? hi : blk);
+  }
+  return blk;
+}
+
 // A further block of a long leaf.
 template <uint32_t NCH>
 __device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk,
@@ -1272,7 +1300,8 @@ __global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uin
     wave_lds_fence();
     if (ob < oe) {
       const uint32_t nch = chunk_count(ob, oe);
-      cnt = nch <= 1u   ? count_first<1>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
+      cnt = oe - ob <= 32u ? count_half(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
+            : nch <= 1u ? count_first<1>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
             : nch <= 2u ? count_first<2>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
             : nch <= 4u ? count_first<4>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
                         : count_first<8>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r);
@@ -1391,6 +1420,35 @@ __device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint3
   write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
 }
 
+// Decoding side of count_half: a round writes the hits of subquery kk
+// (low half) and kk + 1 (high half), each lane ranked within its half.
+__device__ __forceinline__ void write_half(float4 *wrect, uint64_t *woff, uint32_t nk,
+                                           const float2 *__restrict__ sxy,
+                                           const uint32_t *__restrict__ sid, uint32_t ob,
+                                           uint32_t oe, const float4 *__restrict__ qrect,
+                                           const uint64_t *__restrict__ res_off, uint2 e,
+                                           uint32_t lane, uint32_t *__restrict__ res_ids) {
+  const uint32_t half = lane >> 5, i = min(ob + (lane & 31u), oe - 1u);
+  const uint64_t h = ballot(ob + (lane & 31u) < oe);
+  const float2 p = sxy[i];
+  const uint32_t id = sid[i];
+  if (lane < nk) {
+    const float4 r = qrect[e.x];
+    woff[lane] = res_off[e.y];
+    wrect[lane] = r;
+  }
+  wave_lds_fence();
+  const uint64_t mine = half ? ~kLowHalf : kLowHalf;
+  for (uint32_t kk = 0; kk < nk; kk += 2) {
+    const uint32_t k = min(kk + half, nk - 1u);
+    const float4 rk = wrect[k];
+    const uint64_t base = woff[k];
+    uint64_t m = hits(rk, p, h);
+    if (kk + 1u >= nk) m &= kLowHalf;
+    if (__builtin_amdgcn_inverse_ballot_w64(m)) res_ids[base + mbcnt(m & mine)] = id;
+  }
+}
+
 template <uint32_t NCH>
 __device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff, uint32_t nk,
                                             const float2 *__restrict__ sxy,
@@ -1458,7 +1516,9 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
       const uint32_t nch = chunk_count(ob, oe);
       const bool more = ob + (uint32_t)kWave * kJoinRegChunks < oe;
       wave_lds_fence();
-      if (nch <= 1u)
+      if (oe - ob <= 32u)
+        write_half(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids);
+      else if (nch <= 1u)
         write_first<1>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
       else if (nch <= 2u)
         write_first<2>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
