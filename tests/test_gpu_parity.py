@@ -277,6 +277,27 @@ def test_objects_leaving_the_frame_of_a_reused_index():
         assert sc.stats()["rebuilt"] == (1 if k == 0 else 0)
 
 
+def test_kept_quadtree_of_one_level():
+    # at most th objects: the four level-1 quadrants are the leaves (the
+    # root is always split) and the start table has four cells; ticks that
+    # keep the quadtree map objects to those leaves
+    n = 40
+    rng = np.random.default_rng(7)
+    sc = Scene(n, n, th=64, rebuild="never")
+    st = oracle.State(n)
+    for k in range(3):
+        x = rng.uniform(0.2, 0.6, n).astype(F32)
+        y = rng.uniform(0.2, 0.6, n).astype(F32)
+        h = F32(0.05)
+        rects = (x - h, y - h, x + h, y + h)
+        t = T(ids=range(n), x=x, y=y, qid=range(n), rects=rects)
+        oracle_apply(st, t)
+        gpu_tick(sc, t)
+        assert sc.fetch().to_lists() == oracle_lists(st, t), f"tick {k}"
+        s = sc.stats()
+        assert s["n_leaves"] == 4 and s["rebuilt"] == (1 if k == 0 else 0)
+
+
 def test_partial_updates_keep_last_known_positions():
     n = 3000
     wl = workloads.make("hotspot", n=n, n_ticks=3)
