@@ -507,6 +507,46 @@ int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const flo
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "run_tick launch");
 }
 
+// Event record nodes e0 -> (join write kernel node) -> e1 in a captured
+// tick: the kernel node's incoming edges move to e0, its outgoing edges to
+// e1.  False (graph possibly edited) if the node or an edit is refused.
+static bool time_join_node(hipGraph_t graph, hipEvent_t e0, hipEvent_t e1) {
+  size_t n = 0;
+  if (hipGraphGetNodes(graph, nullptr, &n) != hipSuccess || n == 0) return false;
+  hipGraphNode_t *nodes = new (std::nothrow) hipGraphNode_t[n];
+  if (!nodes) return false;
+  hipGraphNode_t kw = nullptr;
+  if (hipGraphGetNodes(graph, nodes, &n) == hipSuccess) {
+    for (size_t i = 0; i < n && !kw; ++i) {
+      hipGraphNodeType t;
+      hipKernelNodeParams kp;
+      if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+      if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess) continue;
+      if (kp.func == sj::join_write_kernel()) kw = nodes[i];
+    }
+  }
+  delete[] nodes;
+  if (!kw) return false;
+  size_t np = 0, ns = 0;
+  if (hipGraphNodeGetDependencies(kw, nullptr, &np) != hipSuccess ||
+      hipGraphNodeGetDependentNodes(kw, nullptr, &ns) != hipSuccess || np > 8 || ns > 8)
+    return false;
+  hipGraphNode_t pre[8], suc[8], a, b;
+  if ((np && hipGraphNodeGetDependencies(kw, pre, &np) != hipSuccess) ||
+      (ns && hipGraphNodeGetDependentNodes(kw, suc, &ns) != hipSuccess))
+    return false;
+  for (size_t i = 0; i < np; ++i)
+    if (hipGraphRemoveDependencies(graph, &pre[i], &kw, 1) != hipSuccess) return false;
+  for (size_t i = 0; i < ns; ++i)
+    if (hipGraphRemoveDependencies(graph, &kw, &suc[i], 1) != hipSuccess) return false;
+  if (hipGraphAddEventRecordNode(&a, graph, np ? pre : nullptr, np, e0) != hipSuccess) return false;
+  if (hipGraphAddDependencies(graph, &a, &kw, 1) != hipSuccess) return false;
+  if (hipGraphAddEventRecordNode(&b, graph, &kw, 1, e1) != hipSuccess) return false;
+  for (size_t i = 0; i < ns; ++i)
+    if (hipGraphAddDependencies(graph, &b, &suc[i], 1) != hipSuccess) return false;
+  return true;
+}
+
 int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const float *d_y,
                   uint32_t m, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
                   const float *d_xb, const float *d_yb, uint32_t nq) {
@@ -567,9 +607,20 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
       (void)hipGraphDestroy(graph);
       if (rc != SJ_OK) return rc;
     } else {
-      // one launch: the tick up to the join write pass, an event, the join
-      // write pass, an event; two launches with the events between them if
-      // the runtime does not take event nodes
+      // one launch: the captured tick with event nodes inserted right
+      // around its join write node; else the tick up to the join write pass
+      // and the pass as child graphs with event nodes between them; else two
+      // launches with the events recorded between them
+      {
+        hipGraph_t graph;
+        rc = capture(0, &graph);
+        if (rc != SJ_OK) return rc;
+        const bool ok = time_join_node(graph, s->ev[7], s->ev[8]) &&
+                        hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();  // a refused edit is not an error of the tick
+        if (ok) goto captured;
+      }
       hipGraph_t g1, g2, top = nullptr;
       rc = capture(1, &g1);
       if (rc != SJ_OK) return rc;
@@ -599,6 +650,7 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
       (void)hipGraphDestroy(g2);
       if (rc != SJ_OK) return rc;
     }
+  captured:
     g.valid = true;
     g.m = m;
     g.nq = nq;

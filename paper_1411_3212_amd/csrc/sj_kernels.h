@@ -86,6 +86,8 @@ void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s);
 void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
                  const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,
                  uint32_t covering, hipStream_t s);
+// Host handle of the join write kernel (to find its node in a captured graph).
+const void *join_write_kernel();
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s);
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s);
 void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt, uint64_t *hash,

@@ -1812,6 +1812,8 @@ void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
          (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
 }
 
+const void *join_write_kernel() { return reinterpret_cast<const void *>(&k_join_write); }
+
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s) {
   LAUNCH(k_ctl_out, 1, kWave, s, (const Ctl *)B.ctl, host);
 }
