@@ -524,37 +524,60 @@ __global__ void __launch_bounds__(kBlock) k_nodes_open(const Ctl *ctl, const uin
     nopen[t] = llevel[t] - open_level(lstart[t]);
 }
 
+// One thread per internal node: its leaf t (the last leaf whose first node
+// index is <= the node's) and level, then the four children's leaves by four
+// interleaved branchless binary searches over the leaf starts, so the
+// longest dependent chain is two searches whatever the depth.
 __global__ void __launch_bounds__(kBlock) k_nodes_build(Ctl *ctl, const uint32_t *lstart,
                                                         const uint32_t *llevel,
                                                         const uint32_t *node_off, uint4 *nodes,
                                                         uint32_t ncap) {
   if (!ctl->rebuild) return;
   const uint32_t n = ctl->n_leaves;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
-    const uint32_t s = lstart[t], l = llevel[t], k0 = open_level(s);
-    for (uint32_t k = k0; k < l; ++k) {
-      const uint32_t idx = node_off[t] + (k - k0);
-      const uint32_t p = k == 0 ? 0u : s >> (2u * (kFine - k));
-      uint32_t ref[4];
-      bool bad = false;
-      for (uint32_t c = 0; c < 4; ++c) {
-        const uint32_t cs = (p * 4u + c) << (2u * (kFine - k - 1));
-        const uint32_t u = lower_bound_u32(lstart, 0u, n, cs);
-        if (u >= n || lstart[u] != cs) {
-          bad = true;
-          ref[c] = kLeafBit;
-          continue;
-        }
-        const uint32_t lu = llevel[u];
-        ref[c] = lu == k + 1 ? (kLeafBit | u) : node_off[u] + (k + 1 - open_level(cs));
-      }
-      if (bad) atomicOr(&ctl->err, kErrOvfTree);
-      if (idx < ncap)
-        nodes[idx] = make_uint4(ref[0], ref[1], ref[2], ref[3]);
-      else
-        atomicOr(&ctl->err, kErrOvfTree);
+  if (n == 0) return;
+  const uint32_t total = node_off[n];
+  bool bad = false;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    // t: last index with node_off[t] <= i (node_off[0] = 0 <= i)
+    uint32_t base = 0, len = n;
+    while (len > 1) {
+      const uint32_t half = len >> 1;
+      base = node_off[base + half] <= i ? base + half : base;
+      len -= half;
     }
+    const uint32_t t = base, s = lstart[t], k0 = open_level(s);
+    const uint32_t k = k0 + (i - node_off[t]);
+    const uint32_t p = k == 0 ? 0u : s >> (2u * (kFine - k));
+    uint32_t key[4], b4[4];
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+      key[c] = (p * 4u + c) << (2u * (kFine - k - 1));
+      b4[c] = 0;
+    }
+    for (uint32_t l2 = n; l2 > 1;) {
+      const uint32_t half = l2 >> 1;
+#pragma unroll
+      for (uint32_t c = 0; c < 4; ++c) b4[c] = lstart[b4[c] + half] < key[c] ? b4[c] + half : b4[c];
+      l2 -= half;
+    }
+    uint32_t ref[4];
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+      const uint32_t u = b4[c] + (lstart[b4[c]] < key[c] ? 1u : 0u);  // first start >= key
+      if (u >= n || lstart[u] != key[c]) {
+        bad = true;
+        ref[c] = kLeafBit;
+        continue;
+      }
+      const uint32_t lu = llevel[u];
+      ref[c] = lu == k + 1 ? (kLeafBit | u) : node_off[u] + (k + 1 - open_level(key[c]));
+    }
+    if (i < ncap)
+      nodes[i] = make_uint4(ref[0], ref[1], ref[2], ref[3]);
+    else
+      bad = true;
   }
+  flag_error(ctl, kErrOvfTree, bad);
 }
 
 // Start table at level T = min(l_deep, cap) in Morton order (the paper's
