@@ -177,10 +177,31 @@ def _ptr(t):
 
 
 class Results:
-    """Compressed results of a tick as torch views into the workspace."""
+    """Compressed results of a tick as torch views into the workspace (made
+    on first access, so a fetch for the counters builds no tensor)."""
+
+    _VIEWS = {  # attribute: (pointer field, length, dtype name)
+        "isect_off": ("d_isect_off", lambda r: r.nq + 1, "int64"),
+        "isect_id": ("d_isect_id", lambda r: r.n_isect_ids, "int32"),
+        "cov_off": ("d_cov_off", lambda r: r.nq + 1, "int32"),
+        "cov_leaf": ("d_cov_leaf", lambda r: r.n_cov_entries, "int32"),
+        "leaf_beg": ("d_leaf_beg", lambda r: r.n_leaves + 1, "int32"),
+        "sorted_id": ("d_sorted_id", lambda r: r.n_present if r.n_leaves else 0, "int32"),
+    }
+
+    def __getattr__(self, name):
+        spec = Results._VIEWS.get(name)
+        if spec is None:
+            raise AttributeError(name)
+        import torch
+        field, length, dtype = spec
+        t = self._scene._view(self._ptrs[field], length(self), getattr(torch, dtype))
+        setattr(self, name, t)
+        return t
 
     def __init__(self, scene: "Scene", r: SjResults):
-        import torch
+        self._scene = scene
+        self._ptrs = {f: getattr(r, f) for f, _, _ in Results._VIEWS.values()}
         self.nq = int(r.nq)
         self.n_leaves = int(r.n_leaves)
         self.n_isect_ids = int(r.n_isect_ids)
@@ -192,13 +213,6 @@ class Results:
         self.cov_pairs = int(r.cov_pairs)
         self.tests = int(r.tests)
         self.error_bits = int(r.error_bits)
-        v = scene._view
-        self.isect_off = v(r.d_isect_off, self.nq + 1, torch.int64)
-        self.isect_id = v(r.d_isect_id, self.n_isect_ids, torch.int32)
-        self.cov_off = v(r.d_cov_off, self.nq + 1, torch.int32)
-        self.cov_leaf = v(r.d_cov_leaf, self.n_cov_entries, torch.int32)
-        self.leaf_beg = v(r.d_leaf_beg, self.n_leaves + 1, torch.int32)
-        self.sorted_id = v(r.d_sorted_id, self.n_present if self.n_leaves else 0, torch.int32)
 
     def counters(self):
         """The tick's counters in the order of Scene.counters_into."""
@@ -275,7 +289,7 @@ class Scene:
 
     def _view(self, ptr, count, dtype):
         import torch
-        item = torch.empty((), dtype=dtype).element_size()
+        item = dtype.itemsize
         if count == 0 or not ptr:
             return torch.empty(0, dtype=dtype, device=self.device)
         off = int(ptr) - self.ws.data_ptr()
