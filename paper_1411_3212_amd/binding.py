@@ -271,6 +271,7 @@ class Scene:
         _check(rc, None)
         self.handle = h
         self._keep = []
+        self._graph_key = None  # inputs of the last tick_graph call, checked and kept
 
     @property
     def workspace_bytes(self) -> int:
@@ -311,6 +312,7 @@ class Scene:
         self._dev(y, torch.float32, m)
         _check(self._lib.sj_apply_updates(self.handle, _ptr(ids), _ptr(x), _ptr(y), m), self.handle)
         self._keep = [ids, x, y]
+        self._graph_key = None
 
     def build_index(self, th: int = 0):
         _check(self._lib.sj_build_index(self.handle, th), self.handle)
@@ -324,19 +326,25 @@ class Scene:
         _check(self._lib.sj_run_tick(self.handle, _ptr(qid), _ptr(xa), _ptr(ya), _ptr(xb),
                                      _ptr(yb), nq), self.handle)
         self._keep = [qid, xa, ya, xb, yb]
+        self._graph_key = None
 
     def tick_graph(self, ids, x, y, qid, xa, ya, xb, yb):
         """Updates + tick as one graph launch (captured once per quadtree
         decision for these buffers, replayed afterwards)."""
-        import torch
-        m, nq = ids.numel(), qid.numel()
-        for t in (ids, qid):
-            assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
-        for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
-            self._dev(t, torch.float32, n)
-        _check(self._lib.sj_tick_graph(self.handle, _ptr(ids), _ptr(x), _ptr(y), m, _ptr(qid),
-                                       _ptr(xa), _ptr(ya), _ptr(xb), _ptr(yb), nq), self.handle)
-        self._keep = [ids, x, y, qid, xa, ya, xb, yb]
+        args = (ids, x, y, qid, xa, ya, xb, yb)
+        key = tuple((id(t), t.data_ptr(), t.numel()) for t in args)
+        if key != self._graph_key:  # the same tensors as the last call were checked then
+            import torch
+            m, nq = ids.numel(), qid.numel()
+            for t in (ids, qid):
+                assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
+            for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
+                self._dev(t, torch.float32, n)
+            p = [_ptr(t) for t in args]
+            self._graph_args = (p[0], p[1], p[2], m, p[3], p[4], p[5], p[6], p[7], nq)
+            self._graph_key = key
+            self._keep = list(args)
+        _check(self._lib.sj_tick_graph(self.handle, *self._graph_args), self.handle)
 
     def fetch(self) -> Results:
         r = SjResults()
