@@ -228,9 +228,10 @@ int sj_run_tick(sj_scene *scene, const uint32_t *d_qid, const float *d_xa,
  * sj_apply_updates(d_id, d_x, d_y, m) followed by sj_run_tick(...), on the
  * scene's stream.  The graph is captured on first use for each quadtree
  * decision (keep, build, decided on the device) and replayed afterwards;
- * it is captured again whenever a pointer or a size differs from the
- * captured ones, so callers that keep their inputs in fixed buffers replay
- * without capture.  The graph holds kernels only.  If updates were already
+ * it is captured again when m or nq differs from the captured sizes.  The
+ * graph reads the input arrays through a small block in the workspace that
+ * one kernel launched before it writes, so any buffers replay the same
+ * graph without copies.  The graph holds kernels only.  If updates were already
  * enqueued for this tick by sj_apply_updates, the tick runs eagerly. */
 int sj_tick_graph(sj_scene *scene, const uint32_t *d_id, const float *d_x, const float *d_y,
                   uint32_t m, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
@@ -355,15 +356,15 @@ int sj_index_view_get(sj_scene *scene, sj_index_view *out);
  * batching of ticks and the latency definitions of Section "Problem
  * setting and statement": latency = queueing + processing).
  *
- * The server carves every admitted scene's workspace, input slots and
- * output slots from one caller-owned device pool with its own first-fit
+ * The server carves every admitted scene's workspace and output slots
+ * from one caller-owned device pool with its own first-fit
  * allocator: admission succeeds while the scene fits (an HBM budget), and
  * retiring a scene returns its memory.  Every scene has its own stream.
  * Tick requests queue per scene in submission order; sj_server_poll
  * retires finished ticks and starts queued ones, up to max_running at
- * once, so ticks of different scenes overlap on the device.  A tick copies
- * its inputs into the scene's slots, replays the scene's captured graph
- * (sj_tick_graph), then writes per-query counts and pair-set hashes
+ * once, so ticks of different scenes overlap on the device.  A tick replays
+ * the scene's captured graph (sj_tick_graph) on the request's own input
+ * arrays, then writes per-query counts and pair-set hashes
  * (sj_result_hashes) and the tick counters (sj_tick_counters) into the
  * scene's output slots.  Not thread-safe.
  * ------------------------------------------------------------------------ */
@@ -385,7 +386,7 @@ typedef struct sj_server_stats {
   uint32_t scenes, running, queued;
 } sj_server_stats;
 
-/* Device bytes a scene takes from the pool (workspace + slots). */
+/* Device bytes a scene takes from the pool (workspace + output slots). */
 size_t sj_server_scene_bytes(const sj_config *cfg, uint32_t max_updates);
 
 /* d_pool: caller-owned device memory, 256-byte aligned, pool_bytes long.

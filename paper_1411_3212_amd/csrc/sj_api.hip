@@ -23,7 +23,6 @@ struct GraphSlot {
   bool valid;
   bool split;            // exec2 is launched after exec, between the timing events
   uint32_t m, nq, key_bits;
-  const void *ptrs[8];
 };
 
 struct sj_scene {
@@ -159,6 +158,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   Bufs b{};
   const uint64_t N = d.N, Q = d.Q, L = d.LCAP;
   b.ctl = c.take<Ctl>(1);
+  b.tin = c.take<sj::TickIn>(1);
   b.pos = c.take<float2>(N);
   b.ustamp = c.take<uint64_t>(N);
   b.qstamp = c.take<uint64_t>(N);
@@ -318,9 +318,9 @@ void count_build(sj_scene *s, uint32_t decision, bool tune) {
 }
 
 // part: 0 the whole tick; 1 up to the result-offset scan; 2 the join write.
-void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const float *d_ya,
-                  const float *d_xb, const float *d_yb, uint32_t nq, uint32_t decision,
-                  uint64_t upd_total, bool events, int part = 0, bool tune = false) {
+// The tick's query arrays are those last written to the scene's input block.
+void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_total, bool events,
+                  int part = 0, bool tune = false) {
   const hipStream_t st = s->stream;
   const uint32_t flags = s->cfg.flags;
   const uint32_t policy = s->cfg.rebuild_policy;
@@ -333,16 +333,15 @@ void enqueue_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const f
     return;
   }
   rec(0);
-  sj::launch_index(s->B, decision, policy, upd_total, d_qid, nq, key_bits(s, decision), st);
+  sj::launch_index(s->B, decision, policy, upd_total, nq, key_bits(s, decision), st);
   rec(1);
   if (tune)
-    sj::launch_tune(s->B, s->n_cand, s->l_max, d_qid, d_xa, d_ya, d_xb, d_yb, nq,
-                    (flags & SJ_COVERING) ? 1u : 0u, st);
+    sj::launch_tune(s->B, s->n_cand, s->l_max, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
   rec(2);
   sj::launch_leaves(s->B, st);
   rec(3);
-  sj::launch_split(s->B, d_qid, d_xa, d_ya, d_xb, d_yb, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  sj::launch_split(s->B, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   rec(4);
   const bool learned = (flags & SJ_SCHEDULE_MLP) && s->cm_set;
   sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, learned, st);
@@ -434,6 +433,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
   sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
   sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
   sj::launch_fill_u32((uint32_t *)s->B.tune, sizeof(sj::TuneState) / 4, 0u, stream);
+  sj::launch_fill_u32((uint32_t *)s->B.tin, sizeof(sj::TickIn) / 4, 0u, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     snprintf(g_create_err, sizeof g_create_err, "kernel launch: %s", hipGetErrorString(e));
@@ -475,7 +475,12 @@ int sj_apply_updates(sj_scene *s, const uint32_t *d_id, const float *d_x, const 
     s->upd_open = true;
   }
   s->mirror = false;  // the control block changes after the last tick's copy
-  sj::launch_updates(s->B, d_id, d_x, d_y, m, s->upd_pending, s->stream);
+  sj::TickIn in{};
+  in.id = d_id;
+  in.x = d_x;
+  in.y = d_y;
+  sj::launch_tick_in(s->B, in, 1u, s->stream);
+  sj::launch_updates(s->B, m, s->upd_pending, s->stream);
   s->upd_pending += m;
   if (s->prof) (void)hipEventRecord(s->ev_u1, s->stream);
   hipError_t e = hipGetLastError();
@@ -500,7 +505,14 @@ int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const flo
   if (rc != SJ_OK) return rc;
   const uint32_t decision = host_decision(s);
   const bool tune = want_tune(s, decision);
-  enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, s->upd_pending, s->prof, 0, tune);
+  sj::TickIn in{};
+  in.qid = d_qid;
+  in.xa = d_xa;
+  in.ya = d_ya;
+  in.xb = d_xb;
+  in.yb = d_yb;
+  sj::launch_tick_in(s->B, in, 2u, s->stream);
+  enqueue_tick(s, nq, decision, s->upd_pending, s->prof, 0, tune);
   count_build(s, decision, tune);
   after_tick(s, d_qid, nq);
   hipError_t e = hipGetLastError();
@@ -565,11 +577,8 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
   const uint32_t decision = host_decision(s);
   const bool tune = want_tune(s, decision);
   GraphSlot &g = s->graphs[tune ? 3u : decision];
-  const void *ptrs[8] = {d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
   const uint32_t kb = key_bits(s, decision);
-  bool same = g.valid && g.m == m && g.nq == nq && g.key_bits == kb;
-  for (int i = 0; same && i < 8; ++i) same = g.ptrs[i] == ptrs[i];
-  if (!same) {
+  if (!(g.valid && g.m == m && g.nq == nq && g.key_bits == kb)) {
     if (g.valid) {
       (void)hipGraphExecDestroy(g.exec);
       if (g.split) (void)hipGraphExecDestroy(g.exec2);
@@ -588,8 +597,8 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
       hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(s, e, "hipStreamBeginCapture");
       s->stream = s->cap_stream;
-      if (part != 2 && m) sj::launch_updates(s->B, d_id, d_x, d_y, m, 0, s->stream);
-      enqueue_tick(s, d_qid, d_xa, d_ya, d_xb, d_yb, nq, decision, m, false, part, tune);
+      if (part != 2 && m) sj::launch_updates(s->B, m, 0, s->stream);
+      enqueue_tick(s, nq, decision, m, false, part, tune);
       s->stream = user;
       e = hipStreamEndCapture(s->cap_stream, out);
       return e == hipSuccess ? SJ_OK : hip_fail(s, e, "hipStreamEndCapture");
@@ -655,9 +664,12 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     g.m = m;
     g.nq = nq;
     g.key_bits = kb;
-    for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
   }
-  hipError_t e = hipGraphLaunch(g.exec, s->stream);
+  // the graph reads this tick's arrays from the scene's input block
+  const sj::TickIn in{d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
+  sj::launch_tick_in(s->B, in, 3u, s->stream);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipGraphLaunch(g.exec, s->stream);
   if (e == hipSuccess && g.split) {
     e = hipEventRecord(s->ev[7], s->stream);
     if (e == hipSuccess) e = hipGraphLaunch(g.exec2, s->stream);

@@ -64,6 +64,16 @@ struct Ctl {
   uint64_t upd_seq, qry_seq;
 };
 
+// Input arrays of a tick.  Kernels read them from this block in device
+// memory, written on the stream just before the tick, so that a captured
+// tick does not depend on where its caller keeps its inputs.
+struct TickIn {
+  const uint32_t *id;  // updates: object ids, positions
+  const float *x, *y;
+  const uint32_t *qid;  // queries: issuing object, rectangle corners
+  const float *xa, *ya, *xb, *yb;
+};
+
 // Slots of the per-block partial reductions (red[slot * kChunkBlocks + b]).
 enum : int {
   kRedMinX = 0, kRedMinY, kRedMaxX, kRedMaxY, kRedOutside,

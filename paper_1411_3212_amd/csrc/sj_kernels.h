@@ -16,6 +16,7 @@ constexpr unsigned kJoinBlocks = 4096;  // 16384 waves for the join passes
 // Typed views of the caller's workspace (carved by sj_api.hip).
 struct Bufs {
   Ctl *ctl;
+  TickIn *tin;                          // input arrays of the current tick
   // objects (by id) and per-tick sorted arrays
   float2 *pos;                          // position by id (NaN x: no position)
   uint64_t *ustamp, *qstamp;
@@ -62,17 +63,17 @@ void launch_ctl_init(Ctl *ctl, uint32_t th, hipStream_t s);
 void launch_request_build(Ctl *ctl, uint32_t th, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
-void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const float *y, uint32_t m,
-                    uint64_t seq_off, hipStream_t s);
+// Writes the input arrays of a (parts 1: updates, 2: queries) into B.tin,
+// where the kernels of the following launches read them.
+void launch_tick_in(const Bufs &B, const TickIn &a, uint32_t parts, hipStream_t s);
+void launch_updates(const Bufs &B, uint32_t m, uint64_t seq_off, hipStream_t s);
 // key_bits: with decision 0, the width of the leaf keys if the host knows
 // it (then exactly the passes it needs run), else 0.
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
-                  const uint32_t *qid, uint32_t nq, uint32_t key_bits, hipStream_t s);
+                  uint32_t nq, uint32_t key_bits, hipStream_t s);
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s);
 void launch_leaves(const Bufs &B, hipStream_t s);
-void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
-                  const float *xb, const float *yb, uint32_t nq, uint32_t covering,
-                  hipStream_t s);
+void launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipStream_t s);
 void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
                      hipStream_t s);
 // Task keys from the cost model's predicted task times (learned schedule).
@@ -83,9 +84,8 @@ void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t
 void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s);
 // Trial builds and splits at every candidate threshold, cost prediction,
 // and the choice of the threshold that the tick's build then uses.
-void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
-                 const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,
-                 uint32_t covering, hipStream_t s);
+void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, uint32_t covering,
+                 hipStream_t s);
 // Host handle of the join write kernel (to find its node in a captured graph).
 const void *join_write_kernel();
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s);

@@ -93,10 +93,11 @@ __global__ void k_request_build(Ctl *ctl, uint32_t th) {
 // the tick's total when the tick runs); an atomic max per object keeps the
 // latest, then only that one is written.
 
-__global__ void __launch_bounds__(kBlock) k_upd_stamp(const uint32_t *id, const float *x,
-                                                      const float *y, uint32_t m, uint32_t N,
+__global__ void __launch_bounds__(kBlock) k_upd_stamp(const TickIn *tin, uint32_t m, uint32_t N,
                                                       uint64_t seq_off, uint64_t *stamp,
                                                       Ctl *ctl) {
+  const uint32_t *__restrict__ id = tin->id;
+  const float *__restrict__ x = tin->x, *__restrict__ y = tin->y;
   const uint64_t seq = ctl->upd_seq + seq_off;
   const uint32_t mr = (m + kWave - 1) / kWave * kWave;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < mr; k += gridDim.x * kBlock) {
@@ -115,10 +116,11 @@ __global__ void __launch_bounds__(kBlock) k_upd_stamp(const uint32_t *id, const 
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_upd_write(const uint32_t *id, const float *x,
-                                                      const float *y, uint32_t m, uint32_t N,
+__global__ void __launch_bounds__(kBlock) k_upd_write(const TickIn *tin, uint32_t m, uint32_t N,
                                                       uint64_t seq_off, const uint64_t *stamp,
                                                       const Ctl *ctl, float2 *pos) {
+  const uint32_t *__restrict__ id = tin->id;
+  const float *__restrict__ x = tin->x, *__restrict__ y = tin->y;
   const uint64_t seq = ctl->upd_seq + seq_off;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < m; k += gridDim.x * kBlock) {
     const uint32_t o = id[k];
@@ -305,7 +307,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
 // is the one answered).
 __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N, Tree tr,
                                                    Ctl *ctl, const uint32_t *blk, uint32_t *keys,
-                                                   uint32_t *vals, const uint32_t *qid,
+                                                   uint32_t *vals, const TickIn *tin,
                                                    uint32_t nq, uint64_t *qstamp) {
   __shared__ uint32_t lds[kWavesPerBlock + 1];
   const uint32_t chunk = (N + gridDim.x - 1) / gridDim.x;
@@ -330,6 +332,7 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
     base += tot;
   }
   const uint64_t seq = ctl->qry_seq;
+  const uint32_t *__restrict__ qid = tin->qid;
   const uint32_t nr = (nq + kWave - 1) / kWave * kWave;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nr; k += gridDim.x * kBlock) {
     bool bad = false;
@@ -809,10 +812,10 @@ __device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *sta
 // written, so the results do not depend on the order.
 constexpr uint32_t kQueryOrderMin = 1u << 20;
 
-__global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const float *xa,
-                                                        const float *ya, uint32_t nq,
+__global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const TickIn *tin, uint32_t nq,
                                                         uint32_t *qkey, uint32_t *qord) {
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->n_qord = nq;
+  const float *__restrict__ xa = tin->xa, *__restrict__ ya = tin->ya;
   const float x0 = ctl->x0, y0 = ctl->y0, sc = ctl->scale;
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
     qkey[k] = morton2(cell_of(xa[k], x0, sc) >> 8, cell_of(ya[k], y0, sc) >> 8);
@@ -826,12 +829,14 @@ __global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const float *x
 // covering flag) and the positions of its intersecting entries in their
 // leaves' groups are kept for the write pass.
 __global__ void __launch_bounds__(kBlock) k_q_count(
-    Ctl *ctl, const uint32_t *qid, const float *xa, const float *ya, const float *xb,
-    const float *yb, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
+    Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *leaf_nsq,
     uint32_t *leaf_ovf, uint32_t *qlist, uint32_t *qpos, uint32_t slots, uint32_t covering,
     const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
+  const uint32_t *__restrict__ qid = tin->qid;
+  const float *__restrict__ xa = tin->xa, *__restrict__ ya = tin->ya, *__restrict__ xb = tin->xb,
+                            *__restrict__ yb = tin->yb;
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
   tr.tlev = ctl->tlev;
@@ -901,7 +906,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
 // order inside a leaf's group does not matter: a subquery's results go to
 // the offset of its query-order slot.
 __global__ void __launch_bounds__(kBlock) k_q_write(
-    Ctl *ctl, const uint32_t *qid, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
+    Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
     const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, const uint32_t *qpos,
     uint32_t slots, const uint32_t *leaf_sqoff, const uint32_t *leaf_nsq, uint32_t *leaf_ovfc,
@@ -910,6 +915,7 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
   __shared__ uint64_t lds[kWavesPerBlock];
   uint64_t covp = 0;
   if (ctl->go_split) {
+    const uint32_t *__restrict__ qid = tin->qid;
     const uint64_t seq = ctl->qry_seq;
     tr.tlev = ctl->tlev;
     const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
@@ -1699,12 +1705,32 @@ void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   LAUNCH(k_fill_u64, grid_for(n), kBlock, s, p, n, v);
 }
 
-void launch_updates(const Bufs &B, const uint32_t *id, const float *x, const float *y, uint32_t m,
-                    uint64_t seq_off, hipStream_t s) {
+// Writes the selected parts of a (1: updates, 2: queries) into tin.
+__global__ void k_tick_in(TickIn a, uint32_t parts, TickIn *tin) {
+  if (threadIdx.x != 0) return;
+  if (parts & 1u) {
+    tin->id = a.id;
+    tin->x = a.x;
+    tin->y = a.y;
+  }
+  if (parts & 2u) {
+    tin->qid = a.qid;
+    tin->xa = a.xa;
+    tin->ya = a.ya;
+    tin->xb = a.xb;
+    tin->yb = a.yb;
+  }
+}
+
+void launch_tick_in(const Bufs &B, const TickIn &a, uint32_t parts, hipStream_t s) {
+  LAUNCH(k_tick_in, 1, kWave, s, a, parts, B.tin);
+}
+
+void launch_updates(const Bufs &B, uint32_t m, uint64_t seq_off, hipStream_t s) {
   const unsigned g = grid_for(m);
-  LAUNCH(k_upd_stamp, g, kBlock, s, id, x, y, m, B.N, seq_off, B.ustamp, B.ctl);
-  LAUNCH(k_upd_write, g, kBlock, s, id, x, y, m, B.N, seq_off, (const uint64_t *)B.ustamp,
-         (const Ctl *)B.ctl, B.pos);
+  LAUNCH(k_upd_stamp, g, kBlock, s, (const TickIn *)B.tin, m, B.N, seq_off, B.ustamp, B.ctl);
+  LAUNCH(k_upd_write, g, kBlock, s, (const TickIn *)B.tin, m, B.N, seq_off,
+         (const uint64_t *)B.ustamp, (const Ctl *)B.ctl, B.pos);
 }
 
 static Tree tree_of(const Bufs &B) {
@@ -1713,7 +1739,7 @@ static Tree tree_of(const Bufs &B) {
 }
 
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
-                  const uint32_t *qid, uint32_t nq, uint32_t key_bits, hipStream_t s) {
+                  uint32_t nq, uint32_t key_bits, hipStream_t s) {
   LAUNCH(k_mbr, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N,
          (const Ctl *)B.ctl, B.blk, B.red);
   LAUNCH(k_decide, 1, kChunkBlocks, s, B.ctl, B.blk, (const uint64_t *)B.red, B.front[0],
@@ -1724,8 +1750,8 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
     const int passes = (int)((key_bits + 7u) / 8u);
     const bool odd = passes & 1;
     LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
-           (const uint32_t *)B.blk, odd ? B.keyB : B.keyA, odd ? B.valB : B.valA, qid, nq,
-           B.qstamp);
+           (const uint32_t *)B.blk, odd ? B.keyB : B.keyA, odd ? B.valB : B.valA,
+           (const TickIn *)B.tin, nq, B.qstamp);
     if (odd)
       radix_sort_pairs(B.keyB, B.valB, B.keyA, B.valA, &B.ctl->n_present, B.N, nullptr, B.hist,
                        B.tot, 0, 8 * passes, s, B.pos, B.sxy);
@@ -1735,7 +1761,7 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
     return;
   }
   LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
-         (const uint32_t *)B.blk, B.keyA, B.valA, qid, nq, B.qstamp);
+         (const uint32_t *)B.blk, B.keyA, B.valA, (const TickIn *)B.tin, nq, B.qstamp);
   radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, B.N, nullptr, B.hist,
                    B.tot, 0, 32, s, B.pos, B.sxy, &B.ctl->sort_skip);
 }
@@ -1770,20 +1796,18 @@ void launch_leaves(const Bufs &B, hipStream_t s) {
          B.leaf_ovfc);
 }
 
-void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const float *ya,
-                  const float *xb, const float *yb, uint32_t nq, uint32_t covering,
-                  hipStream_t s) {
+void launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipStream_t s) {
+  const TickIn *tin = B.tin;
   const uint32_t *qord = nullptr;
   if (nq >= kQueryOrderMin) {
-    LAUNCH(k_qorder_keys, grid_for(nq), kBlock, s, B.ctl, xa, ya, nq, B.qkey, B.qord);
+    LAUNCH(k_qorder_keys, grid_for(nq), kBlock, s, B.ctl, tin, nq, B.qkey, B.qord);
     const bool alt = radix_sort_pairs(B.qkey, B.qord, B.qkey2, B.qord2, &B.ctl->n_qord, nq, nullptr,
                                       B.hist, B.tot, 0, 16, s);
     qord = alt ? B.qord2 : B.qord;
   }
-  LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, qid, xa, ya,
-         xb, yb, nq, B.N, (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg,
-         B.qrect, B.q_ni, B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering,
-         qord);
+  LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, tin, nq, B.N,
+         (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
+         B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering, qord);
   ScanJobs jobs{};
   jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
   jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
@@ -1791,7 +1815,7 @@ void launch_split(const Bufs &B, const uint32_t *qid, const float *xa, const flo
   mscan_reduce(jobs, 3, B.part, nullptr, s);
   LAUNCH(k_split_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, B.S, B.C);
   mscan_down(jobs, 3, (const uint64_t *)B.part, nullptr, s);
-  LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, qid, nq, B.N, (const uint64_t *)B.qstamp,
+  LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
          (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, (const uint32_t *)B.qpos, B.slots,

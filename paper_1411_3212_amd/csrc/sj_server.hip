@@ -101,9 +101,6 @@ struct ServedScene {
   uint8_t *mem = nullptr;
   size_t mem_bytes = 0;
   uint32_t max_updates = 0, max_queries = 0;
-  // input slots
-  uint32_t *s_id, *s_qid;
-  float *s_x, *s_y, *s_xa, *s_ya, *s_xb, *s_yb;
   // output slots, two sets used by alternate ticks: the set of a finished
   // tick stays valid while the scene's next tick runs
   uint64_t *o_cnt[2], *o_hash[2], *o_counters[2];
@@ -115,15 +112,6 @@ struct ServedScene {
   bool has_result = false;
   Request last{};
   int status = SJ_OK;
-};
-
-struct CopySeg {
-  const uint32_t *src;
-  uint32_t *dst;
-  uint32_t n;
-};
-struct CopyJob {
-  CopySeg seg[8];
 };
 
 // Tick record: the 8 tick counters, then the digest of the tick's results:
@@ -155,13 +143,6 @@ __global__ void __launch_bounds__(256) k_record_digest(const uint64_t *cnt, cons
     atomicAdd((unsigned long long *)&record[8], (unsigned long long)h);
     atomicAdd((unsigned long long *)&record[9], (unsigned long long)c);
   }
-}
-
-// One launch copies the eight input arrays of a tick into the slots.
-__global__ void k_copy_inputs(CopyJob job) {
-  const CopySeg &g = job.seg[blockIdx.y];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += gridDim.x * blockDim.x)
-    g.dst[i] = g.src[i];
 }
 
 }  // namespace
@@ -212,11 +193,11 @@ int sj_server_destroy(sj_server *s) {
 }
 
 size_t sj_server_scene_bytes(const sj_config *cfg, uint32_t max_updates) {
+  (void)max_updates;  // updates are read where the caller keeps them
   const size_t ws = sj_workspace_bytes(cfg);
   if (!ws) return 0;
-  const size_t Q = cfg->capacity_queries, M = max_updates;
-  return align_up(ws) + 3 * align_up(4 * M) + 5 * align_up(4 * Q) + 4 * align_up(8 * Q) +
-         2 * align_up(64);
+  const size_t Q = cfg->capacity_queries;
+  return align_up(ws) + 4 * align_up(8 * Q) + 2 * align_up(64);
 }
 
 int sj_server_admit(sj_server *s, const sj_config *cfg, uint32_t max_updates, uint32_t *scene_id) {
@@ -237,15 +218,7 @@ int sj_server_admit(sj_server *s, const sj_config *cfg, uint32_t max_updates, ui
     p += align_up(bytes);
     return r;
   };
-  const size_t Q = cfg->capacity_queries, M = max_updates;
-  sc.s_id = (uint32_t *)take(4 * M);
-  sc.s_x = (float *)take(4 * M);
-  sc.s_y = (float *)take(4 * M);
-  sc.s_qid = (uint32_t *)take(4 * Q);
-  sc.s_xa = (float *)take(4 * Q);
-  sc.s_ya = (float *)take(4 * Q);
-  sc.s_xb = (float *)take(4 * Q);
-  sc.s_yb = (float *)take(4 * Q);
+  const size_t Q = cfg->capacity_queries;
   for (int b = 0; b < 2; ++b) {
     sc.o_cnt[b] = (uint64_t *)take(8 * Q);
     sc.o_hash[b] = (uint64_t *)take(8 * Q);
@@ -312,23 +285,9 @@ static int start_tick(sj_server *s, uint32_t id) {
   ServedScene &sc = s->scenes[id];
   Request r = sc.queue.front();
   sc.queue.pop_front();
-  CopyJob job{};
-  const uint32_t *src[8] = {r.id, (const uint32_t *)r.x, (const uint32_t *)r.y, r.qid,
-                            (const uint32_t *)r.xa, (const uint32_t *)r.ya,
-                            (const uint32_t *)r.xb, (const uint32_t *)r.yb};
-  uint32_t *dst[8] = {sc.s_id, (uint32_t *)sc.s_x, (uint32_t *)sc.s_y, sc.s_qid,
-                      (uint32_t *)sc.s_xa, (uint32_t *)sc.s_ya, (uint32_t *)sc.s_xb,
-                      (uint32_t *)sc.s_yb};
-  uint32_t n[8] = {r.m, r.m, r.m, r.nq, r.nq, r.nq, r.nq, r.nq};
-  uint32_t mx = 1;
-  for (int i = 0; i < 8; ++i) {
-    job.seg[i] = CopySeg{src[i], dst[i], n[i]};
-    if (n[i] > mx) mx = n[i];
-  }
-  const unsigned gx = (unsigned)((mx + 255) / 256 < 1024 ? (mx + 255) / 256 : 1024);
-  hipLaunchKernelGGL(k_copy_inputs, dim3(gx, 8), dim3(256), 0, sc.stream, job);
-  int rc = sj_tick_graph(sc.scene, sc.s_id, sc.s_x, sc.s_y, r.m, sc.s_qid, sc.s_xa, sc.s_ya,
-                         sc.s_xb, sc.s_yb, r.nq);
+  // the graph reads the request's arrays, which stay valid until the tick
+  // is retired
+  int rc = sj_tick_graph(sc.scene, r.id, r.x, r.y, r.m, r.qid, r.xa, r.ya, r.xb, r.yb, r.nq);
   const uint32_t b = sc.parity;
   if (rc == SJ_OK && r.digest) rc = sj_result_hashes(sc.scene, sc.o_cnt[b], sc.o_hash[b]);
   if (rc == SJ_OK) rc = sj_tick_counters(sc.scene, sc.o_counters[b]);

@@ -276,15 +276,14 @@ void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
          (const uint32_t *)B.xbase, B.TCAP, B.tkey, B.tkhist);
 }
 
-void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, const uint32_t *qid,
-                 const float *xa, const float *ya, const float *xb, const float *yb, uint32_t nq,
-                 uint32_t covering, hipStream_t s) {
+void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, uint32_t covering,
+                 hipStream_t s) {
   LAUNCH(k_tune_begin, 1, 1, s, B.ctl, B.tune);
   for (uint32_t c = 0; c < n_cand; ++c) {
     LAUNCH(k_tune_set, 1, 1, s, B.ctl, (const TuneState *)B.tune, c, B.front[0]);
     launch_build(B, l_max, s);
     launch_leaves(B, s);
-    launch_split(B, qid, xa, ya, xb, yb, nq, covering, s);
+    launch_split(B, nq, covering, s);
     LAUNCH(k_cost_leaves, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
            (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
            (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.red);
