@@ -42,12 +42,15 @@ struct Tree {
 // Leaf containing the finest-level code `code`: its start-table cell gives
 // the leaf, or the internal node at level tlev to descend from (one child
 // reference per level, at most kFine - tlev of them).
-__device__ __forceinline__ uint32_t leaf_of(const Tree &tr, uint32_t code) {
-  const uint32_t T = tr.tlev;
-  const uint32_t e = tr.table[code >> (2u * (kFine - T))];
+__device__ __forceinline__ uint32_t table_entry(const Tree &tr, uint32_t code) {
+  return tr.table[code >> (2u * (kFine - tr.tlev))];
+}
+// The descent from table entry e (split from the table load so that a
+// thread can issue several table loads before it waits for one).
+__device__ __forceinline__ uint32_t leaf_from(const Tree &tr, uint32_t e, uint32_t code) {
   if (e & kLeafBit) return e & kLeafIdxMask;
   uint32_t node = e;
-  for (uint32_t k = T; k < (uint32_t)kFine; ++k) {
+  for (uint32_t k = tr.tlev; k < (uint32_t)kFine; ++k) {
     const uint32_t q = (code >> (2u * (kFine - k - 1u))) & 3u;
     const uint4 nd = tr.nodes[node];
     const uint32_t r = q == 0u ? nd.x : q == 1u ? nd.y : q == 2u ? nd.z : nd.w;
@@ -55,6 +58,9 @@ __device__ __forceinline__ uint32_t leaf_of(const Tree &tr, uint32_t code) {
     node = r;
   }
   return 0u;  // not reached: every level-16 cell lies in a leaf
+}
+__device__ __forceinline__ uint32_t leaf_of(const Tree &tr, uint32_t code) {
+  return leaf_from(tr, table_entry(tr, code), code);
 }
 
 // ------------------------------------------------------------- utilities --
@@ -309,7 +315,11 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
                                                    Ctl *ctl, const uint32_t *blk, uint32_t *keys,
                                                    uint32_t *vals, const TickIn *tin,
                                                    uint32_t nq, uint64_t *qstamp) {
-  __shared__ uint32_t lds[kWavesPerBlock + 1];
+  // A tile is kMortonRows rows of kBlock ids: every row's loads and table
+  // lookups are issued before the first is waited for, and one block scan
+  // ranks all rows (one 16-bit field per row).
+  constexpr uint32_t kMortonRows = 4;
+  __shared__ uint64_t lds[kWavesPerBlock + 1];
   const uint32_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < N ? b0 + chunk : N;
@@ -317,19 +327,40 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
   const bool keep = !ctl->rebuild;  // the quadtree is kept: sort by leaf
   tr.tlev = ctl->tlev;
   uint32_t base = blk[blockIdx.x];
-  for (uint64_t t0 = b0; t0 < b1; t0 += kBlock) {
-    const uint64_t i = t0 + threadIdx.x;
-    const float2 p = i < b1 ? pos[i] : make_float2(NAN, NAN);
-    const bool pres = p.x == p.x;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<uint32_t, kBlock>(pres ? 1u : 0u, lds, &tot);
-    if (pres) {
-      const float xv = p.x, yv = p.y;
-      const uint32_t code = morton2(cell_of(xv, x0, sc), cell_of(yv, y0, sc));
-      keys[base + ex] = keep ? leaf_of(tr, code) : code;
-      vals[base + ex] = (uint32_t)i;
+  for (uint64_t t0 = b0; t0 < b1; t0 += kBlock * kMortonRows) {
+    float2 p[kMortonRows];
+    uint32_t key[kMortonRows];
+    uint64_t flags = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kMortonRows; ++j) {
+      const uint64_t i = t0 + j * kBlock + threadIdx.x;
+      p[j] = i < b1 ? pos[i] : make_float2(NAN, NAN);
     }
-    base += tot;
+#pragma unroll
+    for (uint32_t j = 0; j < kMortonRows; ++j) {
+      const bool pres = p[j].x == p[j].x;
+      flags |= (uint64_t)(pres ? 1u : 0u) << (16u * j);
+      key[j] = pres ? morton2(cell_of(p[j].x, x0, sc), cell_of(p[j].y, y0, sc)) : 0u;
+    }
+    if (keep) {
+      uint32_t e[kMortonRows];
+#pragma unroll
+      for (uint32_t j = 0; j < kMortonRows; ++j)
+        e[j] = (flags >> (16u * j)) & 1u ? table_entry(tr, key[j]) : kLeafBit;
+#pragma unroll
+      for (uint32_t j = 0; j < kMortonRows; ++j) key[j] = leaf_from(tr, e[j], key[j]);
+    }
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan<uint64_t, kBlock>(flags, lds, &tot);
+#pragma unroll
+    for (uint32_t j = 0; j < kMortonRows; ++j) {
+      if ((flags >> (16u * j)) & 1u) {
+        const uint32_t r = base + (uint32_t)((ex >> (16u * j)) & 0xffffu);
+        keys[r] = key[j];
+        vals[r] = (uint32_t)(t0 + j * kBlock + threadIdx.x);
+      }
+      base += (uint32_t)((tot >> (16u * j)) & 0xffffu);
+    }
   }
   const uint64_t seq = ctl->qry_seq;
   const uint32_t *__restrict__ qid = tin->qid;
@@ -1286,15 +1317,13 @@ __device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk
   return count_rounds<NCH>(wrect, nk, p, h, lane);
 }
 
-__global__ void __launch_bounds__(kBlock) k_join_count(const Ctl *ctl, const uint4 *trec,
-                                                       const uint32_t *tleaf,
-                                                       const uint32_t *leaf_sqoff,
-                                                       const uint2 *__restrict__ sq,
-                                                       const float4 *__restrict__ qrect,
-                                                       const float2 *__restrict__ sxy,
-                                                       uint32_t *sq_cnt, float *tlog,
-                                                       const uint32_t *lstart,
-                                                       const uint32_t *llevel) {
+// Eight waves per SIMD (at most 64 registers) hide more of the gathers'
+// latency; this kernel fits without spilling registers to memory.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uint32_t *leaf_sqoff,
+             const uint2 *__restrict__ sq, const float4 *__restrict__ qrect,
+             const float2 *__restrict__ sxy, uint32_t *sq_cnt, float *tlog, const uint32_t *lstart,
+             const uint32_t *llevel) {
   __shared__ float4 lrect[kBlock];
   if (!ctl->go_split) return;
   const uint32_t nt = ctl->n_run;

@@ -170,8 +170,9 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
                                                        const uint32_t *n_dev, const uint32_t *gate,
                                                        const uint32_t *skip, int shift,
                                                        int last_shift, const uint32_t *hist,
-                                                       const uint32_t *tot, const float2 *gpos,
-                                                       float2 *gout) {
+                                                       const uint32_t *tot,
+                                                       const float2 *__restrict__ gpos,
+                                                       float2 *__restrict__ gout) {
   if (gated(gate)) return;
   const int role = pass_role(skip, shift);
   if (role == kPassNone) return;
@@ -251,14 +252,30 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < tile_n; i += kBlock) {
-      const uint32_t k = sk[i];
-      const uint32_t d = (k >> shift) & 255u;
-      const uint32_t g = goff[d] + (i - tbase[d]);
-      const uint32_t v = sv[i];
-      kout[g] = k;
-      vout[g] = v;
-      if (gather) gout[g] = gpos[v];
+    // every item's destination first, then all position gathers (issued
+    // together, at a valid id for items past the tile), then the stores
+    uint32_t gdst[kSortItems];
+    float2 gp[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const uint32_t i = r * kBlock + tid;
+      const bool valid = i < tile_n;
+      key[r] = valid ? sk[i] : 0u;
+      val[r] = valid ? sv[i] : 0u;
+      const uint32_t d = (key[r] >> shift) & 255u;
+      gdst[r] = valid ? goff[d] + (i - tbase[d]) : 0u;
+    }
+    if (gather) {
+#pragma unroll
+      for (int r = 0; r < kSortItems; ++r) gp[r] = gpos[val[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      if (r * kBlock + tid < tile_n) {
+        kout[gdst[r]] = key[r];
+        vout[gdst[r]] = val[r];
+        if (gather) gout[gdst[r]] = gp[r];
+      }
     }
     __syncthreads();
     goff[tid] += tcnt[tid];
