@@ -403,7 +403,8 @@ int sj_server_admit(sj_server *server, const sj_config *cfg, uint32_t max_update
 int sj_server_retire(sj_server *server, uint32_t scene_id);
 
 /* Queues a tick for a scene: device inputs as sj_apply_updates + sj_run_tick
- * (they must stay valid until the tick is retired); tags must be unique per
+ * (4-byte aligned; the tick reads them in place, so they must stay valid and
+ * unmodified until it is retired); tags must be unique per
  * scene.  d_record (device, 10 u64, may be NULL) receives the tick's record
  * when it finishes: the 8 counters of sj_tick_counters, then (with
  * SJ_SERVE_DIGEST, else 0, 0) the sum of the per-query pair-set hashes and

@@ -272,6 +272,9 @@ int sj_server_submit(sj_server *s, uint32_t id, const uint32_t *d_id, const floa
     return srv_fail(s, SJ_EINVAL, "submit: more updates or queries than the scene admits");
   if ((m && (!d_id || !d_x || !d_y)) || (nq && (!d_qid || !d_xa || !d_ya || !d_xb || !d_yb)))
     return srv_fail(s, SJ_EINVAL, "submit: null input");
+  const uintptr_t mis = (uintptr_t)d_id | (uintptr_t)d_x | (uintptr_t)d_y | (uintptr_t)d_qid |
+                        (uintptr_t)d_xa | (uintptr_t)d_ya | (uintptr_t)d_xb | (uintptr_t)d_yb;
+  if (mis & 3u) return srv_fail(s, SJ_EINVAL, "submit: misaligned input");
   if ((uintptr_t)d_record & 7u) return srv_fail(s, SJ_EINVAL, "submit: misaligned record");
   if (flags & ~(uint32_t)SJ_SERVE_DIGEST) return srv_fail(s, SJ_EINVAL, "submit: unknown flags");
   const bool digest = (flags & SJ_SERVE_DIGEST) != 0;

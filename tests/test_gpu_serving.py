@@ -1,6 +1,8 @@
 """Tick serving (continuous batching of many scenes on one GPU): each tick's
 results are the same alone and in the mix, scenes are admitted by the memory
 budget, and served results match the oracle."""
+import time
+
 import numpy as np
 import pytest
 
@@ -60,3 +62,45 @@ def test_serving_order_does_not_change_results():
     a = serving.serve(specs, reqs, 8 << 30, max_running=4, torch=torch, digest=True)
     b = serving.serve(specs, reqs, 8 << 30, max_running=1, torch=torch, digest=True)
     assert a["digest"] == b["digest"] and a["counters"] == b["counters"]
+
+
+def test_submit_checks_its_inputs():
+    """Requests the server cannot run are refused at submission (nothing is
+    queued): misaligned or null inputs, more updates than admitted, unknown
+    flags."""
+    import torch
+    from paper_1411_3212_amd.binding import SjError
+    sp = small_specs()[0]
+    serving.upload([sp], 1, torch)
+    buf, m, nq = sp.ticks[0]
+    views = serving.tick_views(buf, m, nq, torch)
+    need = serving.Server(1 << 20).scene_bytes(sp.cfg, sp.max_updates)
+    srv = serving.Server(need + (1 << 20))
+    sid = srv.admit(sp.cfg, sp.max_updates)
+    assert sid is not None
+    lib, h = srv._lib, srv.handle
+    p = [v.data_ptr() for v in views]
+
+    def submit(ptrs, m_, nq_, flags=0):
+        return lib.sj_server_submit(h, sid, ptrs[0], ptrs[1], ptrs[2], m_, ptrs[3], ptrs[4],
+                                    ptrs[5], ptrs[6], ptrs[7], nq_, 1, None, flags)
+
+    for k in range(8):
+        bad = list(p)
+        bad[k] += 2
+        assert submit(bad, m, nq) != 0, f"misaligned input {k}"
+        bad[k] = 0
+        assert submit(bad, m, nq) != 0, f"null input {k}"
+    assert submit(p, sp.max_updates + 1, nq) != 0
+    assert submit(p, m, nq, flags=2) != 0
+    assert srv.info()["queued"] == 0
+    srv.submit(sid, 7, *views)
+    assert srv.info()["queued"] + srv.info()["running"] == 1
+    done, t_end = [], time.monotonic() + 30.0
+    while not done and time.monotonic() < t_end:
+        done += srv.poll()
+    assert done and done[0][1] == 7 and done[0][2] == 0
+    srv.retire(sid)
+    with pytest.raises(SjError):
+        srv.submit(sid, 8, *views)
+    srv.close()
