@@ -40,12 +40,14 @@ WORKLOAD_TEXT = {
 }
 
 
-def scene_config(wl: workloads.Workload, th: int = 64) -> dict:
+def scene_config(wl: workloads.Workload, th: int = 64, covering: bool = True,
+                 reorder: bool = True) -> dict:
     """Capacities sized for a workload (subqueries, covering entries and
-    result ids per tick, with headroom)."""
+    result ids per tick, with headroom) and the covering / reorder switches."""
     from paper_1411_3212_amd.serving import scene_capacities
-    c = scene_capacities(wl, th)
+    c = scene_capacities(wl, th, covering)
     c.pop("nq")
+    c.update(covering=covering, reorder=reorder)
     return c
 
 
@@ -66,6 +68,10 @@ def parse():
                     help="also run a plain device copy of known size (counter calibration)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the run with the learned threshold")
+    ap.add_argument("--covering", default="on", choices=["on", "off"],
+                    help="off: every overlapped leaf is tested (no covering leaves)")
+    ap.add_argument("--reorder", default="on", choices=["on", "off"],
+                    help="off: join tasks in leaf order instead of heaviest first")
     return ap.parse_args()
 
 
@@ -210,7 +216,7 @@ def main():
     ticks = upload_ticks(wl, torch)
     t_gen = time.perf_counter() - t_gen
     nq = max(q for _, _, q in ticks)
-    cfg = scene_config(wl, args.th)
+    cfg = scene_config(wl, args.th, args.covering == "on", args.reorder == "on")
     scene = Scene(wl.n, nq, profile=True, **cfg)
     # each tick's inputs are checked and marshalled once, before the timing
     prep = [scene.prepare_tick(*tick_tensors(buf, m, q, torch)) for buf, m, q in ticks]
@@ -286,7 +292,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "objects": wl.n, "queries_per_tick": nq, "ticks": K, "th_quad": args.th,
-                   "covering": True, "reorder": True, "rebuild": "auto/32",
+                   "covering": args.covering == "on", "reorder": args.reorder == "on",
+                   "rebuild": "auto/32",
                    "launch": args.mode},
         "ticks_per_s": K / wall,
         "p50_tick_ms": float(np.percentile(lat, 50)),

@@ -41,7 +41,9 @@ class SceneSpec:
     ticks: list = field(default_factory=list)  # (packed device buffer, m, nq)
 
 
-def scene_capacities(wl: workloads.Workload, th: int = 64) -> dict:
+def scene_capacities(wl: workloads.Workload, th: int = 64, covering: bool = True) -> dict:
+    """Per-tick capacities with headroom.  Without covering leaves every
+    pair is written as an id, so the result capacity is four times larger."""
     kind = wl.params.get("kind", wl.name)
     rate = float(wl.params.get("query_rate", 0.1 if kind == "hotspot" else 0.5))
     q = max(1, int(round(rate * wl.n)))
@@ -53,8 +55,9 @@ def scene_capacities(wl: workloads.Workload, th: int = 64) -> dict:
             slots = 64  # queries in the dense cores overlap more than 32 leaves
     else:
         per = dict(sub=16, cov=16, res=96)
+    res = per["res"] * (1 if covering else 4)
     return dict(nq=q, th=th, capacity_subqueries=per["sub"] * q,
-                capacity_covering=per["cov"] * q, capacity_results=per["res"] * q,
+                capacity_covering=per["cov"] * q, capacity_results=res * q,
                 split_slots=slots)
 
 
