@@ -152,6 +152,12 @@ def load():
     return lib
 
 
+def _require(cond: bool, msg: str):
+    """Argument check that stays on under python -O."""
+    if not cond:
+        raise ValueError(msg)
+
+
 def _check(rc: int, handle=None):
     if rc != SJ_OK:
         msg = load().sj_last_error(handle)
@@ -310,9 +316,11 @@ class Scene:
 
     @staticmethod
     def _dev(t, dtype, n=None):
-        assert t.is_cuda and t.is_contiguous() and t.dtype == dtype, (t.dtype, dtype)
+        _require(t.is_cuda and t.is_contiguous() and t.dtype == dtype,
+                 f"expected a contiguous CUDA tensor of {dtype}, got {t.dtype} "
+                 f"(cuda={t.is_cuda}, contiguous={t.is_contiguous()})")
         if n is not None:
-            assert t.numel() == n
+            _require(t.numel() == n, f"expected {n} elements, got {t.numel()}")
         return t
 
     def apply_updates(self, ids, x, y):
@@ -346,7 +354,8 @@ class Scene:
         args = (ids, x, y, qid, xa, ya, xb, yb)
         m, nq = ids.numel(), qid.numel()
         for t in (ids, qid):
-            assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32)
+            _require(t.is_cuda and t.is_contiguous() and t.dtype in (torch.int32, torch.uint32),
+                     "ids and qid must be contiguous CUDA int32/uint32 tensors")
         for t, n in ((x, m), (y, m), (xa, nq), (ya, nq), (xb, nq), (yb, nq)):
             self._dev(t, torch.float32, n)
         p = [_ptr(t) for t in args]
@@ -400,7 +409,8 @@ class Scene:
         """Enqueues a copy of the last tick's 8 counters into ``out`` (an
         int64 CUDA tensor of 8 elements, or a view of a larger one)."""
         import torch
-        assert out.is_cuda and out.dtype == torch.int64 and out.numel() >= 8
+        _require(out.is_cuda and out.dtype == torch.int64 and out.numel() >= 8,
+                 "out must be a CUDA int64 tensor of at least 8 elements")
         _check(self._lib.sj_tick_counters(self.handle, _ptr(out)), self.handle)
 
     def stats(self, check: bool = True) -> dict:
@@ -422,8 +432,9 @@ class Scene:
         tensor of sj_mlp_param_count() values, copied), coef = COST_TERMS floats,
         cand = candidate thresholds (1..8, each >= th_min)."""
         import torch
-        assert w.is_cuda and w.dtype in (torch.int16, torch.uint16) and w.is_contiguous()
-        assert len(coef) == COST_TERMS
+        _require(w.is_cuda and w.dtype in (torch.int16, torch.uint16) and w.is_contiguous(),
+                 "weights must be a contiguous CUDA int16/uint16 tensor of bf16 bits")
+        _require(len(coef) == COST_TERMS, f"expected {COST_TERMS} cost coefficients")
         cf = (c_float * COST_TERMS)(*[float(v) for v in coef])
         cd = (c_uint32 * len(cand))(*[int(v) for v in cand])
         _check(self._lib.sj_set_cost_model(self.handle, _ptr(w), cf, cd, len(cand)), self.handle)
