@@ -45,8 +45,18 @@ __global__ void __launch_bounds__(kBlock) k_mscan_reduce(ScanJobs jobs, uint64_t
   const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  // four rows of loads in flight per thread
   uint64_t s = 0;
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) s += job_in(j, i);
+  for (uint64_t t0 = b0; t0 < b1; t0 += 4u * kBlock) {
+    uint32_t v[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; ++r) {
+      const uint64_t i = t0 + r * kBlock + threadIdx.x;
+      v[r] = i < b1 ? job_in(j, i) : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; ++r) s += v[r];
+  }
   s = wave_sum(s);
   if (lane_id() == 0) lds[threadIdx.x / kWave] = s;
   __syncthreads();
@@ -67,13 +77,23 @@ __global__ void __launch_bounds__(kBlock) k_mscan_down(ScanJobs jobs, const uint
   const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   uint64_t run = part[blockIdx.y * kChunkBlocks + blockIdx.x];
-  for (uint64_t t0 = b0; t0 < b1; t0 += kBlock) {
-    const uint64_t i = t0 + threadIdx.x;
-    const uint64_t v = i < b1 ? job_in(j, i) : 0;
-    uint64_t tot;
-    const uint64_t ex = block_excl_scan<uint64_t, kBlock>(v, lds, &tot);
-    if (i < b1) job_store(j, i, run + ex);
-    run += tot;
+  // the loads of four rows are issued before the first row is scanned
+  for (uint64_t t0 = b0; t0 < b1; t0 += 4u * kBlock) {
+    uint32_t v[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; ++r) {
+      const uint64_t i = t0 + r * kBlock + threadIdx.x;
+      v[r] = i < b1 ? job_in(j, i) : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; ++r) {
+      if (t0 + r * kBlock >= b1) break;  // uniform over the block
+      const uint64_t i = t0 + r * kBlock + threadIdx.x;
+      uint64_t tot;
+      const uint64_t ex = block_excl_scan<uint64_t, kBlock>(v[r], lds, &tot);
+      if (i < b1) job_store(j, i, run + ex);
+      run += tot;
+    }
   }
 }
 
