@@ -164,7 +164,18 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const 
   const uint64_t b1 = b0 + chunk < n ? b0 + chunk : n;
   lh[threadIdx.x] = 0;
   __syncthreads();
-  for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) atomicAdd(&lh[(keys[i] >> shift) & 255u], 1u);
+  // kSortItems rows of loads in flight per thread
+  for (uint64_t t0 = b0; t0 < b1; t0 += (uint64_t)kSortItems * kBlock) {
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const uint64_t i = t0 + (uint64_t)r * kBlock + threadIdx.x;
+      k[r] = i < b1 ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+      if (t0 + (uint64_t)r * kBlock + threadIdx.x < b1) atomicAdd(&lh[(k[r] >> shift) & 255u], 1u);
+  }
   __syncthreads();
   hist[threadIdx.x * kChunkBlocks + blockIdx.x] = lh[threadIdx.x];
 }
