@@ -251,15 +251,21 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   __shared__ uint32_t lds[kChunkBlocks / kWave + 1];
   const int t = threadIdx.x;
   if (t < 512) tkhist[t] = 0;  // task-order totals and cursors of this tick
-  const uint32_t mnx = block_minmax_1024<false>((uint32_t)red[kRedMinX * kChunkBlocks + t], lds);
-  const uint32_t mny = block_minmax_1024<false>((uint32_t)red[kRedMinY * kChunkBlocks + t], lds);
-  const uint32_t mxx = block_minmax_1024<true>((uint32_t)red[kRedMaxX * kChunkBlocks + t], lds);
-  const uint32_t mxy = block_minmax_1024<true>((uint32_t)red[kRedMaxY * kChunkBlocks + t], lds);
+  // every partial is loaded before the first reduction waits on a barrier
+  const uint32_t p_mnx = (uint32_t)red[kRedMinX * kChunkBlocks + t];
+  const uint32_t p_mny = (uint32_t)red[kRedMinY * kChunkBlocks + t];
+  const uint32_t p_mxx = (uint32_t)red[kRedMaxX * kChunkBlocks + t];
+  const uint32_t p_mxy = (uint32_t)red[kRedMaxY * kChunkBlocks + t];
+  const uint32_t p_out = (uint32_t)red[kRedOutside * kChunkBlocks + t];
+  const uint32_t p_cnt = blk[t];
+  const uint32_t mnx = block_minmax_1024<false>(p_mnx, lds);
+  const uint32_t mny = block_minmax_1024<false>(p_mny, lds);
+  const uint32_t mxx = block_minmax_1024<true>(p_mxx, lds);
+  const uint32_t mxy = block_minmax_1024<true>(p_mxy, lds);
   uint32_t outside;
-  block_excl_scan<uint32_t, kChunkBlocks>((uint32_t)red[kRedOutside * kChunkBlocks + t], lds,
-                                          &outside);
+  block_excl_scan<uint32_t, kChunkBlocks>(p_out, lds, &outside);
   uint32_t total;
-  const uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(blk[t], lds, &total);
+  const uint32_t ex = block_excl_scan<uint32_t, kChunkBlocks>(p_cnt, lds, &total);
   blk[t] = ex;
   if (t != 0) return;
   ctl->err = ctl->err_upd;
@@ -951,9 +957,14 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
                                                             uint64_t *part, uint64_t cap_sq,
                                                             uint64_t cap_cov) {
   __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
-  uint64_t tot[3];
+  // the three partials are loaded before the first scan waits on a barrier
+  uint64_t v[3], tot[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v[q] = part[q * kChunkBlocks + threadIdx.x];
+#pragma unroll
   for (int q = 0; q < 3; ++q) {
-    tot[q] = scan_partials(part + q * kChunkBlocks, lds);
+    part[q * kChunkBlocks + threadIdx.x] =
+        block_excl_scan<uint64_t, kChunkBlocks>(v[q], lds, &tot[q]);
     if (threadIdx.x == 0) job_store(jobs.j[q], job_n(jobs.j[q]), tot[q]);
   }
   if (threadIdx.x != 0) return;
@@ -1442,17 +1453,23 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
   __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
   __shared__ uint32_t ldm[kChunkBlocks / kWave + 1];
   const bool ok = ctl->go_split != 0;
+  const int t = threadIdx.x;
+  // every partial is loaded before the first scan waits on a barrier
+  const uint64_t p_res = ok ? part[t] : 0u;
+  const uint64_t p_covp = red[kRedCovPairs * kChunkBlocks + t];
+  const uint64_t p_tests = red[kRedTests * kChunkBlocks + t];
+  const uint64_t p_tasks = red[kRedTasks * kChunkBlocks + t];
+  const uint32_t p_mx = (uint32_t)red[kRedMaxLeaf * kChunkBlocks + t];
   uint64_t total = 0;
   if (ok) {
-    total = scan_partials(part, lds);
-    if (threadIdx.x == 0) job_store(jobs.j[0], job_n(jobs.j[0]), total);
+    part[t] = block_excl_scan<uint64_t, kChunkBlocks>(p_res, lds, &total);
+    if (t == 0) job_store(jobs.j[0], job_n(jobs.j[0]), total);
   }
-  const int t = threadIdx.x;
   uint64_t covp, tests, tasks;
-  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedCovPairs * kChunkBlocks + t], lds, &covp);
-  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedTests * kChunkBlocks + t], lds, &tests);
-  block_excl_scan<uint64_t, kChunkBlocks>(red[kRedTasks * kChunkBlocks + t], lds, &tasks);
-  const uint32_t mx = block_minmax_1024<true>((uint32_t)red[kRedMaxLeaf * kChunkBlocks + t], ldm);
+  block_excl_scan<uint64_t, kChunkBlocks>(p_covp, lds, &covp);
+  block_excl_scan<uint64_t, kChunkBlocks>(p_tests, lds, &tests);
+  block_excl_scan<uint64_t, kChunkBlocks>(p_tasks, lds, &tasks);
+  const uint32_t mx = block_minmax_1024<true>(p_mx, ldm);
   if (t != 0) return;
   ctl->max_leaf = mx;
   ctl->tests = tests;
