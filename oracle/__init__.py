@@ -25,6 +25,11 @@ computes, with the passage of the paper it follows:
 * ``split`` -- query splitting into intersecting and covering subqueries
   (mapping function g; indexing of queries).
 * ``mix64`` -- SplitMix64's output function, used by the pair-set hash.
+* ``ug_col`` / ``ug_cells`` / ``ug_split`` -- the uniform grid of the UG
+  method (Definition "MBR partitioning into a uniform grid"; UG index
+  creation and query indexing): columns and rows of the frame along its
+  finest cells, cells numbered by Morton code, query splitting by the
+  nested loop over the query's cell range.
 """
 from __future__ import annotations
 
@@ -78,6 +83,12 @@ def _load():
         "or_split": (None, [u32, P, P, P, P, P, ctypes.c_float, ctypes.c_float, i32,
                             u32, P, P, P, P, P, P, P, P]),
         "or_num_threads": (ctypes.c_int, []),
+        "or_set_num_threads": (None, [ctypes.c_int]),
+        "or_ug_col": (u32, [u32, u32]),
+        "or_ug_bits": (u32, [u32]),
+        "or_ug_cells": (None, [u32, P, P, P, ctypes.c_float, ctypes.c_float, i32, u32, P]),
+        "or_ug_split": (None, [u32, P, P, P, P, P, ctypes.c_float, ctypes.c_float, i32, u32,
+                               P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -101,6 +112,11 @@ def _u32(a):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over queries (1: single core)."""
+    _load().or_set_num_threads(int(n))
 
 
 class State:
@@ -272,4 +288,46 @@ def split(live, rects, fr, leaves: Leaves):
     li = np.zeros(int(oi[-1]), np.uint32)
     lc = np.zeros(int(oc[-1]), np.uint32)
     lib.or_split(*args, None, None, _p(oi), _p(oc), _p(li), _p(lc))
+    return oi, li, oc, lc
+
+
+def ug_col(fine: int, s: int) -> int:
+    """Grid column (or row) of a finest-level cell for split factor s."""
+    return int(_load().or_ug_col(int(fine), int(s)))
+
+
+def ug_bits(s: int) -> int:
+    return int(_load().or_ug_bits(int(s)))
+
+
+def ug_cells(st: State, fr, s: int) -> np.ndarray:
+    """Grid cell (Morton code over ug_bits(s) bits per axis) of every object
+    by id; 0xffffffff for objects without a position."""
+    cell = np.zeros(st.N, np.uint32)
+    _load().or_ug_cells(st.N, _p(st.px), _p(st.py), _p(st.has), ctypes.c_float(fr[0]),
+                        ctypes.c_float(fr[1]), int(fr[2]), int(s), _p(cell))
+    return cell
+
+
+def ug_split(live, rects, fr, s: int, count):
+    """Query splitting over the grid: (oi, li, oc, lc) as ``split``, with
+    cell Morton codes in place of leaf indices; count[z] = objects of cell z
+    (cells without objects are skipped)."""
+    xa, ya, xb, yb = _q(rects)
+    live = np.ascontiguousarray(live, np.uint8)
+    count = _u32(count)
+    nq = len(xa)
+    lib = _load()
+    ni = np.zeros(nq, np.uint64)
+    nc = np.zeros(nq, np.uint64)
+    args = (nq, _p(live), _p(xa), _p(ya), _p(xb), _p(yb), ctypes.c_float(fr[0]),
+            ctypes.c_float(fr[1]), int(fr[2]), int(s), _p(count))
+    lib.or_ug_split(*args, _p(ni), _p(nc), None, None, None, None)
+    oi = np.zeros(nq + 1, np.uint64)
+    oc = np.zeros(nq + 1, np.uint64)
+    np.cumsum(ni, out=oi[1:])
+    np.cumsum(nc, out=oc[1:])
+    li = np.zeros(int(oi[-1]), np.uint32)
+    lc = np.zeros(int(oc[-1]), np.uint32)
+    lib.or_ug_split(*args, None, None, _p(oi), _p(oc), _p(li), _p(lc))
     return oi, li, oc, lc

@@ -154,9 +154,11 @@ int64_t or_brute_hash(uint32_t N, const float *px, const float *py,
 
 /* ------------------------------------------------------------------ */
 /* Second, independent CPU index: a plain uniform grid in double        */
-/* precision whose cell side is at least the largest query side.  Same  */
-/* exact containment test; used to check the brute force at scale and  */
-/* to replace it where the brute force is too slow.                     */
+/* precision whose cell side is a quarter of the largest query side     */
+/* (at least 1/4096 of the objects' extent).  A query scans every cell  */
+/* its corners' floors span, so no candidate is missed.  Same exact     */
+/* containment test; used to check the brute force at scale and to      */
+/* replace it where the brute force is too slow.                        */
 /* ------------------------------------------------------------------ */
 
 int64_t or_grid_hash(uint32_t N, const float *px, const float *py,
@@ -186,7 +188,8 @@ int64_t or_grid_hash(uint32_t N, const float *px, const float *py,
     if (h > side && isfinite(h)) side = h;
   }
   double ext = fmax(x1 - x0, y1 - y0);
-  if (side < ext / 2048.0) side = ext / 2048.0; /* bound the cell count */
+  side *= 0.25; /* cells of a quarter of the largest query side: fewer candidates */
+  if (side < ext / 4096.0) side = ext / 4096.0; /* bound the cell count */
   if (!(side > 0.0)) side = 1.0;
   int64_t gx = (int64_t)floor((x1 - x0) / side) + 1;
   int64_t gy = (int64_t)floor((y1 - y0) / side) + 1;
@@ -204,10 +207,19 @@ int64_t or_grid_hash(uint32_t N, const float *px, const float *py,
     start[cellof[j] + 1]++;
   }
   for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+  /* positions are copied next to their ids in cell order, so a query scans
+     its candidate cells sequentially */
+  float *ix = (float *)malloc(sizeof(float) * (npres ? npres : 1));
+  float *iy = (float *)malloc(sizeof(float) * (npres ? npres : 1));
   uint32_t *fill = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)ncell);
   memcpy(fill, start, sizeof(uint32_t) * (size_t)ncell);
   for (uint32_t j = 0; j < N; ++j)
-    if (has[j]) items[fill[cellof[j]]++] = j;
+    if (has[j]) {
+      uint32_t t = fill[cellof[j]]++;
+      items[t] = j;
+      ix[t] = px[j];
+      iy[t] = py[j];
+    }
   free(fill);
   int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
@@ -228,10 +240,9 @@ int64_t or_grid_hash(uint32_t N, const float *px, const float *py,
           for (int64_t cx = cx0; cx <= cx1; ++cx) {
             int64_t cell = cy * gx + cx;
             for (uint32_t t = start[cell]; t < start[cell + 1]; ++t) {
-              uint32_t j = items[t];
-              if (or_inside(px[j], py[j], xa[k], ya[k], xb[k], yb[k])) {
+              if (or_inside(ix[t], iy[t], xa[k], ya[k], xb[k], yb[k])) {
                 ++c;
-                h += or_mix64(hi | j);
+                h += or_mix64(hi | items[t]);
               }
             }
           }
@@ -243,6 +254,8 @@ int64_t or_grid_hash(uint32_t N, const float *px, const float *py,
   }
   free(start);
   free(items);
+  free(ix);
+  free(iy);
   free(cellof);
   return total;
 }
@@ -508,4 +521,93 @@ int or_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* Threads of the OpenMP loops over queries (n >= 1), e.g. 1 for a
+ * single-core timing. */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Uniform grid partitioning (Definition "MBR partitioning into a      */
+/* uniform grid"; index creation and indexing of UG).  The frame is the */
+/* same square as the quadtree's; it is cut into s columns and s rows   */
+/* of (nearly) equal width along the finest-level cells of the frame:   */
+/* finest cell i (0..2^16-1) belongs to column floor(i * s / 2^16).     */
+/* Every column then spans floor or ceil of 2^16 / s finest cells (the  */
+/* widths differ by at most one finest cell), the map is monotone, and  */
+/* objects and query corners go through the same finest-cell function   */
+/* (or_cell), so covering decisions stay sound.  A cell (i, j) is        */
+/* identified by its Morton code over b bits per axis, b the smallest   */
+/* with 2^b >= s (the paper numbers the grid cells by Morton codes).    */
+/* ------------------------------------------------------------------ */
+
+uint32_t or_ug_col(uint32_t fine, uint32_t s) {
+  return (uint32_t)(((uint64_t)fine * s) >> OR_L);
+}
+
+uint32_t or_ug_bits(uint32_t s) {
+  uint32_t b = 0;
+  while ((1u << b) < s) ++b;
+  return b;
+}
+
+/* Grid cell (Morton code) of every object with a position: cell[j]
+ * (0xffffffff for objects without one). */
+void or_ug_cells(uint32_t N, const float *px, const float *py, const uint8_t *has, float x0,
+                 float y0, int32_t e, uint32_t s, uint32_t *cell) {
+  uint32_t b = or_ug_bits(s);
+  for (uint32_t j = 0; j < N; ++j) {
+    if (!has[j]) {
+      cell[j] = 0xffffffffu;
+      continue;
+    }
+    uint32_t ci = or_ug_col(or_cell(px[j], x0, e), s);
+    uint32_t cj = or_ug_col(or_cell(py[j], y0, e), s);
+    cell[j] = or_morton(ci, cj, b);
+  }
+}
+
+/* Query splitting over the grid (mapping function g): the query's corner
+ * columns and rows [c(f(x^a)), c(f(x^b))] x [c(f(y^a)), c(f(y^b))] name
+ * every cell it overlaps; a cell strictly inside that range on both axes
+ * is covering, any other intersecting.  Plain definition: the nested loop
+ * over the range.  Cells with no object (count[z] == 0) are skipped.
+ * Pass 1 (out == NULL): counts; pass 2: Morton codes of the cells, in
+ * row-then-column order. */
+void or_ug_split(uint32_t nq, const uint8_t *live, const float *xa, const float *ya,
+                 const float *xb, const float *yb, float x0, float y0, int32_t e, uint32_t s,
+                 const uint32_t *count, uint64_t *ni, uint64_t *nc, const uint64_t *oi,
+                 const uint64_t *oc, uint32_t *out_i, uint32_t *out_c) {
+  uint32_t b = or_ug_bits(s);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < (int64_t)nq; ++k) {
+    uint64_t ci = 0, cc = 0;
+    int ok = live[k] && xa[k] <= xb[k] && ya[k] <= yb[k] && isfinite(xa[k]) &&
+             isfinite(xb[k]) && isfinite(ya[k]) && isfinite(yb[k]);
+    if (ok) {
+      uint32_t i0 = or_ug_col(or_cell(xa[k], x0, e), s), i1 = or_ug_col(or_cell(xb[k], x0, e), s);
+      uint32_t j0 = or_ug_col(or_cell(ya[k], y0, e), s), j1 = or_ug_col(or_cell(yb[k], y0, e), s);
+      for (uint32_t j = j0; j <= j1; ++j)
+        for (uint32_t i = i0; i <= i1; ++i) {
+          uint32_t z = or_morton(i, j, b);
+          if (count[z] == 0) continue;
+          int cov = i0 < i && i < i1 && j0 < j && j < j1;
+          if (cov) {
+            if (out_c) out_c[oc[k] + cc] = z;
+            ++cc;
+          } else {
+            if (out_i) out_i[oi[k] + ci] = z;
+            ++ci;
+          }
+        }
+    }
+    if (ni) ni[k] = ci;
+    if (nc) nc[k] = cc;
+  }
 }
