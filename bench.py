@@ -6,11 +6,21 @@ the join of all its range queries (index, quadtree, query split, schedule,
 join count / scan / write) and the fetch of its compressed results.  Inputs of
 every tick are generated up front and resident in HBM before timing starts.
 
+Default workload: 20M objects in Gaussian hotspots, 2M square queries per
+tick.  The headline configuration builds its quadtrees with the threshold
+that the learned cost model picks (tuning cost amortised over the ticks
+between two tunings); the same ticks run again with fixed thresholds (64,
+the best fixed one 256, and the paper's 384) in the same loop.  Every
+configuration is forced to rebuild its quadtree on the first timed tick, so
+the timed window holds at least one rebuild tick per rebuild period; their
+latency is also reported apart.  A separate untimed pass checks that every
+configuration gives the same per-query result sizes and pair-set hashes.
+
 Prints one JSON line: result pairs/s (value), ticks/s, p50/p99 tick latency,
-the roofline figure of the dominant kernel (measured with HIP events on the
-scene's stream inside the timed region), the CPU oracle's throughput on a
-bounded sample of the same workload, and the same ticks run again with the
-learned leaf threshold (cost model) beside the fixed one.
+the roofline figure of the dominant kernel (its launch time measured with
+HIP events on the scene's stream inside the timed region), and the CPU
+oracle's throughput on a bounded sample of the same workload (uniform grid
+and brute force, on all host cores and on one core).
 """
 from __future__ import annotations
 
@@ -29,13 +39,16 @@ if ROOT not in sys.path:
 from paper_1411_3212_amd import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+MODEL = os.path.join(ROOT, "paper_1411_3212_amd", "data", "cost_model.json")
 
 WORKLOAD_TEXT = {
     "hotspot": "1M objects: 20 Gaussian hotspots (sigma 0.01) + 10% uniform in [0,1]^2, random "
                "walk step U[0,5e-4], 10% issue a square query of side 0.002 per tick, FP32",
     "segments": "4M objects on 1,000 random segments (jitter 2e-4) moving U[1e-4,1e-3]/tick; 50% "
-                "issue rectangles with sides U[5e-4,4e-3]",
-    "hotspot_20m": "20M objects as hotspot",
+                "issue rectangles with sides U[5e-4,4e-3], FP32",
+    "hotspot_20m": "20M objects: 20 Gaussian hotspots (sigma 0.01) + 10% uniform in [0,1]^2, "
+                   "random walk step U[0,5e-4], 10% issue a square query of side 0.002 per tick, "
+                   "FP32",
     "uniform_1tick": "4,096 uniform objects, 1,024 squares of side 0.01",
 }
 
@@ -54,20 +67,24 @@ def scene_config(wl: workloads.Workload, th: int = 64, covering: bool = True,
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=90)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="hotspot", choices=sorted(workloads.WORKLOADS))
-    ap.add_argument("--th", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=64,
+                    help="timed ticks (64 = two rebuild periods)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hotspot_20m", choices=sorted(workloads.WORKLOADS))
+    ap.add_argument("--threshold", default="learned",
+                    help="'learned' (cost model) or a fixed leaf threshold for the headline run")
+    ap.add_argument("--compare", default="64,256,384",
+                    help="fixed thresholds timed beside the headline run ('' for none)")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the untimed pass that compares per-query hashes across runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="target CPU time of the oracle samples (all variants together)")
     ap.add_argument("--mode", default="graph", choices=["graph", "eager"],
                     help="graph: each tick replays as one captured graph on that tick's own input "
                          "buffers; eager: one launch per kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the run with the learned threshold")
     ap.add_argument("--covering", default="on", choices=["on", "off"],
                     help="off: every overlapped leaf is tested (no covering leaves)")
     ap.add_argument("--reorder", default="on", choices=["on", "off"],
@@ -108,7 +125,7 @@ def upload_ticks(wl, torch):
     return ticks
 
 
-def algorithmic_bytes(c: dict, n_present: int, nq: int) -> dict:
+def algorithmic_bytes(c: dict, n_present: int) -> dict:
     """Minimum HBM bytes each join kernel must move for one tick, from the
     tick's counters (each structure read or written once per pass)."""
     sq, res = c["n_isect"], c["n_isect_ids"]
@@ -122,7 +139,165 @@ def algorithmic_bytes(c: dict, n_present: int, nq: int) -> dict:
     }
 
 
+class Run:
+    """One configuration over the workload's ticks: a profiled scene (the
+    join write pass of every tick is bracketed by HIP events on the scene's
+    stream) and the same loop for every configuration."""
+
+    def __init__(self, args, wl, nq, th, torch, learned=False):
+        from paper_1411_3212_amd import costmodel
+        from paper_1411_3212_amd.binding import Scene
+        self.args, self.torch, self.learned = args, torch, learned
+        self.label = "learned" if learned else f"fixed {th}"
+        self.model = costmodel.load(MODEL) if learned else None
+        cfg = scene_config(wl, th if not learned else 64, args.covering == "on",
+                           args.reorder == "on")
+        self.th = None if learned else th
+        kw = {k: v for k, v in cfg.items() if k != "th"}
+        if learned:
+            self.scene = Scene(wl.n, nq, th=64, th_min=min(self.model["cand"]), thresh_mlp=True,
+                               profile=True, **kw)
+            costmodel.install(self.scene, self.model, torch)
+        else:
+            self.scene = Scene(wl.n, nq, th=th, profile=True, **kw)
+
+    def tick(self, prep, buf, m, q, mode=None):
+        sc, torch = self.scene, self.torch
+        if (mode or self.args.mode) == "graph":
+            sc.tick_graph(prep)
+        else:
+            d = views(buf, m, q, torch)
+            sc.apply_updates(d["ids"], d["x"], d["y"])
+            sc.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
+
+    def timed(self, ticks, W, K):
+        """W warmup ticks, a forced rebuild on tick W, then K timed ticks."""
+        torch, sc = self.torch, self.scene
+        prep = [sc.prepare_tick(*tick_tensors(buf, m, q, torch)) for buf, m, q in ticks[:W + K]]
+        counters = np.zeros((W + K, 8), dtype=np.int64)
+        lat, join_ms, rebuilt = [], [], []
+        for i in range(W + K):
+            if i == W:
+                sc.build_index()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            h0 = time.perf_counter()
+            self.tick(prep[i], *ticks[i])
+            r = sc.fetch()  # synchronises: the tick's results and counters are available
+            counters[i] = r.counters()
+            if i >= W:
+                lat.append((time.perf_counter() - h0) * 1e3)
+                join_ms.append(sc.phase_times()["join_write"])
+                rebuilt.append(sc.stats()["rebuilt"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        c = counters[W:]
+        assert (c[:, 7] == 0).all(), f"{self.label}: device error bits {np.unique(c[:, 7])}"
+        lat, rebuilt = np.array(lat), np.array(rebuilt, dtype=bool)
+        self.counters, self.wall, self.K = c, wall, K
+        self.lat, self.rebuilt, self.join_ms = lat, rebuilt, np.array(join_ms)
+        self.n_present = sc.stats()["n_present"]
+        self.th_last = sc.stats()["th"]
+        return self
+
+    def tuning_ms(self, ticks, W):
+        """Extra time of a tick whose build tunes the threshold, against a
+        tick that builds without tuning (eager ticks, the best of two each):
+        the model is installed again so that the next build tunes."""
+        from paper_1411_3212_amd import costmodel
+        torch, sc = self.torch, self.scene
+        buf, m, q = ticks[W]
+        tuned, plain = [], []
+        for _ in range(2):
+            costmodel.install(sc, self.model, torch)
+            for out in (tuned, plain):
+                sc.build_index()
+                torch.cuda.synchronize()
+                h0 = time.perf_counter()
+                self.tick(None, buf, m, q, mode="eager")
+                sc.fetch()
+                out.append((time.perf_counter() - h0) * 1e3)
+        info = sc.tune_info()
+        return max(0.0, min(tuned) - min(plain)), info
+
+    def phase_sample(self, ticks, start, n):
+        """Per-phase device times of n further eager ticks."""
+        from paper_1411_3212_amd.binding import PHASES
+        acc = {k: 0.0 for k in PHASES}
+        for i in range(start, start + n):
+            self.tick(None, *ticks[i], mode="eager")
+            self.scene.fetch()
+            ph = self.scene.phase_times()
+            for k in PHASES:
+                acc[k] += ph[k]
+        return {k: round(v / n, 4) for k, v in acc.items()}
+
+    def summary(self, extra_ms_per_tick: float = 0.0) -> dict:
+        K, c = self.K, self.counters
+        pairs = int(c[:, 0].sum())
+        ms = self.wall * 1e3 / K + extra_ms_per_tick
+        keep = self.lat[~self.rebuilt]
+        out = dict(ticks_per_s=1e3 / ms, ms_per_step=ms, pairs_per_s=pairs / (ms * 1e-3 * K),
+                   p50_tick_ms=float(np.percentile(self.lat, 50)),
+                   p99_tick_ms=float(np.percentile(self.lat, 99)),
+                   rebuild_ticks=int(self.rebuilt.sum()),
+                   rebuild_tick_ms=[round(float(v), 3) for v in self.lat[self.rebuilt]],
+                   keep_tick_p50_ms=float(np.percentile(keep, 50)) if len(keep) else None,
+                   keep_tick_p99_ms=float(np.percentile(keep, 99)) if len(keep) else None,
+                   th=self.th_last)
+        return out
+
+    def close(self):
+        self.scene.close()
+
+
+def verify(args, wl, ticks, nq, configs, torch):
+    """Untimed replay of every configuration (same ticks, same forced
+    rebuild): the per-query result sizes and pair-set hashes of every timed
+    tick must be identical across configurations."""
+    W, K = args.warmup, args.steps
+    ref = None
+    same = {}
+    for label, th, learned in configs:
+        run = Run(args, wl, nq, th, torch, learned)
+        sc = run.scene
+        prep = [sc.prepare_tick(*tick_tensors(b, m, q, torch)) for b, m, q in ticks[:W + K]]
+        hs = []
+        for i in range(W + K):
+            if i == W:
+                sc.build_index()
+            run.tick(prep[i], *ticks[i])
+            if i >= W:
+                cnt, h = sc.hashes()
+                hs.append((cnt.clone(), h.clone()))
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = hs
+            same[label] = True
+        else:
+            same[label] = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+                              for a, b in zip(ref, hs))
+        run.close()
+        del prep
+    return same
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, target_s: float):
+    """The oracle timed on the host on tick 0 of the workload: its uniform
+    grid (every query answered; timed on a sample of the queries and
+    extrapolated to the whole tick: grid build + per-query time x queries)
+    and its brute force (sampled queries against all objects), each on all
+    host cores and on one core."""
     import oracle
     t = next(wl.ticks())
     st = oracle.State(wl.n)
@@ -130,74 +305,65 @@ def cpu_baseline(wl, target_s: float):
     live = oracle.live_queries(wl.n, t.qid)
     rng = np.random.default_rng(123)
     order = rng.permutation(t.nq)
-    n = min(256, t.nq)
-    t0 = time.perf_counter()
-    cnt = oracle.brute_counts(st, live[order[:n]], tuple(r[order[:n]] for r in t.rects))
-    dt = time.perf_counter() - t0
-    if dt < target_s and n < t.nq:
-        n2 = int(min(t.nq, max(n, n * target_s / max(dt, 1e-6))))
-        sel = order[:n2]
+    all_threads = oracle.num_threads()
+    budget = target_s / 4.0  # per variant
+
+    def sel(n):
+        s = np.sort(np.union1d(order[:n], [big]))
+        return s, tuple(r[s] for r in t.rects)
+
+    # the grid's cell side follows the largest query: its build is timed
+    # with that query alone
+    big = int(np.argmax(np.maximum(t.xb - t.xa, t.yb - t.ya)))
+
+    def grid(threads):
+        oracle.set_num_threads(threads)
+        one = np.array([big])
         t0 = time.perf_counter()
-        cnt = oracle.brute_counts(st, live[sel], tuple(r[sel] for r in t.rects))
-        dt = time.perf_counter() - t0
-        n = n2
-    pairs = int(cnt.sum())
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"brute force (Definition 1), tick 0, {n} of {t.nq} queries sampled "
-                      f"uniformly against all {wl.n} objects; {pairs} pairs in {dt:.2f} s; "
-                      f"{n / dt:.1f} queries/s"}
-
-
-MODEL = os.path.join(ROOT, "paper_1411_3212_amd", "data", "cost_model.json")
-
-
-def learned_run(args, wl, ticks, nq, cfg, c_fixed, lat_fixed, wall_fixed, torch) -> dict:
-    """The timed ticks again on a scene whose builds choose their threshold
-    with the learned cost model (same loop, same launch mode)."""
-    from paper_1411_3212_amd import costmodel
-    from paper_1411_3212_amd.binding import Scene
-    model = costmodel.load(MODEL)
-    kw = {k: v for k, v in cfg.items() if k != "th"}
-    sc = Scene(wl.n, nq, th=args.th, th_min=min(model["cand"]), thresh_mlp=True, **kw)
-    costmodel.install(sc, model, torch)
-    counters = np.zeros((args.warmup + args.steps, 8), dtype=np.int64)
-    lat = []
-    prep = [sc.prepare_tick(*tick_tensors(buf, m, q, torch)) for buf, m, q in ticks]
-    for i in range(args.warmup + args.steps):
-        if i == args.warmup:
-            torch.cuda.synchronize()
+        oracle.grid_hash(st, t.qid[one], live[one], tuple(r[one] for r in t.rects))
+        t_build = time.perf_counter() - t0
+        n = min(t.nq, 2048)
+        while True:
+            s, r = sel(n)
             t0 = time.perf_counter()
-        buf, m, q = ticks[i]
-        h0 = time.perf_counter()
-        if args.mode == "graph":
-            sc.tick_graph(prep[i])
-        else:
-            d = views(buf, m, q, torch)
-            sc.apply_updates(d["ids"], d["x"], d["y"])
-            sc.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
-        counters[i] = sc.fetch().counters()
-        if i >= args.warmup:
-            lat.append((time.perf_counter() - h0) * 1e3)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    c = counters[args.warmup:]
-    info = sc.tune_info()
-    K = args.steps
-    pairs = int(c[:, 0].sum())
-    learned = dict(ticks_per_s=K / wall, ms_per_step=wall * 1e3 / K, pairs_per_s=pairs / wall,
-                   p50_tick_ms=float(np.percentile(lat, 50)),
-                   p99_tick_ms=float(np.percentile(lat, 99)), th_last=sc.stats()["th"],
-                   tunings=info["n_tunes"], chosen=info["chosen"],
-                   predicted_cost=dict(zip(map(str, info["cand"]), info["cost"])))
-    fixed = dict(ticks_per_s=K / wall_fixed, ms_per_step=wall_fixed * 1e3 / K,
-                 p50_tick_ms=float(np.percentile(lat_fixed, 50)),
-                 p99_tick_ms=float(np.percentile(lat_fixed, 99)), th=args.th)
-    return dict(fixed=fixed, learned=learned,
-                speedup=learned["ticks_per_s"] / fixed["ticks_per_s"],
-                p99_ratio=learned["p99_tick_ms"] / fixed["p99_tick_ms"],
-                same_pairs_every_tick=bool(np.array_equal(c[:, 0], c_fixed[:, 0])),
-                model="paper_1411_3212_amd/data/cost_model.json")
+            cnt, _ = oracle.grid_hash(st, t.qid[s], live[s], r)
+            dt = time.perf_counter() - t0
+            if dt >= 0.25 * budget or n == t.nq:
+                break
+            n = int(min(t.nq, n * max(2.0, 0.5 * budget / max(dt, 1e-3))))
+        per_q = max(dt - t_build, 0.0) / n
+        tick_s = t_build + per_q * t.nq
+        pairs = float(cnt.sum()) * t.nq / n
+        return dict(pairs_per_s=pairs / tick_s, threads=threads, tick_s_extrapolated=tick_s,
+                    build_s=t_build, queries_sampled=int(n), queries=int(t.nq))
+
+    def brute(threads):
+        oracle.set_num_threads(threads)
+        n = 8
+        while True:
+            s, r = sel(n)
+            t0 = time.perf_counter()
+            cnt = oracle.brute_counts(st, live[s], r)
+            dt = time.perf_counter() - t0
+            if dt >= 0.25 * budget or n == t.nq:
+                break
+            n = int(min(t.nq, n * max(2.0, 0.5 * budget / max(dt, 1e-3))))
+        return dict(pairs_per_s=float(cnt.sum()) / dt, threads=threads,
+                    queries_per_s=n / dt, queries_sampled=int(n), seconds=dt)
+
+    try:
+        g_all, g_one = grid(all_threads), grid(1)
+        b_all, b_one = brute(all_threads), brute(1)
+    finally:
+        oracle.set_num_threads(all_threads)
+    return {"value": g_all["pairs_per_s"], "unit": "pairs/s", "cores": all_threads,
+            "kind": "oracle",
+            "sample": f"uniform-grid oracle on tick 0 ({wl.n} objects, {t.nq} queries): grid "
+                      f"build {g_all['build_s']:.2f} s + {g_all['queries_sampled']} sampled "
+                      f"queries, extrapolated to all {t.nq} queries; {all_threads} threads",
+            "cpu_model": cpu_model(),
+            "variants": {"grid_all_cores": g_all, "grid_1_core": g_one,
+                         "brute_all_cores": b_all, "brute_1_core": b_one}}
 
 
 def main():
@@ -207,113 +373,113 @@ def main():
                                    "GPUs is a design note, not implemented)"}))
         return 2
     import torch
-    from paper_1411_3212_amd.binding import PHASES, Scene
 
-    n_extra = 5  # eager ticks after the timed region, for the per-phase breakdown
-    n_ticks = args.warmup + args.steps + n_extra
-    wl = workloads.make(args.workload, n_ticks=n_ticks)
+    W, K = args.warmup, args.steps
+    n_extra = 3  # eager ticks after the timed region, for the per-phase breakdown
+    wl = workloads.make(args.workload, n_ticks=W + K + n_extra)
     t_gen = time.perf_counter()
     ticks = upload_ticks(wl, torch)
     t_gen = time.perf_counter() - t_gen
     nq = max(q for _, _, q in ticks)
-    cfg = scene_config(wl, args.th, args.covering == "on", args.reorder == "on")
-    scene = Scene(wl.n, nq, profile=True, **cfg)
-    # each tick's inputs are checked and marshalled once, before the timing
-    prep = [scene.prepare_tick(*tick_tensors(buf, m, q, torch)) for buf, m, q in ticks]
-    counters = np.zeros((n_ticks, 8), dtype=np.int64)
-    phase_sum = {k: 0.0 for k in PHASES}
-    lat = []
-    start_ev = torch.cuda.Event(enable_timing=True)
-    end_ev = torch.cuda.Event(enable_timing=True)
 
-    def one_tick(i, timed, mode=args.mode, phases=phase_sum):
-        buf, m, q = ticks[i]
-        h0 = time.perf_counter()
-        if mode == "graph":
-            scene.tick_graph(prep[i])
-        else:
-            d = views(buf, m, q, torch)
-            scene.apply_updates(d["ids"], d["x"], d["y"])
-            scene.run_tick(d["qid"], d["xa"], d["ya"], d["xb"], d["yb"])
-        # synchronises: the tick's results and counters are available
-        counters[i] = scene.fetch().counters()
-        h1 = time.perf_counter()
-        if timed:
-            lat.append((h1 - h0) * 1e3)
-        if phases is not None:
-            ph = scene.phase_times()
-            for k in PHASES:
-                phases[k] += ph[k]
+    learned = args.threshold == "learned"
+    configs = [("learned", None, True)] if learned else \
+        [(f"fixed {int(args.threshold)}", int(args.threshold), False)]
+    for th in [int(v) for v in args.compare.split(",") if v.strip()]:
+        if learned or th != int(args.threshold):
+            configs.append((f"fixed {th}", th, False))
 
-    for i in range(args.warmup):
-        one_tick(i, False, phases=None)
-    torch.cuda.synchronize()
-    start_ev.record()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + args.steps):
-        one_tick(i, True)
-    end_ev.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dev_ms = start_ev.elapsed_time(end_ev)
-    eager_phase = {k: 0.0 for k in PHASES}
-    for i in range(args.warmup + args.steps, n_ticks):
-        one_tick(i, False, mode="eager", phases=eager_phase)
-    c = counters[args.warmup:args.warmup + args.steps]
-    assert (c[:, 7] == 0).all(), f"device error bits {np.unique(c[:, 7])}"
-    pairs = int(c[:, 0].sum())
-    K = args.steps
-    st = scene.stats()
+    runs = {}
+    head = None
+    for label, th, lrn in configs:
+        run = Run(args, wl, nq, th, torch, lrn).timed(ticks, W, K)
+        if head is None:
+            head = run
+            phases = run.phase_sample(ticks, W + K, n_extra)
+            tune_ms, tune_info = run.tuning_ms(ticks, W) if lrn else (0.0, None)
+        runs[label] = run
+        if run is not head:
+            run.close()
 
-    # dominant single-kernel phase of the join and its roofline
-    avg = {k: phase_sum[k] / K for k in PHASES}
-    per_tick = {
-        "n_isect": float(c[:, 3].mean()), "n_isect_ids": float(c[:, 1].mean()),
-        "n_tasks": float(c[:, 6].mean()), "tests": float(c[:, 5].mean()),
-    }
-    ab = algorithmic_bytes(per_tick, st["n_present"], nq)
-    dom = max(("join_count", "join_write"), key=lambda k: avg[k])
-    achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
+    # headline: the first configuration, tuning amortised over the ticks
+    # between two tunings (tune_every builds, one per rebuild period)
+    period, tune_every = 32, 8
+    amort = tune_ms / (period * tune_every) if learned else 0.0
+    hs = head.summary(amort)
+    c = head.counters
+    per_tick = {"n_isect": float(c[:, 3].mean()), "n_isect_ids": float(c[:, 1].mean()),
+                "n_cov": float(c[:, 4].mean()), "n_tasks": float(c[:, 6].mean()),
+                "tests": float(c[:, 5].mean()), "pairs": float(c[:, 0].mean())}
+    ab = algorithmic_bytes(per_tick, head.n_present)
+    avg_join = float(head.join_ms.mean())
+    achieved = ab["join_write"] / (avg_join * 1e-3) / 1e9
     from paper_1411_3212_amd.profiling import load_traffic
-    tr = load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_1m_k_{dom}_traffic.txt")
-                      if args.workload == "hotspot" else os.devnull)
+    tr = load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_k_join_write_traffic.txt"))
     out = {
         "metric": "result pairs/s",
-        "value": pairs / wall,
+        "value": hs["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / K,
+        "warmup": W,
+        "ms_per_step": hs["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
-                   "objects": wl.n, "queries_per_tick": nq, "ticks": K, "th_quad": args.th,
+                   "objects": wl.n, "queries_per_tick": nq, "ticks": K,
+                   "threshold": "learned (cost model; tuning amortised)" if learned
+                   else int(args.threshold),
                    "covering": args.covering == "on", "reorder": args.reorder == "on",
-                   "rebuild": "auto/32",
+                   "rebuild": "auto, period 32, forced on the first timed tick",
                    "launch": args.mode},
-        "ticks_per_s": K / wall,
-        "p50_tick_ms": float(np.percentile(lat, 50)),
-        "p99_tick_ms": float(np.percentile(lat, 99)),
-        "device_ms_per_tick": dev_ms / K,
-        "pairs_per_tick": pairs / K,
-        "queries_per_s": nq * K / wall,
-        "phase_ms": {k: round(v, 4) for k, v in avg.items()},
-        "phase_ms_eager_sample": {k: round(v / n_extra, 4) for k, v in eager_phase.items()},
+        "ticks_per_s": hs["ticks_per_s"],
+        "p50_tick_ms": hs["p50_tick_ms"],
+        "p99_tick_ms": hs["p99_tick_ms"],
+        "rebuild_tick_ms": hs["rebuild_tick_ms"],
+        "keep_tick_p50_ms": hs["keep_tick_p50_ms"],
+        "keep_tick_p99_ms": hs["keep_tick_p99_ms"],
+        "pairs_per_tick": per_tick["pairs"],
+        "queries_per_s": nq * hs["ticks_per_s"],
+        "threshold_used": head.th_last,
+        "phase_ms_eager_sample": phases,
         "counters_per_tick": per_tick,
-        "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "k_join_write", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": tr["bytes"] if tr else None,
-                     "algorithmic_bytes_per_launch": ab[dom],
-                     "avg_launch_ms": avg[dom]},
+                     "algorithmic_bytes_per_launch": ab["join_write"],
+                     "avg_launch_ms": avg_join},
         "input_generation_s": t_gen,
     }
-    if not args.no_learned and os.path.exists(MODEL):
-        out["learned_vs_fixed"] = learned_run(args, wl, ticks, nq, cfg, c, lat, wall,
-                                              torch)
+    if learned:
+        out["tuning"] = {"tuned_tick_extra_ms": tune_ms, "amortised_ms_per_tick": amort,
+                         "ticks_between_tunings": period * tune_every,
+                         "chosen": tune_info["chosen"],
+                         "predicted_cost": dict(zip(map(str, tune_info["cand"]),
+                                                    tune_info["cost"]))}
+    cmp = {}
+    for label, run in runs.items():
+        s = run.summary(amort if run is head else 0.0)
+        cmp[label] = {k: s[k] for k in ("ticks_per_s", "ms_per_step", "p50_tick_ms",
+                                        "p99_tick_ms", "rebuild_tick_ms", "keep_tick_p99_ms",
+                                        "th")}
+        cmp[label]["join_write_ms"] = float(run.join_ms.mean())
+    head.close()
+    del runs
+    if len(cmp) > 1:
+        out["learned_vs_fixed" if learned else "vs_fixed"] = {
+            "runs": cmp,
+            "speedup": {k: cmp[configs[0][0]]["ticks_per_s"] / v["ticks_per_s"]
+                        for k, v in cmp.items() if k != configs[0][0]},
+            "p99_ratio": {k: cmp[configs[0][0]]["p99_tick_ms"] / v["p99_tick_ms"]
+                          for k, v in cmp.items() if k != configs[0][0]},
+        }
+    if not args.no_verify and len(configs) > 1:
+        same = verify(args, wl, ticks, nq, configs, torch)
+        out.setdefault("learned_vs_fixed" if learned else "vs_fixed", {})[
+            "identical_per_query_hashes"] = same
     if args.copy_probe:
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -321,6 +487,7 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * a.numel()
+    del ticks
     if not args.no_cpu_baseline:
         small = workloads.make(args.workload, n_ticks=1)
         out["cpu_baseline"] = cpu_baseline(small, args.cpu_seconds)

@@ -74,10 +74,28 @@ enum sj_flags {
   SJ_TIMING_LOG = 1u << 3, /* per-leaf join timing log (sj_timing_log) */
   SJ_THRESH_MLP = 1u << 4, /* builds pick their threshold with the cost
                               model installed by sj_set_cost_model */
-  SJ_SCHEDULE_MLP = 1u << 5 /* with SJ_REORDER and a cost model installed:
+  SJ_SCHEDULE_MLP = 1u << 5, /* with SJ_REORDER and a cost model installed:
                               join tasks run in the order of the model's
                               predicted task time instead of the weight
                               |Q_I^c| x |P^c| (learned schedule) */
+  SJ_UNIFORM_GRID = 1u << 6, /* the UG method's index instead of the
+                              quadtree (Definition "MBR partitioning into a
+                              uniform grid"): the frame cut into grid_split
+                              columns and rows along its finest cells, cells
+                              numbered by Morton code, materialised on every
+                              tick; same query split and join.  Not with
+                              SJ_THRESH_MLP, SJ_SCHEDULE_MLP or
+                              SJ_TIMING_LOG. */
+  SJ_ATOMIC_RESULTS = 1u << 7, /* the paper's baseline filter (UG_Baseline,
+                              Algorithm SQB) in place of the lock-free count,
+                              scan and write: intersecting results are
+                              appended as (query, object) pairs through an
+                              LDS buffer and a global atomic counter, in no
+                              particular order (sj_results.d_pairs).  An
+                              ablation; results are the same sets. */
+  SJ_CU_COUNTERS = 1u << 8   /* containment tests per compute unit of the
+                              filtering pass (sj_cu_counters; the S3
+                              imbalance study) */
 };
 
 /* Quadtree reuse across ticks (the paper builds the partitioning on the
@@ -117,27 +135,41 @@ typedef struct sj_config {
                                    queries with more are walked twice (0: 32) */
   uint32_t tune_every;          /* SJ_THRESH_MLP: host-decided builds between
                                    two tunings; the first build is tuned (0: 8) */
+  uint32_t grid_split;          /* SJ_UNIFORM_GRID: columns (= rows) of the
+                                   grid, the paper's split factor, 1..4096 */
 } sj_config;
 
 /* Compressed results of the last tick (Sections "Bitmap decoding" and
- * "Optimizations"): for query k (input order of the tick),
- *   intersecting part: d_isect_id[d_isect_off[k] .. d_isect_off[k+1])
+ * "Optimizations").  The result of query k (input order of the tick) is a
+ * list of runs of object ids:
+ *   intersecting part, one run per intersecting subquery (the decoded
+ *     bitmap of the query against one leaf): for every slot s in
+ *     [d_isect_slot_off[k], d_isect_slot_off[k+1]), run r = d_slot_run[s]
+ *     is d_isect_id[d_run_off[r] .. d_run_off[r+1]);
  *   covering part: for every c in [d_cov_off[k], d_cov_off[k+1]), leaf
  *     L = d_cov_leaf[c] contributes all objects
  *     d_sorted_id[d_leaf_beg[L] .. d_leaf_beg[L+1]).
- * Order inside a query is unspecified (leaves in Morton order, ids in leaf
- * order); lists of distinct leaves are disjoint, so the result set is their
- * concatenation.  A query superseded by a later query of the same object in
- * the tick, or one rejected as invalid, has an empty result.  Pointers are
- * device views into the workspace, valid until the next call on the scene. */
+ * Runs are stored in the join's order (the runs of one leaf's subqueries
+ * side by side), not by query.  Order inside a query is unspecified
+ * (intersecting runs in the order of the query's split, then covering
+ * leaves in that order; ids inside a run in d_sorted_id order); lists of
+ * distinct leaves are disjoint, so the result set is their concatenation
+ * (sj_expand_results gives per-query lists, with SJ_SORTED in the canonical
+ * ascending order).  A query superseded by a later query of the same object
+ * in the tick, or one rejected as invalid, has an empty result.  Pointers
+ * are device views into the workspace, valid until the next call on the
+ * scene. */
 typedef struct sj_results {
   uint32_t nq;
   uint32_t n_leaves;
-  uint64_t n_isect_ids;       /* = d_isect_off[nq] */
+  uint64_t n_isect_ids;       /* = d_run_off[n_runs] */
   uint64_t n_cov_entries;     /* = d_cov_off[nq] */
   uint64_t total_pairs;       /* sum over queries of |res(q)| */
-  const uint64_t *d_isect_off; /* [nq + 1] */
-  const uint32_t *d_isect_id;
+  uint64_t n_runs;            /* intersecting subqueries = d_isect_slot_off[nq] */
+  const uint32_t *d_isect_slot_off; /* [nq + 1] */
+  const uint32_t *d_slot_run;  /* [n_runs] */
+  const uint64_t *d_run_off;   /* [n_runs + 1] */
+  const uint32_t *d_isect_id;  /* [n_isect_ids] */
   const uint32_t *d_cov_off;   /* [nq + 1] */
   const uint32_t *d_cov_leaf;
   const uint32_t *d_leaf_beg;  /* [n_leaves + 1] */
@@ -151,6 +183,11 @@ typedef struct sj_results {
   uint64_t tests;             /* containment tests of the filtering */
   uint32_t error_bits;        /* SJ_ERR_* bits of the tick */
   uint32_t reserved;
+  /* SJ_ATOMIC_RESULTS: the intersecting results are these pairs instead of
+   * runs (n_runs is 0): d_pairs[2 i] = query index k, d_pairs[2 i + 1] =
+   * object id, for i < n_pairs, in no particular order. */
+  uint64_t n_pairs;
+  const uint32_t *d_pairs;
 } sj_results;
 
 /* Counters of the last tick (read back by sj_stats, which synchronises). */
@@ -241,13 +278,22 @@ int sj_tick_graph(sj_scene *scene, const uint32_t *d_id, const float *d_x, const
  * the last tick, or the latched error of the tick. */
 int sj_fetch_results(sj_scene *scene, sj_results *out);
 
-/* Expanded results: per-query CSR, covering leaves expanded.  With
- * d_ids == NULL only *n_pairs is set (the size the caller must provide).
- * Otherwise writes d_off[nq + 1] and d_ids[total_pairs] (ids of query k in
- * d_ids[d_off[k] .. d_off[k+1]), unspecified order) if ids_cap suffices,
- * else returns SJ_EINVAL.  Synchronises. */
-int sj_expand_results(sj_scene *scene, uint64_t *d_off, uint32_t *d_ids,
-                      uint64_t ids_cap, uint64_t *n_pairs);
+/* Expanded results (Section "Bitmap decoding": the per-query lists the
+ * paper's decoding produces, with the covering leaves of Section
+ * "Optimizations" expanded): per-query CSR of the last tick.
+ *   d_sel == NULL: every query of the tick, in input order (n_sel ignored).
+ *   d_sel != NULL: the n_sel query indices d_sel[0 .. n_sel) (device, each
+ *     < nq; repeats allowed; n_sel <= capacity_queries), in that order.
+ * List i is d_ids[d_off[i] .. d_off[i+1]) (d_off: n + 1 u64, device).  Ids
+ * in a list are unordered unless flags has SJ_SORTED (ascending ids, the
+ * canonical order).  Two-call protocol: with d_ids == NULL only *n_pairs is
+ * set (the number of ids to provide room for; with a selection d_off is
+ * written too).  Otherwise the lists are written if ids_cap suffices, else
+ * SJ_EINVAL.  SJ_EINVAL also for an index >= nq, a misaligned pointer, or
+ * unknown flags.  Synchronises. */
+#define SJ_SORTED 1u
+int sj_expand_results(sj_scene *scene, const uint32_t *d_sel, uint32_t n_sel, uint32_t flags,
+                      uint64_t *d_off, uint32_t *d_ids, uint64_t ids_cap, uint64_t *n_pairs);
 
 /* Per-query result size and order-independent pair-set hash
  * H(q) = sum over id in res(q) of mix64((qid << 32) | id) mod 2^64, mix64
@@ -262,6 +308,14 @@ int sj_result_hashes(sj_scene *scene, uint64_t *d_count, uint64_t *d_hash);
  * [7] latched error bits.  Lets a caller collect per-tick totals without
  * synchronising. */
 int sj_tick_counters(sj_scene *scene, uint64_t *d_out);
+
+/* SJ_CU_COUNTERS: containment tests of the last tick's filtering pass per
+ * compute-unit slot, copied to out[0 .. n) (host memory, n <= 4096).  Slot
+ * = XCC id << 8 | shader engine << 5 | shader array << 4 | CU id, from the
+ * waves' hardware id registers; unused slots stay 0.  Synchronises.  The
+ * paper's SM imbalance (Experimental evaluation, S3) is the relative
+ * difference between the largest and the smallest count of the CUs. */
+int sj_cu_counters(sj_scene *scene, uint64_t *out, uint32_t n);
 
 /* Counters of the last tick; synchronises; returns the latched error. */
 int sj_stats(sj_scene *scene, sj_tick_stats *out);

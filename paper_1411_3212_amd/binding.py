@@ -19,6 +19,9 @@ LIB_PATH = Path(__file__).resolve().parent / "libsj.so"
 SJ_OK, SJ_EINVAL, SJ_ENOSPACE, SJ_EOVERFLOW, SJ_EDATA, SJ_EDEVICE, SJ_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SJ_COVERING, SJ_REORDER, SJ_PROFILE, SJ_TIMING_LOG, SJ_THRESH_MLP, SJ_SCHEDULE_MLP = \
     1, 2, 4, 8, 16, 32
+SJ_UNIFORM_GRID, SJ_ATOMIC_RESULTS, SJ_CU_COUNTERS = 64, 128, 256
+CU_SLOTS = 4096
+SJ_SORTED = 1  # sj_expand_results: ascending ids per list
 COST_TERMS = 6  # SJ_COST_TERMS
 REBUILD = {"auto": 0, "always": 1, "never": 2}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
@@ -38,17 +41,19 @@ class SjConfig(Structure):
                 ("capacity_subqueries", c_uint64), ("capacity_covering", c_uint64),
                 ("capacity_results", c_uint64), ("th_quad", c_uint32), ("th_min", c_uint32),
                 ("l_max", c_uint32), ("flags", c_uint32), ("rebuild_policy", c_uint32),
-                ("rebuild_period", c_uint32), ("split_slots", c_uint32), ("tune_every", c_uint32)]
+                ("rebuild_period", c_uint32), ("split_slots", c_uint32), ("tune_every", c_uint32),
+                ("grid_split", c_uint32)]
 
 
 class SjResults(Structure):
     _fields_ = [("nq", c_uint32), ("n_leaves", c_uint32), ("n_isect_ids", c_uint64),
-                ("n_cov_entries", c_uint64), ("total_pairs", c_uint64),
-                ("d_isect_off", c_void_p), ("d_isect_id", c_void_p), ("d_cov_off", c_void_p),
+                ("n_cov_entries", c_uint64), ("total_pairs", c_uint64), ("n_runs", c_uint64),
+                ("d_isect_slot_off", c_void_p), ("d_slot_run", c_void_p), ("d_run_off", c_void_p),
+                ("d_isect_id", c_void_p), ("d_cov_off", c_void_p),
                 ("d_cov_leaf", c_void_p), ("d_leaf_beg", c_void_p), ("d_sorted_id", c_void_p),
                 ("n_present", c_uint32), ("n_tasks", c_uint32), ("n_subqueries", c_uint64),
                 ("cov_pairs", c_uint64), ("tests", c_uint64), ("error_bits", c_uint32),
-                ("reserved", c_uint32)]
+                ("reserved", c_uint32), ("n_pairs", c_uint64), ("d_pairs", c_void_p)]
 
 
 class SjTickStats(Structure):
@@ -99,7 +104,8 @@ EXPORTS = {
     "sj_tick_graph": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_uint32]),
     "sj_fetch_results": (c_int, [c_void_p, POINTER(SjResults)]),
-    "sj_expand_results": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64, POINTER(c_uint64)]),
+    "sj_expand_results": (c_int, [c_void_p, c_void_p, c_uint32, c_uint32, c_void_p, c_void_p,
+                                  c_uint64, POINTER(c_uint64)]),
     "sj_result_hashes": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sj_tick_counters": (c_int, [c_void_p, c_void_p]),
     "sj_stats": (c_int, [c_void_p, POINTER(SjTickStats)]),
@@ -110,6 +116,7 @@ EXPORTS = {
                                   c_uint32]),
     "sj_tune_info_get": (c_int, [c_void_p, POINTER(SjTuneInfo)]),
     "sj_last_error": (c_char_p, [c_void_p]),
+    "sj_cu_counters": (c_int, [c_void_p, c_void_p, c_uint32]),
     "sj_server_scene_bytes": (c_size_t, [POINTER(SjConfig), c_uint32]),
     "sj_server_create": (c_int, [c_void_p, c_size_t, c_uint32, POINTER(c_void_p)]),
     "sj_server_destroy": (c_int, [c_void_p]),
@@ -169,13 +176,19 @@ def make_config(capacity_objects: int, capacity_queries: int, *, th: int = 64, t
                 rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                 capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
                 profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
-                schedule_mlp: bool = False, tune_every: int = 0) -> SjConfig:
+                schedule_mlp: bool = False, tune_every: int = 0, grid_split: int = 0,
+                atomic_results: bool = False, cu_counters: bool = False) -> SjConfig:
+    """grid_split > 0 selects the uniform-grid index with that split factor;
+    atomic_results the baseline filter (appended pairs); cu_counters the
+    per-CU test counters."""
     flags = (SJ_COVERING if covering else 0) | (SJ_REORDER if reorder else 0) | \
             (SJ_PROFILE if profile else 0) | (SJ_TIMING_LOG if timing_log else 0) | \
-            (SJ_THRESH_MLP if thresh_mlp else 0) | (SJ_SCHEDULE_MLP if schedule_mlp else 0)
+            (SJ_THRESH_MLP if thresh_mlp else 0) | (SJ_SCHEDULE_MLP if schedule_mlp else 0) | \
+            (SJ_UNIFORM_GRID if grid_split else 0) | \
+            (SJ_ATOMIC_RESULTS if atomic_results else 0) | (SJ_CU_COUNTERS if cu_counters else 0)
     return SjConfig(capacity_objects, capacity_queries, capacity_subqueries, capacity_covering,
                     capacity_results, th, th_min, l_max, flags, REBUILD[rebuild], rebuild_period,
-                    split_slots, tune_every)
+                    split_slots, tune_every, grid_split)
 
 
 def _ptr(t):
@@ -187,12 +200,15 @@ class Results:
     on first access, so a fetch for the counters builds no tensor)."""
 
     _VIEWS = {  # attribute: (pointer field, length, dtype name)
-        "isect_off": ("d_isect_off", lambda r: r.nq + 1, "int64"),
+        "isect_slot_off": ("d_isect_slot_off", lambda r: r.nq + 1, "int32"),
+        "slot_run": ("d_slot_run", lambda r: r.n_runs, "int32"),
+        "run_off": ("d_run_off", lambda r: r.n_runs + 1, "int64"),
         "isect_id": ("d_isect_id", lambda r: r.n_isect_ids, "int32"),
         "cov_off": ("d_cov_off", lambda r: r.nq + 1, "int32"),
         "cov_leaf": ("d_cov_leaf", lambda r: r.n_cov_entries, "int32"),
         "leaf_beg": ("d_leaf_beg", lambda r: r.n_leaves + 1, "int32"),
         "sorted_id": ("d_sorted_id", lambda r: r.n_present if r.n_leaves else 0, "int32"),
+        "pairs": ("d_pairs", lambda r: 2 * r.n_pairs, "int32"),
     }
 
     def __getattr__(self, name):
@@ -212,6 +228,8 @@ class Results:
         self.n_leaves = int(r.n_leaves)
         self.n_isect_ids = int(r.n_isect_ids)
         self.n_cov_entries = int(r.n_cov_entries)
+        self.n_runs = int(r.n_runs)
+        self.n_pairs = int(r.n_pairs)
         self.total_pairs = int(r.total_pairs)
         self.n_present = int(r.n_present)
         self.n_tasks = int(r.n_tasks)
@@ -225,22 +243,14 @@ class Results:
         return [self.total_pairs, self.n_isect_ids, self.cov_pairs, self.n_subqueries,
                 self.n_cov_entries, self.tests, self.n_tasks, self.error_bits]
 
-    def to_lists(self):
-        """Per-query result lists (ascending ids), computed on the host from
-        the compressed form (for tests and small cases)."""
-        io = self.isect_off.cpu().numpy()
-        ii = self.isect_id.cpu().numpy().view(np.uint32)
-        co = self.cov_off.cpu().numpy().view(np.uint32)
-        cl = self.cov_leaf.cpu().numpy().view(np.uint32)
-        lb = self.leaf_beg.cpu().numpy().view(np.uint32)
-        sid = self.sorted_id.cpu().numpy().view(np.uint32)
-        out = []
-        for k in range(self.nq):
-            parts = [ii[io[k]:io[k + 1]]]
-            for c in cl[co[k]:co[k + 1]]:
-                parts.append(sid[lb[c]:lb[c + 1]])
-            out.append(np.sort(np.concatenate(parts)).tolist() if parts else [])
-        return out
+    def to_lists(self, sel=None):
+        """Per-query result lists in the canonical order (ascending ids),
+        expanded and sorted on the device (sj_expand_results with SJ_SORTED);
+        sel: optional query indices (all queries of the tick by default)."""
+        off, ids = self._scene.expand(sel=sel, sorted=True)
+        off = off.cpu().numpy()
+        ids = ids.cpu().numpy().view(np.uint32)
+        return [ids[off[i]:off[i + 1]].tolist() for i in range(len(off) - 1)]
 
 
 class TickArgs:
@@ -264,7 +274,9 @@ class Scene:
                  rebuild: str = "auto", rebuild_period: int = 32, capacity_subqueries: int = 0,
                  capacity_covering: int = 0, capacity_results: int = 0, split_slots: int = 0,
                  profile: bool = False, timing_log: bool = False, thresh_mlp: bool = False,
-                 schedule_mlp: bool = False, tune_every: int = 0, device=None, stream=None):
+                 schedule_mlp: bool = False, tune_every: int = 0, grid_split: int = 0,
+                 atomic_results: bool = False, cu_counters: bool = False, device=None,
+                 stream=None):
         import torch
         self._lib = load()
         self.device = torch.device(device if device is not None else "cuda")
@@ -275,7 +287,9 @@ class Scene:
                                capacity_covering=capacity_covering,
                                capacity_results=capacity_results, split_slots=split_slots,
                                profile=profile, timing_log=timing_log, thresh_mlp=thresh_mlp,
-                               schedule_mlp=schedule_mlp, tune_every=tune_every)
+                               schedule_mlp=schedule_mlp, tune_every=tune_every,
+                               grid_split=grid_split, atomic_results=atomic_results,
+                               cu_counters=cu_counters)
         nbytes = int(self._lib.sj_workspace_bytes(byref(self.cfg)))
         if nbytes == 0:
             raise SjError(SJ_EINVAL, "invalid configuration")
@@ -381,18 +395,41 @@ class Scene:
         _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
         return Results(self, r)
 
-    def expand(self):
-        """(off[nq+1] int64, ids int32) with covering leaves expanded."""
+    def expand(self, sel=None, sorted: bool = False):
+        """(off[n+1] int64, ids int32): per-query lists with covering leaves
+        expanded, for every query of the tick or the query indices sel (a
+        sequence or an int32 tensor); ascending ids per list if sorted."""
         import torch
+        flags = SJ_SORTED if sorted else 0
         n = c_uint64()
-        _check(self._lib.sj_expand_results(self.handle, None, None, 0, byref(n)), self.handle)
-        r = SjResults()
-        _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
-        off = torch.empty(int(r.nq) + 1, dtype=torch.int64, device=self.device)
+        if sel is None:
+            _check(self._lib.sj_expand_results(self.handle, None, 0, flags, None, None, 0,
+                                               byref(n)), self.handle)
+            r = SjResults()
+            _check(self._lib.sj_fetch_results(self.handle, byref(r)), self.handle)
+            nsel, dsel = int(r.nq), None
+        else:
+            if not isinstance(sel, torch.Tensor):
+                sel = torch.from_numpy(np.ascontiguousarray(sel, dtype=np.uint32).view(np.int32))
+            dsel = self._dev(sel.to(self.device).contiguous(), torch.int32)
+            nsel = int(dsel.numel())
+        off = torch.empty(nsel + 1, dtype=torch.int64, device=self.device)
+        if dsel is not None:
+            _check(self._lib.sj_expand_results(self.handle, _ptr(dsel), nsel, flags, _ptr(off),
+                                               None, 0, byref(n)), self.handle)
         ids = torch.empty(max(int(n.value), 1), dtype=torch.int32, device=self.device)
-        _check(self._lib.sj_expand_results(self.handle, _ptr(off), _ptr(ids), ids.numel(),
+        _check(self._lib.sj_expand_results(self.handle, _ptr(dsel) if dsel is not None else None,
+                                           nsel, flags, _ptr(off), _ptr(ids), ids.numel(),
                                            byref(n)), self.handle)
         return off, ids[:int(n.value)]
+
+    def cu_counters(self) -> np.ndarray:
+        """Containment tests of the last tick's filtering per CU slot
+        (SJ_CU_COUNTERS), uint64[CU_SLOTS]."""
+        out = np.zeros(CU_SLOTS, np.uint64)
+        _check(self._lib.sj_cu_counters(self.handle, out.ctypes.data_as(c_void_p), CU_SLOTS),
+               self.handle)
+        return out
 
     def hashes(self):
         """Per-query (count, pair-set hash) as int64 tensors (hash bits are

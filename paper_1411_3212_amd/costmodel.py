@@ -364,6 +364,51 @@ def compare(name: str, n_ticks: int, warm: int, torch, model: dict, th_fixed: in
     return out
 
 
+def mix(torch, model: dict, fixed=(64, 128, 256, 384), n_ticks: int = 6, warm: int = 2,
+        n_scenes: int = 16, log=print) -> dict:
+    """The serving mix's scenes (16 scenes of 1e5-8e6 objects, hotspot and
+    segment workloads) each run alone on the same ticks with every fixed
+    threshold and with the learned one: the total time of all scenes' ticks
+    per configuration, identical per-query results required.  One fixed
+    threshold has to serve every scene; the learned one is chosen per scene."""
+    specs = serving.make_specs(n_scenes)
+    tot = {f"fixed {t}": 0.0 for t in fixed}
+    tot["learned"] = 0.0
+    per_scene, same = [], True
+    for sp in specs:
+        sp.wl.n_ticks = n_ticks
+        ticks = serving.pack_ticks(sp.wl, torch)
+        caps = serving.scene_capacities(sp.wl)
+        nq = max(q for _, _, q in ticks)
+        kw = dict(capacity_subqueries=caps["capacity_subqueries"],
+                  capacity_covering=caps["capacity_covering"],
+                  capacity_results=caps["capacity_results"], split_slots=caps["split_slots"])
+        row, ref = {"objects": sp.wl.n, "kind": sp.wl.params.get("kind")}, None
+        for label, th in [(f"fixed {t}", t) for t in fixed] + [("learned", None)]:
+            if th is None:
+                sc = Scene(sp.wl.n, nq, th=64, th_min=min(model["cand"]), thresh_mlp=True, **kw)
+                install(sc, model, torch)
+            else:
+                sc = Scene(sp.wl.n, nq, th=th, th_min=min(th, 64), **kw)
+            r = run_ticks(sc, ticks, torch, warm)
+            if th is None:
+                row["learned_th"] = sorted(set(r["th"]))
+            sc.close()
+            d = r.pop("digests")
+            same = same and (ref is None or d == ref)
+            ref = d if ref is None else ref
+            row[label] = r["ms_per_tick"]
+            tot[label] += r["ms_per_tick"]
+        per_scene.append(row)
+        log(json.dumps(row))
+        del ticks
+        torch.cuda.empty_cache()
+    best_fixed = min((v, k) for k, v in tot.items() if k != "learned")
+    return dict(total_ms_per_round=tot, best_fixed=best_fixed[1],
+                learned_vs_best_fixed=best_fixed[0] / tot["learned"], identical_results=same,
+                scenes=per_scene)
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -378,6 +423,11 @@ def main(argv=None) -> int:
     c.add_argument("--model", default=str(MODEL_PATH))
     c.add_argument("--schedule", action="store_true",
                    help="also run the learned threshold with the learned task order")
+    m = sub.add_parser("mix", help="the serving mix's scenes alone: learned vs fixed thresholds")
+    m.add_argument("--fixed", default="64,128,256,384")
+    m.add_argument("--ticks", type=int, default=6)
+    m.add_argument("--scenes", type=int, default=16)
+    m.add_argument("--model", default=str(MODEL_PATH))
     args = ap.parse_args(argv)
     import torch
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
@@ -396,6 +446,11 @@ def main(argv=None) -> int:
                                   for k, v in fit["per_workload"].items()})))
         return 0
     model = load(Path(args.model))
+    if args.cmd == "mix":
+        out = mix(torch, model, tuple(int(v) for v in args.fixed.split(",")), args.ticks,
+                  n_scenes=args.scenes, log=log)
+        print(json.dumps(out))
+        return 0 if out["identical_results"] else 1
     out = compare(args.workload, args.ticks + args.warmup, args.warmup, torch, model,
                   schedule=args.schedule, log=log)
     print(json.dumps(out))

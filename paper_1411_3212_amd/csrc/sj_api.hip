@@ -63,8 +63,8 @@ static char g_create_err[256] = "";
 namespace {
 
 struct Derived {
-  uint32_t N, Q, th, th_min, l_max, period, slots, tcap, tune_every;
-  bool log;
+  uint32_t N, Q, th, th_min, l_max, period, slots, tcap, tune_every, ug, ug_bits;
+  bool log, sqb, cu;
   uint64_t S, C, R;
   uint32_t LCAP, NCAP, FCAP;
 };
@@ -105,6 +105,8 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
   d->period = cfg->rebuild_period ? cfg->rebuild_period : 32u;
   d->slots = cfg->split_slots ? cfg->split_slots : 32u;
   d->log = (cfg->flags & SJ_TIMING_LOG) != 0;
+  d->sqb = (cfg->flags & SJ_ATOMIC_RESULTS) != 0;
+  d->cu = (cfg->flags & SJ_CU_COUNTERS) != 0;
   d->tune_every = cfg->tune_every ? cfg->tune_every : 8u;
   if (d->slots > 4096u) {
     snprintf(msg, msz, "split_slots must be at most 4096");
@@ -113,6 +115,20 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
   if (cfg->rebuild_policy > SJ_REBUILD_NEVER) {
     snprintf(msg, msz, "unknown rebuild policy");
     return SJ_EINVAL;
+  }
+  d->ug = 0;
+  d->ug_bits = 0;
+  if (cfg->flags & SJ_UNIFORM_GRID) {
+    if (cfg->grid_split < 1u || cfg->grid_split > 4096u) {
+      snprintf(msg, msz, "grid_split must be in 1..4096");
+      return SJ_EINVAL;
+    }
+    if (cfg->flags & (SJ_THRESH_MLP | SJ_SCHEDULE_MLP | SJ_TIMING_LOG)) {
+      snprintf(msg, msz, "the uniform grid takes no cost model and no timing log");
+      return SJ_EINVAL;
+    }
+    d->ug = cfg->grid_split;
+    while ((1u << d->ug_bits) < d->ug) ++d->ug_bits;
   }
   // Split nodes at level l are disjoint and hold more than th_min objects
   // each, and there are at most 4^l of them: bound the tree by that.
@@ -136,6 +152,7 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
   d->tcap = lu + 4u < 4u ? 4u : (lu + 4u > 12u ? 12u : lu + 4u);
   if (d->tcap > d->l_max) d->tcap = d->l_max;
   d->LCAP = (uint32_t)leaves;
+  if (d->ug && (1u << (2u * d->ug_bits)) > d->LCAP) d->LCAP = 1u << (2u * d->ug_bits);
   d->NCAP = (uint32_t)splits;
   d->FCAP = (uint32_t)fmax;
   return SJ_OK;
@@ -183,10 +200,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.nodes = c.take<uint4>(d.NCAP);
   b.table = c.take<uint32_t>(1ull << (2 * d.tcap));
   b.leaf_beg = c.take<uint32_t>(L + 1);
-  b.leaf_nsq = c.take<uint32_t>(L);
   b.leaf_sqoff = c.take<uint32_t>(L + 1);
-  b.leaf_ovf = c.take<uint32_t>(L);
-  b.leaf_ovfc = c.take<uint32_t>(L);
   // join tasks: one per leaf and one per further kTaskSub subqueries of a leaf
   const uint64_t T = (uint64_t)L + d.S / sj::kTaskSub + 1u;
   b.tkey = c.take<uint32_t>(T);
@@ -205,15 +219,16 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.q_nc = c.take<uint32_t>(Q);
   b.q_ioff = c.take<uint32_t>(Q + 1);
   b.q_coff = c.take<uint32_t>(Q + 1);
-  b.q_roff = c.take<uint64_t>(Q + 1);
   b.qlist = c.take<uint32_t>(Q * d.slots);
-  b.qpos = c.take<uint32_t>(Q * d.slots);
-  b.sq = c.take<uint2>(d.S);
+  b.sq = c.take<uint32_t>(d.S);
+  b.slot_sq = c.take<uint32_t>(d.S);
   b.sq_cnt = c.take<uint32_t>(d.S);
   b.res_off = c.take<uint64_t>(d.S + 1);
   b.cov_leaf = c.take<uint32_t>(d.C);
   b.res_ids = c.take<uint32_t>(d.R);
   b.tlog = d.log ? c.take<float>((uint64_t)L * 8) : nullptr;
+  b.pairs = d.sqb ? c.take<uint2>(d.R) : nullptr;
+  b.cu_tests = d.cu ? c.take<uint64_t>(sj::kCuSlots) : nullptr;
   b.tune = c.take<sj::TuneState>(1);
   b.N = d.N;
   b.Q = d.Q;
@@ -282,6 +297,7 @@ int check_tick_args(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const
 // tick it decides (and launches the build kernels only if needed);
 // otherwise the device decides and the build kernels are launched gated.
 uint32_t host_decision(const sj_scene *s) {
+  if (s->cfg.flags & SJ_UNIFORM_GRID) return 1u;  // the grid is materialised every tick
   if (!s->known) return 2u;
   const Ctl &c = s->host_ctl;
   const uint32_t policy = s->cfg.rebuild_policy;
@@ -327,31 +343,41 @@ void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_tota
   auto rec = [&](int i) {
     if (events) (void)hipEventRecord(s->ev[i], st);
   };
+  const bool sqb = (flags & SJ_ATOMIC_RESULTS) != 0;
   if (part == 2) {
-    sj::launch_join_write(s->B, nq, st);
+    if (!sqb) sj::launch_join_write(s->B, nq, st);
     sj::launch_ctl_out(s->B, s->pin_ctl, st);
     return;
   }
+  if (s->B.cu_tests) sj::launch_fill_u64(s->B.cu_tests, sj::kCuSlots, 0ull, st);
   rec(0);
   sj::launch_index(s->B, decision, policy, upd_total, nq, key_bits(s, decision), st);
   rec(1);
   if (tune)
     sj::launch_tune(s->B, s->n_cand, s->l_max, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
-  if (decision != 0u) sj::launch_build(s->B, s->l_max, st);
+  if (decision != 0u && !(flags & SJ_UNIFORM_GRID)) sj::launch_build(s->B, s->l_max, st);
   rec(2);
   sj::launch_leaves(s->B, st);
   rec(3);
-  sj::launch_split(s->B, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  const uint32_t *qord = sj::launch_split(s->B, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   rec(4);
   const bool learned = (flags & SJ_SCHEDULE_MLP) && s->cm_set;
   sj::launch_schedule(s->B, (flags & SJ_REORDER) ? 1u : 0u, s->l_max, learned, st);
   rec(5);
-  sj::launch_join_count(s->B, st);
-  rec(6);
-  sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
+  if (sqb) {
+    // the baseline filter appends every result (timed as the count phase),
+    // then the tick's totals
+    sj::launch_join_sqb(s->B, nq, qord, st);
+    rec(6);
+    sj::launch_join_top_sqb(s->B, s->B.R, policy, s->period, st);
+  } else {
+    sj::launch_join_count(s->B, st);
+    rec(6);
+    sj::launch_join_scan(s->B, s->B.R, policy, s->period, st);
+  }
   rec(7);
   if (part == 1) return;
-  sj::launch_join_write(s->B, nq, st);
+  if (!sqb) sj::launch_join_write(s->B, nq, st);
   rec(8);
   rec(9);
   sj::launch_ctl_out(s->B, s->pin_ctl, st);
@@ -428,7 +454,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
       return SJ_EDEVICE;
     }
   }
-  sj::launch_ctl_init(s->B.ctl, d.th, stream);
+  sj::launch_ctl_init(s->B.ctl, d.th, d.ug, d.ug_bits, stream);
   sj::launch_fill_u32((uint32_t *)s->B.pos, 2ull * d.N, 0x7fc00000u, stream);  // NaN: no position
   sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
   sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
@@ -728,7 +754,12 @@ int sj_fetch_results(sj_scene *s, sj_results *out) {
   out->n_isect_ids = ok ? c.n_res : 0;
   out->n_cov_entries = ok ? c.n_cov : 0;
   out->total_pairs = ok ? c.n_res + c.cov_pairs : 0;
-  out->d_isect_off = s->B.q_roff;
+  out->n_runs = ok && !s->B.pairs ? c.n_isect : 0;
+  out->n_pairs = ok && s->B.pairs ? c.n_res : 0;
+  out->d_pairs = (const uint32_t *)s->B.pairs;
+  out->d_isect_slot_off = s->B.q_ioff;
+  out->d_slot_run = s->B.slot_sq;
+  out->d_run_off = s->B.res_off;
   out->d_isect_id = s->B.res_ids;
   out->d_cov_off = s->B.q_coff;
   out->d_cov_leaf = s->B.cov_leaf;
@@ -751,21 +782,49 @@ int sj_result_hashes(sj_scene *s, uint64_t *d_count, uint64_t *d_hash) {
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "result_hashes launch");
 }
 
-int sj_expand_results(sj_scene *s, uint64_t *d_off, uint32_t *d_ids, uint64_t ids_cap,
-                      uint64_t *n_pairs) {
+int sj_expand_results(sj_scene *s, const uint32_t *d_sel, uint32_t n_sel, uint32_t flags,
+                      uint64_t *d_off, uint32_t *d_ids, uint64_t ids_cap, uint64_t *n_pairs) {
   if (!s) return SJ_EINVAL;
   if (!s->ticked) return fail(s, SJ_ESTATE, "expand_results before run_tick");
+  if (flags & ~(uint32_t)SJ_SORTED) return fail(s, SJ_EINVAL, "expand_results: unknown flags");
+  if (d_sel && s->B.pairs)
+    return fail(s, SJ_EINVAL, "expand_results: no selection with appended pairs (SJ_ATOMIC_RESULTS)");
+  if (d_sel && (((uintptr_t)d_sel & 3u) || !d_off || ((uintptr_t)d_off & 7u) ||
+                n_sel > s->B.Q))
+    return fail(s, SJ_EINVAL,
+                "expand_results: a selection needs aligned d_sel and d_off, n_sel <= "
+                "capacity_queries");
   int rc = sync_ctl(s);
   if (rc != SJ_OK) return rc;
   const Ctl &c = s->host_ctl;
-  const uint64_t total = c.go_join ? c.n_res + c.cov_pairs : 0;
-  if (n_pairs) *n_pairs = total;
   rc = status_of(s, c.err);
   if (rc == SJ_EOVERFLOW) return rc;
-  if (!d_ids) return SJ_OK;
-  if (!d_off || ids_cap < total) return fail(s, SJ_EINVAL, "expand_results: buffer too small");
-  sj::launch_expand_count(s->B, s->last_nq, d_off, s->stream);
-  sj::launch_expand(s->B, s->last_nq, d_off, d_ids, s->stream);
+  const uint32_t n = d_sel ? n_sel : s->last_nq;
+  uint64_t total = c.go_join ? c.n_res + c.cov_pairs : 0;
+  if (d_sel) {
+    // sizes of the selected lists: counted and scanned into d_off, the total
+    // and the index check read back
+    uint32_t *bad = &s->B.ctl->exp_bad;
+    sj::launch_fill_u32(bad, 1, 0u, s->stream);
+    sj::launch_expand_count(s->B, s->last_nq, d_sel, n, d_off, bad, s->stream);
+    uint32_t hbad = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&total, d_off + n, sizeof total, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "expand_results count");
+    if (hbad) return fail(s, SJ_EINVAL, "expand_results: selected query index >= nq");
+  }
+  if (n_pairs) *n_pairs = total;
+  if (!d_ids) return rc;
+  if (!d_off || ((uintptr_t)d_off & 7u) || ((uintptr_t)d_ids & 3u) || ids_cap < total)
+    return fail(s, SJ_EINVAL, "expand_results: missing, misaligned or too small buffer");
+  if (!d_sel) sj::launch_expand_count(s->B, s->last_nq, nullptr, n, d_off, &s->B.ctl->exp_bad,
+                                      s->stream);
+  sj::launch_expand(s->B, s->last_nq, d_sel, n, d_off, d_ids, (flags & SJ_SORTED) != 0,
+                    s->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(s, e, "expand_results launch");
   e = hipStreamSynchronize(s->stream);
@@ -814,6 +873,8 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[SJ_COST
                       const uint32_t *cand,
                       uint32_t n_cand) {
   if (!s || !d_w || !coef || !cand) return SJ_EINVAL;
+  if (s->cfg.flags & SJ_UNIFORM_GRID)
+    return fail(s, SJ_EINVAL, "set_cost_model: the uniform grid has no threshold to tune");
   if (n_cand == 0 || n_cand > (uint32_t)sj::kMaxCand)
     return fail(s, SJ_EINVAL, "set_cost_model: n_cand must be in 1..8");
   const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
@@ -904,6 +965,15 @@ int sj_index_view_get(sj_scene *s, sj_index_view *out) {
   out->d_leaf_beg = s->B.leaf_beg;
   out->d_pos = (const float *)s->B.pos;
   return SJ_OK;
+}
+
+int sj_cu_counters(sj_scene *s, uint64_t *out, uint32_t n) {
+  if (!s || !out || n == 0 || n > sj::kCuSlots) return SJ_EINVAL;
+  if (!s->B.cu_tests) return fail(s, SJ_ESTATE, "scene created without SJ_CU_COUNTERS");
+  hipError_t e = hipMemcpyAsync(out, s->B.cu_tests, (size_t)n * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "cu_counters copy");
 }
 
 const char *sj_last_error(const sj_scene *s) { return s ? s->err : g_create_err; }

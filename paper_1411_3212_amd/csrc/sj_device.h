@@ -54,6 +54,10 @@ struct Ctl {
   uint32_t n_entries;     // join tasks: one per leaf + one per further kTaskSub subqueries
   uint32_t n_run;         // join tasks with work, in run order in the task records
   uint32_t n_qord;        // queries put in spatial order
+  uint32_t exp_bad;       // an expansion selected a query index >= nq
+  uint32_t ug_split;      // uniform-grid index: columns (and rows) of the frame; 0: quadtree
+  uint32_t ug_bits;       // bits per axis of the grid cells' Morton codes
+  uint32_t sq_skip;       // radix digits of the subqueries' leaf keys (multiple of 8)
   uint32_t max_leaf;
   uint32_t err_upd;       // errors of updates since the last tick
   uint32_t err;           // errors of the current tick (includes err_upd)
@@ -86,6 +90,33 @@ __device__ __forceinline__ uint32_t fenc(float f) {
 }
 __device__ __forceinline__ float fdec(uint32_t u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// SplitMix64's output function (the pair-set hash of a result set adds it
+// over the pairs (qid << 32) | id).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Per-CU work counters: the slot of the compute unit running the wave, from
+// its hardware id registers (HW_ID: CU, shader array and shader engine;
+// XCC_ID: the accelerator complex die).  Distinct CUs get distinct slots
+// below kCuSlots.
+constexpr uint32_t kCuSlots = 4096;
+__device__ __forceinline__ uint32_t cu_slot() {
+  const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_REG_HW_ID, 32 bits
+  const uint32_t xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // HW_REG_XCC_ID, 32 bits
+  const uint32_t cu = (hw >> 8) & 0xfu, sh = (hw >> 12) & 1u, se = (hw >> 13) & 7u;
+  return ((xcc & 0xfu) << 8) | (se << 5) | (sh << 4) | cu;
+}
+
+// Column (or row) of the uniform grid holding finest-level cell `fine`:
+// the frame's 2^16 finest cells are cut into s runs of floor or ceil of
+// 2^16 / s cells (monotone, exact integer arithmetic).
+__device__ __forceinline__ uint32_t ug_col(uint32_t fine, uint32_t s) {
+  return (uint32_t)(((uint64_t)fine * s) >> 16);
 }
 
 // Finest-level cell index of a coordinate: one binary32 subtraction, an

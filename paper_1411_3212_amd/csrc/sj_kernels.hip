@@ -77,12 +77,14 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
-__global__ void k_ctl_init(Ctl *ctl, uint32_t th) {
+__global__ void k_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits) {
   Ctl c;
   uint8_t *b = (uint8_t *)&c;
   for (unsigned i = 0; i < sizeof(Ctl); ++i) b[i] = 0;
   c.th_cur = th;
   c.scale = 65536.0f;
+  c.ug_split = ug_split;
+  c.ug_bits = ug_bits;
   *ctl = c;
 }
 
@@ -321,6 +323,14 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   ctl->n_leaves = 0;
   ctl->l_deep = 0;
   front0[0] = make_uint4(0u, 0u, total, 0u);
+  if (ctl->ug_split) {
+    // uniform grid: every cell of the Morton range is a leaf, the sort keys
+    // (cell codes) are below 4^ug_bits
+    const uint32_t b = ctl->ug_bits;
+    ctl->n_leaves = 1u << (2u * b);
+    ctl->l_deep = b;
+    ctl->sort_skip = (2u * b + 7u) / 8u * 8u < 8u ? 8u : (2u * b + 7u) / 8u * 8u;
+  }
 }
 
 // Sort keys of present objects, compacted in id order: their Morton codes
@@ -343,6 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
   const uint64_t b1 = b0 + chunk < N ? b0 + chunk : N;
   const float x0 = ctl->x0, y0 = ctl->y0, sc = ctl->scale;
   const bool keep = !ctl->rebuild;  // the quadtree is kept: sort by leaf
+  const uint32_t ug = ctl->ug_split;  // uniform grid: sort by grid cell
   tr.tlev = ctl->tlev;
   uint32_t base = blk[blockIdx.x];
   for (uint64_t t0 = b0; t0 < b1; t0 += kBlock * kMortonRows) {
@@ -358,7 +369,8 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
     for (uint32_t j = 0; j < kMortonRows; ++j) {
       const bool pres = p[j].x == p[j].x;
       flags |= (uint64_t)(pres ? 1u : 0u) << (16u * j);
-      key[j] = pres ? morton2(cell_of(p[j].x, x0, sc), cell_of(p[j].y, y0, sc)) : 0u;
+      const uint32_t ci = cell_of(p[j].x, x0, sc), cj = cell_of(p[j].y, y0, sc);
+      key[j] = !pres ? 0u : ug ? morton2(ug_col(ci, ug), ug_col(cj, ug)) : morton2(ci, cj);
     }
     if (keep) {
       uint32_t e[kMortonRows];
@@ -672,16 +684,19 @@ __global__ void __launch_bounds__(kBlock) k_table_build(const Ctl *ctl, const ui
 // Object range of every leaf in the sorted keys: codes after a build
 // (first code >= the leaf's start), leaf indices otherwise.
 __global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const uint32_t *keys,
-                                                        const uint32_t *lstart, uint32_t *leaf_beg,
-                                                        uint32_t *leaf_nsq, uint32_t *leaf_ovf,
-                                                        uint32_t *leaf_ovfc) {
+                                                        const uint32_t *lstart,
+                                                        uint32_t *leaf_beg) {
   const uint32_t n = ctl->n_leaves, np = ctl->n_present;
-  const bool by_code = ctl->rebuild != 0;
+  // the keys are leaf indices on kept-tree ticks and grid cells (the leaves
+  // of a uniform grid)
+  const bool by_code = ctl->rebuild != 0 && !ctl->ug_split;
   const uint32_t stride = gridDim.x * kBlock, g = blockIdx.x * kBlock + threadIdx.x;
   // one binary search per leaf, or one pass over the sorted leaf keys when
   // leaves hold at most 48 objects on average (measured: the pass is faster
-  // at 31 objects per leaf, the searches at 115)
-  if (by_code || (uint64_t)np > 48ull * n) {
+  // at 31 objects per leaf, the searches at 115); a uniform grid's Morton
+  // range holds long runs of cells outside the grid (always empty), which
+  // one position of the pass would fill alone, so it takes the searches
+  if (by_code || ctl->ug_split || (uint64_t)np > 48ull * n) {
     for (uint32_t t = g; t < n; t += stride)
       leaf_beg[t] = lower_bound_u32(keys, 0u, np, by_code ? lstart[t] : t);
     if (g == 0) leaf_beg[n] = np;
@@ -706,11 +721,6 @@ __global__ void __launch_bounds__(kBlock) k_leaf_ranges(const Ctl *ctl, const ui
           for (uint32_t t = lo[j]; t <= hi[j]; ++t) leaf_beg[t] = (uint32_t)i;
       }
     }
-  }
-  for (uint32_t t = g; t < n; t += stride) {
-    leaf_nsq[t] = 0u;
-    leaf_ovf[t] = 0u;
-    leaf_ovfc[t] = 0u;
   }
 }
 
@@ -808,6 +818,7 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
 // receives the leaf's index in the query's list and its rank among the
 // intersecting (ri) or covering (rc) entries.  Inactive leaves are skipped.
 constexpr uint32_t kSplitGroup = 16;
+constexpr uint32_t kSplitBatch = 4;  // rounds of table cells whose loads go out together
 
 struct LeafCounts {
   uint32_t n, ni, nc;
@@ -824,59 +835,121 @@ __device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *sta
   const bool from_root = ncell > kTableScanMax;
   const uint32_t rounds = from_root ? 1u : (ncell + kSplitGroup - 1u) / kSplitGroup;
   uint32_t nl = 0, ni = 0, nc = 0;  // the same on every lane of the group
-  for (uint32_t rd = 0; rd < rounds; ++rd) {
-    const uint32_t c = rd * kSplitGroup + gl;
-    bool a = false, b = false, cv = false;
-    uint32_t leaf = 0, node = 0, ci = 0, cj = 0, depth = T;
-    if (from_root) {
-      b = gl == 0;
-      depth = 0;
-    } else if (c < ncell) {
-      ci = ti0 + c % w;
-      cj = tj0 + c / w;
-      const uint32_t e = tr.table[morton2(ci, cj)];
-      if (!(e & kLeafBit)) {
-        b = true;
-        node = e;
-      } else {
-        const uint32_t l = ((e >> kLeafIdxBits) & 15u) + 1u, m = T - l;
+  // kSplitBatch rounds at a time: their table entries are loaded together,
+  // then the object ranges of the leaves they keep, then the rounds run in
+  // order
+  for (uint32_t rd0 = 0; rd0 < rounds; rd0 += kSplitBatch) {
+    uint32_t ent[kSplitBatch], lb[kSplitBatch], le[kSplitBatch];
+    bool cell[kSplitBatch], kept[kSplitBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kSplitBatch; ++j) {
+      const uint32_t c = (rd0 + j) * kSplitGroup + gl;
+      cell[j] = !from_root && rd0 + j < rounds && c < ncell;
+      ent[j] = cell[j] ? tr.table[morton2(ti0 + c % w, tj0 + c / w)] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kSplitBatch; ++j) {
+      kept[j] = false;
+      lb[j] = le[j] = 0u;
+      if (cell[j] && (ent[j] & kLeafBit)) {
+        // a leaf is kept at the query's cell with minimal coordinates in it
+        const uint32_t c = (rd0 + j) * kSplitGroup + gl;
+        const uint32_t ci = ti0 + c % w, cj = tj0 + c / w;
+        const uint32_t l = ((ent[j] >> kLeafIdxBits) & 15u) + 1u, m = T - l;
         const uint32_t li0 = (ci >> m) << m, lj0 = (cj >> m) << m;
-        if (ci == (ti0 > li0 ? ti0 : li0) && cj == (tj0 > lj0 ? tj0 : lj0)) {
-          leaf = e & kLeafIdxMask;
-          a = leaf_beg[leaf + 1] != leaf_beg[leaf];
+        kept[j] = ci == (ti0 > li0 ? ti0 : li0) && cj == (tj0 > lj0 ? tj0 : lj0);
+        if (kept[j]) {
+          const uint32_t leaf = ent[j] & kLeafIdxMask;
+          lb[j] = leaf_beg[leaf];
+          le[j] = leaf_beg[leaf + 1];
+        }
+      }
+    }
+    for (uint32_t j = 0; j < kSplitBatch && rd0 + j < rounds; ++j) {
+      const uint32_t c = (rd0 + j) * kSplitGroup + gl;
+      bool a = false, b = false, cv = false;
+      uint32_t leaf = 0, node = 0, ci = 0, cj = 0, depth = T;
+      if (from_root) {
+        b = gl == 0;
+        depth = 0;
+      } else if (cell[j]) {
+        ci = ti0 + c % w;
+        cj = tj0 + c / w;
+        if (!(ent[j] & kLeafBit)) {
+          b = true;
+          node = ent[j];
+        } else if (kept[j]) {
+          const uint32_t l = ((ent[j] >> kLeafIdxBits) & 15u) + 1u, m = T - l;
+          const uint32_t li0 = (ci >> m) << m, lj0 = (cj >> m) << m;
+          leaf = ent[j] & kLeafIdxMask;
+          a = le[j] != lb[j];
           const uint32_t ilo = li0 << sh, jlo = lj0 << sh, span = (1u << (kFine - l)) - 1u;
           cv = a && covering &&
                (q.i0 < ilo && ilo + span < q.i1 && q.j0 < jlo && jlo + span < q.j1);
         }
       }
+      const uint64_t ma = ballot(a) & gm, mc = ballot(cv) & gm, mi = ma & ~mc;
+      if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc));
+      nl += (uint32_t)__popcll(ma);
+      ni += (uint32_t)__popcll(mi);
+      nc += (uint32_t)__popcll(mc);
+      uint64_t mb = ballot(b) & gm;
+      while (mb) {
+        const uint32_t bl = (uint32_t)__ffsll((unsigned long long)mb) - 1u;
+        mb &= mb - 1u;
+        uint32_t dl = 0, di = 0, dc = 0;
+        if (lane == bl) {
+          auto v = [&](uint32_t lf, bool cov0) {
+            if (leaf_beg[lf + 1] == leaf_beg[lf]) return;
+            const bool cc = cov0 && covering;
+            visit(lf, cc, nl + dl, ni + di, nc + dc);
+            ++dl;
+            if (cc)
+              ++dc;
+            else
+              ++di;
+          };
+          walk_from(tr.nodes, stack, node, depth, ci, cj, q, v);
+        }
+        nl += (uint32_t)__shfl((int)dl, (int)bl);
+        ni += (uint32_t)__shfl((int)di, (int)bl);
+        nc += (uint32_t)__shfl((int)dc, (int)bl);
+      }
+    }
+  }
+  return LeafCounts{nl, ni, nc};
+}
+
+// Leaves of a uniform grid overlapping a query: the cells of the query's
+// column and row range in row order, kSplitGroup at a time (one per lane),
+// visited like group_leaves' (index in the query's list, rank among the
+// intersecting or covering ones).  A cell strictly inside the range on
+// both axes is covering.  Cells without objects are skipped.
+template <typename Visit>
+__device__ __forceinline__ LeafCounts grid_leaves(uint32_t s, const QBox q,
+                                                  const uint32_t *leaf_beg, uint32_t covering,
+                                                  uint32_t lane, uint64_t gm, Visit &visit) {
+  const uint32_t gl = lane & (kSplitGroup - 1u);
+  const uint32_t i0 = ug_col(q.i0, s), i1 = ug_col(q.i1, s);
+  const uint32_t j0 = ug_col(q.j0, s), j1 = ug_col(q.j1, s);
+  const uint32_t w = i1 - i0 + 1u;
+  const uint64_t ncell = (uint64_t)w * (j1 - j0 + 1u);
+  uint32_t nl = 0, ni = 0, nc = 0;  // the same on every lane of the group
+  for (uint64_t c0 = 0; c0 < ncell; c0 += kSplitGroup) {
+    const uint64_t c = c0 + gl;
+    bool a = false, cv = false;
+    uint32_t leaf = 0;
+    if (c < ncell) {
+      const uint32_t ci = i0 + (uint32_t)(c % w), cj = j0 + (uint32_t)(c / w);
+      leaf = morton2(ci, cj);
+      a = leaf_beg[leaf + 1] != leaf_beg[leaf];
+      cv = a && covering && i0 < ci && ci < i1 && j0 < cj && cj < j1;
     }
     const uint64_t ma = ballot(a) & gm, mc = ballot(cv) & gm, mi = ma & ~mc;
     if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc));
     nl += (uint32_t)__popcll(ma);
     ni += (uint32_t)__popcll(mi);
     nc += (uint32_t)__popcll(mc);
-    uint64_t mb = ballot(b) & gm;
-    while (mb) {
-      const uint32_t bl = (uint32_t)__ffsll((unsigned long long)mb) - 1u;
-      mb &= mb - 1u;
-      uint32_t dl = 0, di = 0, dc = 0;
-      if (lane == bl) {
-        auto v = [&](uint32_t lf, bool cov0) {
-          if (leaf_beg[lf + 1] == leaf_beg[lf]) return;
-          const bool cc = cov0 && covering;
-          visit(lf, cc, nl + dl, ni + di, nc + dc);
-          ++dl;
-          if (cc)
-            ++dc;
-          else
-            ++di;
-        };
-        walk_from(tr.nodes, stack, node, depth, ci, cj, q, v);
-      }
-      nl += (uint32_t)__shfl((int)dl, (int)bl);
-      ni += (uint32_t)__shfl((int)di, (int)bl);
-      nc += (uint32_t)__shfl((int)dc, (int)bl);
-    }
   }
   return LeafCounts{nl, ni, nc};
 }
@@ -901,21 +974,23 @@ __global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const TickIn *
 }
 
 // Count pass, one query per group of kSplitGroup lanes: the numbers of
-// intersecting and covering subqueries per query and of intersecting
-// subqueries per leaf; the first `slots` entries of a query's list (leaf,
-// covering flag) and the positions of its intersecting entries in their
-// leaves' groups are kept for the write pass.
+// intersecting and covering subqueries per query; the first `slots`
+// entries of a query's list (leaf, covering flag) are kept for the write
+// pass.  The rectangle of the g-th query in processing order is stored at
+// qrect[g], so that the subqueries of one leaf (queries that lie close
+// together, processed close together in a spatially ordered batch) read
+// nearby rectangles in the join.
 __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
-    const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *leaf_nsq,
-    uint32_t *leaf_ovf, uint32_t *qlist, uint32_t *qpos, uint32_t slots, uint32_t covering,
-    const uint32_t *qord) {
+    const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *qlist,
+    uint32_t slots, uint32_t covering, const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
   const uint32_t *__restrict__ qid = tin->qid;
   const float *__restrict__ xa = tin->xa, *__restrict__ ya = tin->ya, *__restrict__ xb = tin->xb,
                             *__restrict__ yb = tin->yb;
   const uint64_t seq = ctl->qry_seq;
   const bool tree_ok = !(ctl->err & kErrOvfTree);
+  const uint32_t ug = ctl->ug_split;
   tr.tlev = ctl->tlev;
   const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
   const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
@@ -927,24 +1002,18 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
     QBox q;
     if (query_box(ctl, k, qid[k], N, qstamp, seq, r, &q, &bad_rect) && tree_ok) {
-      uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      uint32_t *lst = qlist + (uint64_t)k * slots;
       auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t, uint32_t) {
         if (i < slots) lst[i] = leaf | (c ? kLeafBit : 0u);
-        if (c) return;
-        // subqueries past the list get a position after the leaf's other
-        // subqueries in the write pass
-        if (i < slots)
-          pos[i] = atomicAdd(&leaf_nsq[leaf], 1u);
-        else
-          atomicAdd(&leaf_ovf[leaf], 1u);
       };
-      const LeafCounts n = group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm,
-                                        visit);
+      const LeafCounts n =
+          ug ? grid_leaves(ug, q, leaf_beg, covering, lane, gm, visit)
+             : group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm, visit);
       ni = n.ni;
       nc = n.nc;
     }
     if (gl == 0) {
-      qrect[k] = r;
+      qrect[g] = r;
       q_ni[k] = ni;
       q_nc[k] = nc;
     }
@@ -957,12 +1026,12 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
                                                             uint64_t *part, uint64_t cap_sq,
                                                             uint64_t cap_cov) {
   __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
-  // the three partials are loaded before the first scan waits on a barrier
-  uint64_t v[3], tot[3];
+  // both partials are loaded before the first scan waits on a barrier
+  uint64_t v[2], tot[2];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) v[q] = part[q * kChunkBlocks + threadIdx.x];
+  for (int q = 0; q < 2; ++q) v[q] = part[q * kChunkBlocks + threadIdx.x];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 2; ++q) {
     part[q * kChunkBlocks + threadIdx.x] =
         block_excl_scan<uint64_t, kChunkBlocks>(v[q], lds, &tot[q]);
     if (threadIdx.x == 0) job_store(jobs.j[q], job_n(jobs.j[q]), tot[q]);
@@ -977,28 +1046,35 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
   ctl->n_cov = tot[1];
   ctl->n_entries = ctl->n_leaves;
   ctl->go_split = err ? 0u : 1u;
+  // radix passes that sort the subqueries by leaf: the digits of n_leaves - 1
+  const uint32_t nl = ctl->n_leaves;
+  const uint32_t bits = nl > 1u ? 32u - (uint32_t)__clz((int)(nl - 1u)) : 0u;
+  ctl->sq_skip = bits <= 8u ? 8u : (bits + 7u) / 8u * 8u;
   ctl->n32[0] = err ? 0u : (uint32_t)tot[0];
   ctl->n32[1] = err ? 0u : (uint32_t)tot[1];
 }
 
-// Write pass, one query per group: intersecting subqueries grouped by leaf
-// (record: query, slot of the subquery in query order), covering leaves per
-// query.  A query whose list fit reads it back, kSplitGroup entries at a
-// time; a longer one enumerates its leaves again in the same order.  The
-// order inside a leaf's group does not matter: a subquery's results go to
-// the offset of its query-order slot.
+// Write pass, one query per group, in query order: every intersecting
+// subquery's leaf at its slot (skey[slot]; sval[slot] = slot, the value the
+// sort by leaf carries; sg[slot] = g, the index of its query's rectangle),
+// covering leaves per query.  A query whose list fit reads it back,
+// kSplitGroup entries at a time; a longer one enumerates its leaves again
+// in the same order.  A stable sort by leaf then groups the subqueries
+// (k_sq_final), in slot order inside a leaf, so the grouping and the
+// results' layout are the same on every run.
 __global__ void __launch_bounds__(kBlock) k_q_write(
     Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
-    const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, const uint32_t *qpos,
-    uint32_t slots, const uint32_t *leaf_sqoff, const uint32_t *leaf_nsq, uint32_t *leaf_ovfc,
-    uint2 *sq, uint32_t *cov_leaf, uint32_t covering, uint64_t *red, const uint32_t *qord) {
+    const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, uint32_t slots,
+    uint32_t *skey, uint32_t *sval, uint32_t *sg, uint32_t *cov_leaf, uint32_t covering,
+    uint64_t *red, const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
   __shared__ uint64_t lds[kWavesPerBlock];
   uint64_t covp = 0;
   if (ctl->go_split) {
     const uint32_t *__restrict__ qid = tin->qid;
     const uint64_t seq = ctl->qry_seq;
+    const uint32_t ug = ctl->ug_split;
     tr.tlev = ctl->tlev;
     const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
     const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
@@ -1008,39 +1084,40 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
       const uint32_t n = q_ni[k] + q_nc[k];
       if (n == 0) continue;
       const uint32_t wi = q_ioff[k], wc = q_coff[k];
-      const uint32_t *lst = qlist + (uint64_t)k * slots, *pos = qpos + (uint64_t)k * slots;
+      auto put = [&](uint32_t leaf, bool c, uint32_t ri, uint32_t rc) {
+        if (c) {
+          cov_leaf[wc + rc] = leaf;
+          covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
+        } else {
+          skey[wi + ri] = leaf;
+          sval[wi + ri] = wi + ri;
+          sg[wi + ri] = g;
+        }
+      };
       if (n <= slots) {
+        const uint32_t *lst = qlist + (uint64_t)k * slots;
         uint32_t ri = 0, rc = 0;
         for (uint32_t i0 = 0; i0 < n; i0 += kSplitGroup) {
           const uint32_t i = i0 + gl;
           const bool v = i < n;
           const uint32_t e = v ? lst[i] : 0u;
           const bool c = v && (e & kLeafBit), x = v && !(e & kLeafBit);
-          const uint32_t leaf = e & ~kLeafBit;
           const uint64_t mi = ballot(x) & gm, mc = ballot(c) & gm;
-          if (x) sq[leaf_sqoff[leaf] + pos[i]] = make_uint2(k, wi + ri + mbcnt(mi));
-          if (c) {
-            cov_leaf[wc + rc + mbcnt(mc)] = leaf;
-            covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
-          }
+          if (v) put(e & ~kLeafBit, c, ri + mbcnt(mi), rc + mbcnt(mc));
           ri += (uint32_t)__popcll(mi);
           rc += (uint32_t)__popcll(mc);
         }
       } else {
         QBox q;
         bool bad_rect;
-        query_box(ctl, k, qid[k], N, qstamp, seq, qrect[k], &q, &bad_rect);
-        auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t ri, uint32_t rc) {
-          if (c) {
-            cov_leaf[wc + rc] = leaf;
-            covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
-            return;
-          }
-          const uint32_t p =
-              i < slots ? pos[i] : leaf_nsq[leaf] + atomicAdd(&leaf_ovfc[leaf], 1u);
-          sq[leaf_sqoff[leaf] + p] = make_uint2(k, wi + ri);
+        query_box(ctl, k, qid[k], N, qstamp, seq, qrect[g], &q, &bad_rect);
+        auto visit = [&](uint32_t leaf, bool c, uint32_t, uint32_t ri, uint32_t rc) {
+          put(leaf, c, ri, rc);
         };
-        group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm, visit);
+        if (ug)
+          grid_leaves(ug, q, leaf_beg, covering, lane, gm, visit);
+        else
+          group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm, visit);
       }
     }
   }
@@ -1051,6 +1128,34 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     uint64_t t = 0;
     for (int w = 0; w < kWavesPerBlock; ++w) t += lds[w];
     red[kRedCovPairs * kChunkBlocks + blockIdx.x] = t;
+  }
+}
+
+// After the sort by leaf (keys skey, values the slots, both in sorted
+// order): position p of the grouped subqueries holds slot s = sval[p];
+// sq[p] = the index of its query's rectangle (sg[s]), slot_sq[s] = p (sg
+// and slot_sq share memory: a slot is read, then written, by the one
+// thread of its position), and every leaf's first position (leaf_sqoff,
+// with the leaves in between empty ones included).
+__global__ void __launch_bounds__(kBlock) k_sq_final(const Ctl *ctl, const uint32_t *skey,
+                                                     const uint32_t *sval, uint32_t *sq,
+                                                     uint32_t *slot_sq, uint32_t *leaf_sqoff) {
+  if (!ctl->go_split) return;
+  const uint32_t n = ctl->n32[0], nl = ctl->n_leaves;
+  const uint32_t stride = gridDim.x * kBlock, t0 = blockIdx.x * kBlock + threadIdx.x;
+  if (n == 0) {
+    for (uint32_t t = t0; t <= nl; t += stride) leaf_sqoff[t] = 0u;
+    return;
+  }
+  for (uint32_t p = t0; p < n; p += stride) {
+    const uint32_t key = skey[p], s = sval[p];
+    const uint32_t lo = p ? skey[p - 1] + 1u : 0u;
+    const uint32_t g = slot_sq[s];
+    slot_sq[s] = p;
+    sq[p] = g;
+    for (uint32_t t = lo; t <= key; ++t) leaf_sqoff[t] = p;
+    if (p == n - 1u)
+      for (uint32_t t = key + 1u; t <= nl; ++t) leaf_sqoff[t] = n;
   }
 }
 
@@ -1089,6 +1194,7 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *
   auto key_of = [&](uint64_t w) { return reorder ? task_key(w) : (w ? 0u : 255u); };
   const uint32_t n = ctl->n_leaves;
   const bool ok = ctl->go_split != 0;
+  const bool ug = ctl->ug_split != 0;
   uint64_t tests = 0;
   uint32_t mx = 0, nt = 0;
   bool ovf = false;
@@ -1103,7 +1209,7 @@ __global__ void __launch_bounds__(kBlock) k_task_keys(Ctl *ctl, const uint32_t *
     if (!valid) continue;
     tests += w;
     nt += w != 0;
-    if (llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
+    if (ug || llevel[t] < l_max) mx = cnt > mx ? cnt : mx;
     const uint32_t k0 = key_of((uint64_t)(nsq < kTaskSub ? nsq : kTaskSub) * cnt);
     tkey[t] = k0;
     if (count && k0 < 255u) atomicAdd(&lh[k0], 1u);
@@ -1261,9 +1367,10 @@ __device__ __forceinline__ uint4 rec_read(uint32_t v, uint32_t t, uint32_t nt) {
                              (uint32_t)__builtin_amdgcn_readlane((int)v, 3));
   return t < nt ? r : make_uint4(0u, 0u, 0u, 0u);
 }
-// Lane l's subquery entry (query, slot) of a task (l < its count).
-__device__ __forceinline__ uint2 sq_entry(const uint2 *__restrict__ sq, const uint4 rec,
-                                          uint32_t lane) {
+// Lane l's subquery entry of a task (l < its count): the index of its
+// query's rectangle.
+__device__ __forceinline__ uint32_t sq_entry(const uint32_t *__restrict__ sq, const uint4 rec,
+                                             uint32_t lane) {
   return sq[rec.x < rec.y ? min(rec.x + lane, rec.y - 1u) : 0u];
 }
 
@@ -1317,12 +1424,12 @@ template <uint32_t NCH>
 __device__ __forceinline__ uint32_t count_first(float4 *wrect, uint32_t nk,
                                                 const float2 *__restrict__ sxy, uint32_t ob,
                                                 uint32_t oe, const float4 *__restrict__ qrect,
-                                                uint2 e, uint32_t lane, float4 *r) {
+                                                uint32_t e, uint32_t lane, float4 *r) {
   float2 p[NCH];
   uint64_t h[NCH];
   load_chunks<NCH>(sxy, ob, oe, lane, p, h);
   if (lane < nk) {
-    *r = qrect[e.x];
+    *r = qrect[e];
     wrect[lane] = *r;
   }
   wave_lds_fence();
@@ -1337,12 +1444,12 @@ constexpr uint64_t kLowHalf = 0xffffffffull;
 __device__ __forceinline__ uint32_t count_half(float4 *wrect, uint32_t nk,
                                                const float2 *__restrict__ sxy, uint32_t ob,
                                                uint32_t oe, const float4 *__restrict__ qrect,
-                                               uint2 e, uint32_t lane, float4 *r) {
+                                               uint32_t e, uint32_t lane, float4 *r) {
   const uint32_t half = lane >> 5, i = ob + (lane & 31u);
   const uint64_t h = ballot(i < oe);
   const float2 p = sxy[min(i, oe - 1u)];
   if (lane < nk) {
-    *r = qrect[e.x];
+    *r = qrect[e];
     wrect[lane] = *r;
   }
   wave_lds_fence();
@@ -1372,9 +1479,9 @@ __device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk
 // latency; this kernel fits without spilling registers to memory.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uint32_t *leaf_sqoff,
-             const uint2 *__restrict__ sq, const float4 *__restrict__ qrect,
+             const uint32_t *__restrict__ sq, const float4 *__restrict__ qrect,
              const float2 *__restrict__ sxy, uint32_t *sq_cnt, float *tlog, const uint32_t *lstart,
-             const uint32_t *llevel) {
+             const uint32_t *llevel, uint64_t *cu_tests) {
   __shared__ float4 lrect[kBlock];
   if (!ctl->go_split) return;
   const uint32_t nt = ctl->n_run;
@@ -1387,12 +1494,12 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
   const uint32_t *trec32 = (const uint32_t *)trec;
   uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
   uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
-  uint2 ea = sq_entry(sq, rec, lane), eb;
+  uint32_t ea = sq_entry(sq, rec, lane), eb;
   // one step per task: the next task's entries and the record after it are
   // loaded first; the record is read out after this task's own loads have
   // been waited for, so no wait is spent on it.  The entry registers
   // alternate roles, so none is copied (a copy would wait for its load).
-  auto step = [&](uint32_t t, const uint2 e, uint2 &enx) {
+  auto step = [&](uint32_t t, const uint32_t e, uint32_t &enx) {
     enx = sq_entry(sq, rn, lane);
     const uint32_t recv = rec_load(trec32, t + 2u * nwaves, nt, lane);
     const uint32_t sb = rec.x, se = rec.y, ob = rec.z, oe = rec.w;
@@ -1404,6 +1511,8 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
     const uint32_t leaf = tlog ? tleaf[t] : 0u;
     const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
     const uint32_t nk = se - sb;  // at most kTaskSub
+    if (cu_tests && lane == 0)
+      atomicAdd((unsigned long long *)&cu_tests[cu_slot()], (unsigned long long)nk * (oe - ob));
     float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t cnt = 0;
     wave_lds_fence();
@@ -1423,10 +1532,10 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
                            : count_block<8>(wrect, nk, sxy, o0, oe, lane);
       }
     } else if (tlog && lane < nk) {
-      r = qrect[e.x];
+      r = qrect[e];
     }
     rn = rec_read(recv, t + 2u * nwaves, nt);
-    if (lane < nk) sq_cnt[e.y] = cnt;
+    if (lane < nk) sq_cnt[sb + lane] = cnt;
     if (tlog) {  // a leaf's record sums its tasks: mean overlap, clock ticks
       const float ovl = wave_sum(lane < nk ? overlap_frac(ctl, lstart, llevel, leaf, r) : 0.0f);
       const uint64_t clk1 = __builtin_amdgcn_s_memrealtime();
@@ -1447,24 +1556,28 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
 // Top of the result-offset scan: total result ids, reductions of the
 // tick's partials, result capacity check, and the automatic rebuild
 // decision for the next tick.
+// sqb: the results were appended by the baseline filter, whose global
+// counter holds their total (no scan).
 __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jobs, uint64_t *part,
                                                            const uint64_t *red, uint64_t cap_res,
-                                                           uint32_t policy, uint32_t period) {
+                                                           uint32_t policy, uint32_t period,
+                                                           uint32_t sqb) {
   __shared__ uint64_t lds[kChunkBlocks / kWave + 1];
   __shared__ uint32_t ldm[kChunkBlocks / kWave + 1];
   const bool ok = ctl->go_split != 0;
   const int t = threadIdx.x;
   // every partial is loaded before the first scan waits on a barrier
-  const uint64_t p_res = ok ? part[t] : 0u;
+  const uint64_t p_res = ok && !sqb ? part[t] : 0u;
   const uint64_t p_covp = red[kRedCovPairs * kChunkBlocks + t];
   const uint64_t p_tests = red[kRedTests * kChunkBlocks + t];
   const uint64_t p_tasks = red[kRedTasks * kChunkBlocks + t];
   const uint32_t p_mx = (uint32_t)red[kRedMaxLeaf * kChunkBlocks + t];
   uint64_t total = 0;
-  if (ok) {
+  if (ok && !sqb) {
     part[t] = block_excl_scan<uint64_t, kChunkBlocks>(p_res, lds, &total);
     if (t == 0) job_store(jobs.j[0], job_n(jobs.j[0]), total);
   }
+  if (sqb) total = ctl->n_res;
   uint64_t covp, tests, tasks;
   block_excl_scan<uint64_t, kChunkBlocks>(p_covp, lds, &covp);
   block_excl_scan<uint64_t, kChunkBlocks>(p_tests, lds, &tests);
@@ -1477,7 +1590,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
   if (ok) {
     ctl->n_res = total;
     ctl->cov_pairs = covp;
-    if (total > cap_res) {
+    if (total > cap_res || (sqb && (ctl->err & kErrOvfRes))) {
       ctl->err |= kErrOvfRes;
       ctl->go_join = 0;
     } else {
@@ -1518,17 +1631,17 @@ __device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint3
                                             const float2 *__restrict__ sxy,
                                             const uint32_t *__restrict__ sid, uint32_t ob,
                                             uint32_t oe, const float4 *__restrict__ qrect,
-                                            const uint64_t *__restrict__ res_off, uint2 e,
-                                            uint32_t lane, uint32_t *__restrict__ res_ids,
-                                            bool more) {
+                                            const uint64_t *__restrict__ res_off, uint32_t e,
+                                            uint32_t sb, uint32_t lane,
+                                            uint32_t *__restrict__ res_ids, bool more) {
   float2 p[NCH];
   uint64_t h[NCH];
   uint32_t id[NCH];
   load_chunks<NCH>(sxy, ob, oe, lane, p, h);
   load_ids<NCH>(sid, ob, oe, lane, id);
   if (lane < nk) {
-    const float4 r = qrect[e.x];
-    woff[lane] = res_off[e.y];
+    const float4 r = qrect[e];
+    woff[lane] = res_off[sb + lane];
     wrect[lane] = r;
   }
   wave_lds_fence();
@@ -1541,15 +1654,16 @@ __device__ __forceinline__ void write_half(float4 *wrect, uint64_t *woff, uint32
                                            const float2 *__restrict__ sxy,
                                            const uint32_t *__restrict__ sid, uint32_t ob,
                                            uint32_t oe, const float4 *__restrict__ qrect,
-                                           const uint64_t *__restrict__ res_off, uint2 e,
-                                           uint32_t lane, uint32_t *__restrict__ res_ids) {
+                                           const uint64_t *__restrict__ res_off, uint32_t e,
+                                           uint32_t sb, uint32_t lane,
+                                           uint32_t *__restrict__ res_ids) {
   const uint32_t half = lane >> 5, i = min(ob + (lane & 31u), oe - 1u);
   const uint64_t h = ballot(ob + (lane & 31u) < oe);
   const float2 p = sxy[i];
   const uint32_t id = sid[i];
   if (lane < nk) {
-    const float4 r = qrect[e.x];
-    woff[lane] = res_off[e.y];
+    const float4 r = qrect[e];
+    woff[lane] = res_off[sb + lane];
     wrect[lane] = r;
   }
   wave_lds_fence();
@@ -1578,16 +1692,19 @@ __device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff,
   write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
 }
 
+// The write pass puts the results of the subqueries in subquery order: task
+// by task, the runs of a task's subqueries are adjacent, so the pass stores
+// its ids as one contiguous stream and reads its offsets in order; a
+// query's results are its slots' runs (slot_sq).
 __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
                                                        const uint32_t *tleaf,
-                                                       const uint2 *__restrict__ sq,
+                                                       const uint32_t *__restrict__ sq,
                                                        const float4 *__restrict__ qrect,
                                                        const float2 *__restrict__ sxy,
                                                        const uint32_t *__restrict__ sid,
                                                        const uint64_t *__restrict__ res_off,
                                                        uint32_t *__restrict__ res_ids,
-                                                       uint32_t nq, const uint32_t *q_ioff,
-                                                       uint64_t *q_roff, float *tlog) {
+                                                       uint32_t nq, float *tlog) {
   __shared__ float4 lrect[kBlock];
   __shared__ uint64_t loff[kBlock];
   const bool go = ctl->go_join != 0;
@@ -1595,15 +1712,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     ctl->qry_seq += nq;
     ctl->tick += 1;
   }
-  // per-query offsets of the intersecting results, after this wave's tasks
-  auto query_offsets = [&]() {
-    for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k <= nq; k += gridDim.x * kBlock)
-      q_roff[k] = go ? res_off[k < nq ? q_ioff[k] : ctl->n32[0]] : 0ull;
-  };
-  if (!go) {
-    query_offsets();
-    return;
-  }
+  if (!go) return;
   const uint32_t nt = ctl->n_run;
   const uint32_t lane = lane_id();
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
@@ -1611,62 +1720,63 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint64_t *woff = loff + (threadIdx.x & ~(uint32_t)(kWave - 1));
-  if (w0 < nt) {
-    const uint32_t *trec32 = (const uint32_t *)trec;
-    uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
-    uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
-    uint2 ea = sq_entry(sq, rec, lane), eb;
-    auto step = [&](uint32_t t, const uint2 e, uint2 &enx) {
-      enx = sq_entry(sq, rn, lane);
-      const uint32_t recv = rec_load(trec32, t + 2u * nwaves, nt, lane);
-      const uint32_t sb = rec.x, se = rec.y, ob = rec.z, oe = rec.w;
-      rec = rn;
-      if (sb >= se || ob >= oe) {
-        rn = rec_read(recv, t + 2u * nwaves, nt);
-        return;
-      }
-      const uint32_t leaf = tlog ? tleaf[t] : 0u;
-      const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
-      const uint32_t nk = se - sb;  // at most kTaskSub
-      const uint32_t nch = chunk_count(ob, oe);
-      const bool more = ob + (uint32_t)kWave * kJoinRegChunks < oe;
-      wave_lds_fence();
-      if (oe - ob <= 32u)
-        write_half(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids);
-      else if (nch <= 1u)
-        write_first<1>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
-      else if (nch <= 2u)
-        write_first<2>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
-      else if (nch <= 4u)
-        write_first<4>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
-      else
-        write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, lane, res_ids, more);
+  if (w0 >= nt) return;
+  const uint32_t *trec32 = (const uint32_t *)trec;
+  uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
+  uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
+  uint32_t ea = sq_entry(sq, rec, lane), eb;
+  auto step = [&](uint32_t t, const uint32_t e, uint32_t &enx) {
+    enx = sq_entry(sq, rn, lane);
+    const uint32_t recv = rec_load(trec32, t + 2u * nwaves, nt, lane);
+    const uint32_t sb = rec.x, se = rec.y, ob = rec.z, oe = rec.w;
+    rec = rn;
+    if (sb >= se || ob >= oe) {
       rn = rec_read(recv, t + 2u * nwaves, nt);
-      for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
-           o0 += (uint32_t)kWave * kJoinRegChunks) {
-        const uint32_t nc2 = chunk_count(o0, oe);
-        const bool more2 = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
-        wave_lds_fence();
-        if (nc2 <= 1u)
-          write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-        else if (nc2 <= 2u)
-          write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-        else if (nc2 <= 4u)
-          write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-        else
-          write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-      }
-      if (tlog && lane == 0)
-        atomicAdd(&tlog[(uint64_t)leaf * 8 + 5],
-                  (float)(__builtin_amdgcn_s_memrealtime() - clk0));
-    };
-    for (uint32_t t = w0; t < nt; t += 2u * nwaves) {
-      step(t, ea, eb);
-      if (t + nwaves >= nt) break;
-      step(t + nwaves, eb, ea);
+      return;
     }
+    const uint32_t leaf = tlog ? tleaf[t] : 0u;
+    const uint64_t clk0 = tlog ? __builtin_amdgcn_s_memrealtime() : 0;
+    const uint32_t nk = se - sb;  // at most kTaskSub
+    const uint32_t nch = chunk_count(ob, oe);
+    const bool more = ob + (uint32_t)kWave * kJoinRegChunks < oe;
+    wave_lds_fence();
+    if (oe - ob <= 32u)
+      write_half(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids);
+    else if (nch <= 1u)
+      write_first<1>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
+                     more);
+    else if (nch <= 2u)
+      write_first<2>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
+                     more);
+    else if (nch <= 4u)
+      write_first<4>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
+                     more);
+    else
+      write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
+                     more);
+    rn = rec_read(recv, t + 2u * nwaves, nt);
+    for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
+         o0 += (uint32_t)kWave * kJoinRegChunks) {
+      const uint32_t nc2 = chunk_count(o0, oe);
+      const bool more2 = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
+      wave_lds_fence();
+      if (nc2 <= 1u)
+        write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+      else if (nc2 <= 2u)
+        write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+      else if (nc2 <= 4u)
+        write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+      else
+        write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+    }
+    if (tlog && lane == 0)
+      atomicAdd(&tlog[(uint64_t)leaf * 8 + 5], (float)(__builtin_amdgcn_s_memrealtime() - clk0));
+  };
+  for (uint32_t t = w0; t < nt; t += 2u * nwaves) {
+    step(t, ea, eb);
+    if (t + nwaves >= nt) break;
+    step(t + nwaves, eb, ea);
   }
-  query_offsets();
 }
 
 // --------------------------------------------------------------- results --
@@ -1692,95 +1802,13 @@ __global__ void k_counters(const Ctl *ctl, uint64_t *out) {
   out[7] = ctl->err;
 }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  return z ^ (z >> 31);
-}
-
-__global__ void __launch_bounds__(kBlock) k_hash(const Ctl *ctl, uint32_t nq, const uint32_t *qid,
-                                                 const uint64_t *q_roff, const uint32_t *res_ids,
-                                                 const uint32_t *q_coff, const uint32_t *cov_leaf,
-                                                 const uint32_t *leaf_beg, const uint32_t *sid,
-                                                 uint64_t *out_cnt, uint64_t *out_hash) {
-  const uint32_t lane = lane_id();
-  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-  const bool ok = ctl->go_join != 0;
-  for (uint32_t k = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; k < nq; k += nwaves) {
-    if (!ok) {
-      if (lane == 0) out_cnt[k] = out_hash[k] = 0ull;
-      continue;
-    }
-    const uint64_t hi = (uint64_t)qid[k] << 32;
-    uint64_t h = 0, c = 0;
-    for (uint64_t i = q_roff[k] + lane; i < q_roff[k + 1]; i += kWave) {
-      h += mix64(hi | res_ids[i]);
-      ++c;
-    }
-    for (uint32_t e = q_coff[k]; e < q_coff[k + 1]; ++e) {
-      const uint32_t leaf = cov_leaf[e];
-      for (uint32_t i = leaf_beg[leaf] + lane; i < leaf_beg[leaf + 1]; i += kWave) {
-        h += mix64(hi | sid[i]);
-        ++c;
-      }
-    }
-    h = wave_sum(h);
-    c = wave_sum(c);
-    if (lane == 0) {
-      out_cnt[k] = c;
-      out_hash[k] = h;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_exp_count(const Ctl *ctl, uint32_t nq,
-                                                      const uint64_t *q_roff,
-                                                      const uint32_t *q_coff,
-                                                      const uint32_t *cov_leaf,
-                                                      const uint32_t *leaf_beg, uint32_t *cnt) {
-  const bool ok = ctl->go_join != 0;
-  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
-    if (!ok) {
-      cnt[k] = 0u;
-      continue;
-    }
-    uint64_t c = q_roff[k + 1] - q_roff[k];
-    for (uint32_t e = q_coff[k]; e < q_coff[k + 1]; ++e)
-      c += leaf_beg[cov_leaf[e] + 1] - leaf_beg[cov_leaf[e]];
-    cnt[k] = (uint32_t)c;
-  }
-}
-
-__global__ void __launch_bounds__(kBlock) k_exp_write(const Ctl *ctl, uint32_t nq,
-                                                      const uint64_t *q_roff,
-                                                      const uint32_t *res_ids,
-                                                      const uint32_t *q_coff,
-                                                      const uint32_t *cov_leaf,
-                                                      const uint32_t *leaf_beg,
-                                                      const uint32_t *sid, const uint64_t *off,
-                                                      uint32_t *ids) {
-  if (!ctl->go_join) return;
-  const uint32_t lane = lane_id();
-  const uint32_t nwaves = gridDim.x * kWavesPerBlock;
-  for (uint32_t k = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; k < nq; k += nwaves) {
-    uint64_t dst = off[k];
-    const uint64_t a = q_roff[k], b = q_roff[k + 1];
-    for (uint64_t i = a + lane; i < b; i += kWave) ids[dst + (i - a)] = res_ids[i];
-    dst += b - a;
-    for (uint32_t e = q_coff[k]; e < q_coff[k + 1]; ++e) {
-      const uint32_t leaf = cov_leaf[e];
-      const uint32_t lb = leaf_beg[leaf], le = leaf_beg[leaf + 1];
-      for (uint32_t i = lb + lane; i < le; i += kWave) ids[dst + (i - lb)] = sid[i];
-      dst += le - lb;
-    }
-  }
-}
-
 // ------------------------------------------------------- host launchers --
 
 #define LAUNCH(k, g, b, s, ...) hipLaunchKernelGGL(k, dim3(g), dim3(b), 0, s, __VA_ARGS__)
 
-void launch_ctl_init(Ctl *ctl, uint32_t th, hipStream_t s) { LAUNCH(k_ctl_init, 1, 1, s, ctl, th); }
+void launch_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits, hipStream_t s) {
+  LAUNCH(k_ctl_init, 1, 1, s, ctl, th, ug_split, ug_bits);
+}
 void launch_request_build(Ctl *ctl, uint32_t th, hipStream_t s) {
   LAUNCH(k_request_build, 1, 1, s, ctl, th);
 }
@@ -1879,11 +1907,10 @@ void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
 void launch_leaves(const Bufs &B, hipStream_t s) {
   // a thread per leaf (binary searches) or per sorted object (one pass)
   LAUNCH(k_leaf_ranges, grid_for(B.LCAP > B.N ? B.LCAP : B.N, 4096), kBlock, s, (const Ctl *)B.ctl,
-         (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg, B.leaf_nsq, B.leaf_ovf,
-         B.leaf_ovfc);
+         (const uint32_t *)B.keyA, (const uint32_t *)B.lstart, B.leaf_beg);
 }
 
-void launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipStream_t s) {
+const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipStream_t s) {
   const TickIn *tin = B.tin;
   const uint32_t *qord = nullptr;
   if (nq >= kQueryOrderMin) {
@@ -1894,20 +1921,27 @@ void launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipStream_t s) 
   }
   LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, tin, nq, B.N,
          (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
-         B.q_nc, B.leaf_nsq, B.leaf_ovf, B.qlist, B.qpos, B.slots, covering, qord);
+         B.q_nc, B.qlist, B.slots, covering, qord);
   ScanJobs jobs{};
   jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
   jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
-  jobs.j[2] = job_u32(B.leaf_nsq, B.leaf_sqoff, &B.ctl->n_leaves, 0, B.leaf_ovf);
-  mscan_reduce(jobs, 3, B.part, nullptr, s);
+  mscan_reduce(jobs, 2, B.part, nullptr, s);
   LAUNCH(k_split_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, B.S, B.C);
-  mscan_down(jobs, 3, (const uint64_t *)B.part, nullptr, s);
+  mscan_down(jobs, 2, (const uint64_t *)B.part, nullptr, s);
+  // subqueries in slot order: leaf keys in sq_cnt, slots in sq, rectangle
+  // indices in slot_sq; the sort by leaf ping-pongs through res_off's
+  // memory and ends where it started
+  uint32_t *skey = B.sq_cnt, *sval = B.sq, *k1 = (uint32_t *)B.res_off, *v1 = k1 + B.S;
   LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
-         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, (const uint32_t *)B.qpos, B.slots,
-         (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.leaf_nsq, B.leaf_ovfc, B.sq,
+         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots, skey, sval, B.slot_sq,
          B.cov_leaf, covering, B.red, qord);
+  radix_sort_pairs(skey, sval, k1, v1, &B.ctl->n32[0], B.S, &B.ctl->go_split, B.hist, B.tot, 0,
+                   32, s, nullptr, nullptr, &B.ctl->sq_skip);
+  LAUNCH(k_sq_final, grid_for(B.S, 4096), kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)skey,
+         (const uint32_t *)sval, B.sq, B.slot_sq, B.leaf_sqoff);
+  return qord;
 }
 
 void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learned,
@@ -1924,9 +1958,9 @@ void launch_schedule(const Bufs &B, uint32_t reorder, uint32_t l_max, bool learn
 
 void launch_join_count(const Bufs &B, hipStream_t s) {
   LAUNCH(k_join_count, kJoinBlocks, kBlock, s, (const Ctl *)B.ctl, (const uint4 *)B.trec,
-         (const uint32_t *)B.tleaf, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
+         (const uint32_t *)B.tleaf, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq,
          (const float4 *)B.qrect, (const float2 *)B.sxy, B.sq_cnt,
-         B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel);
+         B.tlog, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.cu_tests);
 }
 
 void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
@@ -1935,15 +1969,23 @@ void launch_join_scan(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t
   jobs.j[0] = job_u64(B.sq_cnt, B.res_off, &B.ctl->n32[0], 0);
   mscan_reduce(jobs, 1, B.part, &B.ctl->go_split, s);
   LAUNCH(k_join_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, (const uint64_t *)B.red, cap_res,
-         policy, period);
+         policy, period, 0u);
   mscan_down(jobs, 1, (const uint64_t *)B.part, &B.ctl->go_split, s);
+}
+
+void launch_join_top_sqb(const Bufs &B, uint64_t cap_res, uint32_t policy, uint32_t period,
+                         hipStream_t s) {
+  ScanJobs jobs{};
+  jobs.j[0] = job_u64(B.sq_cnt, B.res_off, &B.ctl->n32[0], 0);
+  LAUNCH(k_join_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, (const uint64_t *)B.red, cap_res,
+         policy, period, 1u);
 }
 
 void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
   LAUNCH(k_join_write, kJoinBlocks, kBlock, s, B.ctl, (const uint4 *)B.trec,
-         (const uint32_t *)B.tleaf, (const uint2 *)B.sq, (const float4 *)B.qrect,
-         (const float2 *)B.sxy, (const uint32_t *)B.valA,
-         (const uint64_t *)B.res_off, B.res_ids, nq, (const uint32_t *)B.q_ioff, B.q_roff, B.tlog);
+         (const uint32_t *)B.tleaf, (const uint32_t *)B.sq, (const float4 *)B.qrect,
+         (const float2 *)B.sxy, (const uint32_t *)B.valA, (const uint64_t *)B.res_off, B.res_ids,
+         nq, B.tlog);
 }
 
 const void *join_write_kernel() { return reinterpret_cast<const void *>(&k_join_write); }
@@ -1954,30 +1996,6 @@ void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s) {
 
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s) {
   LAUNCH(k_counters, 1, 1, s, (const Ctl *)B.ctl, out);
-}
-
-void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt, uint64_t *hash,
-                 hipStream_t s) {
-  LAUNCH(k_hash, grid_for((uint64_t)nq * kWave, 4096), kBlock, s, (const Ctl *)B.ctl, nq, qid,
-         (const uint64_t *)B.q_roff, (const uint32_t *)B.res_ids, (const uint32_t *)B.q_coff,
-         (const uint32_t *)B.cov_leaf, (const uint32_t *)B.leaf_beg, (const uint32_t *)B.valA,
-         cnt, hash);
-}
-
-void launch_expand_count(const Bufs &B, uint32_t nq, uint64_t *off, hipStream_t s) {
-  LAUNCH(k_exp_count, grid_for(nq, 4096), kBlock, s, (const Ctl *)B.ctl, nq,
-         (const uint64_t *)B.q_roff, (const uint32_t *)B.q_coff, (const uint32_t *)B.cov_leaf,
-         (const uint32_t *)B.leaf_beg, B.q_ni);
-  ScanJobs jobs{};
-  jobs.j[0] = job_u64(B.q_ni, off, nullptr, nq);
-  mscan(jobs, 1, B.part, nullptr, nullptr, s);
-}
-
-void launch_expand(const Bufs &B, uint32_t nq, uint64_t *off, uint32_t *ids, hipStream_t s) {
-  LAUNCH(k_exp_write, grid_for((uint64_t)nq * kWave, 4096), kBlock, s, (const Ctl *)B.ctl, nq,
-         (const uint64_t *)B.q_roff, (const uint32_t *)B.res_ids, (const uint32_t *)B.q_coff,
-         (const uint32_t *)B.cov_leaf, (const uint32_t *)B.leaf_beg, (const uint32_t *)B.valA,
-         (const uint64_t *)off, ids);
 }
 
 }  // namespace sj

@@ -95,11 +95,11 @@ __device__ __forceinline__ float wave_mlp(const MlpLds &m, float x0, float x1, f
 // of the leaf's area their rectangle covers (whole wave).
 __device__ __forceinline__ float mean_overlap(const Ctl *ctl, const uint32_t *lstart,
                                               const uint32_t *llevel, uint32_t t, uint32_t sb,
-                                              uint32_t se, const uint2 *sq,
+                                              uint32_t se, const uint32_t *sq,
                                               const float4 *qrect) {
   float ov = 0.0f;
   for (uint32_t i = sb + lane_id(); i < se; i += kWave)
-    ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq[i].x]);
+    ov += overlap_frac(ctl, lstart, llevel, t, qrect[sq[i]]);
   return wave_sum(ov) / (float)(se - sb);
 }
 
@@ -109,7 +109,7 @@ __device__ __forceinline__ float mean_overlap(const Ctl *ctl, const uint32_t *ls
 __global__ void __launch_bounds__(kBlock) k_cost_leaves(const Ctl *ctl, const TuneState *ts,
                                                         const uint32_t *leaf_beg,
                                                         const uint32_t *leaf_sqoff,
-                                                        const uint2 *sq, const float4 *qrect,
+                                                        const uint32_t *sq, const float4 *qrect,
                                                         const uint32_t *lstart,
                                                         const uint32_t *llevel, uint64_t *red) {
   __shared__ MlpLds m;
@@ -168,7 +168,7 @@ __device__ __forceinline__ uint32_t time_key(float y) {
 __global__ void __launch_bounds__(kBlock) k_task_keys_mlp(const Ctl *ctl, const TuneState *ts,
                                                           const uint32_t *leaf_beg,
                                                           const uint32_t *leaf_sqoff,
-                                                          const uint2 *sq,
+                                                          const uint32_t *sq,
                                                           const float4 *qrect,
                                                           const uint32_t *lstart,
                                                           const uint32_t *llevel,
@@ -271,7 +271,7 @@ __global__ void k_tune_pick(Ctl *ctl, TuneState *ts, uint4 *front0) {
 
 void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
   LAUNCH(k_task_keys_mlp, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
-         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
+         (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq,
          (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel,
          (const uint32_t *)B.xbase, B.TCAP, B.tkey, B.tkhist);
 }
@@ -285,7 +285,7 @@ void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, ui
     launch_leaves(B, s);
     launch_split(B, nq, covering, s);
     LAUNCH(k_cost_leaves, kChunkBlocks, kBlock, s, (const Ctl *)B.ctl, (const TuneState *)B.tune,
-           (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint2 *)B.sq,
+           (const uint32_t *)B.leaf_beg, (const uint32_t *)B.leaf_sqoff, (const uint32_t *)B.sq,
            (const float4 *)B.qrect, (const uint32_t *)B.lstart, (const uint32_t *)B.llevel, B.red);
     LAUNCH(k_tune_cost, 1, kChunkBlocks, s, (const Ctl *)B.ctl, B.tune, c,
            (const uint64_t *)B.red);

@@ -224,7 +224,8 @@ def test_outputs_are_deterministic_and_expand_matches():
         sc = run_scene(wl.n, t, th=16)
         r = sc.fetch()
         outs.append([x.cpu().numpy().tobytes() for x in
-                     (r.isect_off, r.isect_id, r.cov_off, r.cov_leaf, r.leaf_beg, r.sorted_id)])
+                     (r.isect_slot_off, r.slot_run, r.run_off, r.isect_id, r.cov_off, r.cov_leaf,
+                      r.leaf_beg, r.sorted_id)])
         off, ids = sc.expand()
         off, ids = off.cpu().numpy(), ids.cpu().numpy()
         assert [sorted(ids[off[k]:off[k + 1]].tolist()) for k in range(t.nq)] == want
@@ -420,8 +421,10 @@ def test_graph_ticks_equal_eager_ticks():
         if k % 2 == 1:  # ticks the host has not fetched: device decides
             continue
         re, rg = eager.fetch(), graph.fetch()
-        for a, b in zip((re.isect_off, re.isect_id, re.cov_off, re.cov_leaf, re.leaf_beg),
-                        (rg.isect_off, rg.isect_id, rg.cov_off, rg.cov_leaf, rg.leaf_beg)):
+        for a, b in zip((re.isect_slot_off, re.slot_run, re.run_off, re.isect_id, re.cov_off,
+                         re.cov_leaf, re.leaf_beg),
+                        (rg.isect_slot_off, rg.slot_run, rg.run_off, rg.isect_id, rg.cov_off,
+                         rg.cov_leaf, rg.leaf_beg)):
             assert torch.equal(a, b)
         cnt, h = gpu_count_hash(graph)
         oc, oh = oracle_count_hash(st, t, grid=False)
