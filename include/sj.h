@@ -410,17 +410,27 @@ int sj_index_view_get(sj_scene *scene, sj_index_view *out);
  * batching of ticks and the latency definitions of Section "Problem
  * setting and statement": latency = queueing + processing).
  *
- * The server carves every admitted scene's workspace and output slots
+ * The server carves every resident scene's workspace and output slots
  * from one caller-owned device pool with its own first-fit
  * allocator: admission succeeds while the scene fits (an HBM budget), and
- * retiring a scene returns its memory.  Every scene has its own stream.
- * Tick requests queue per scene in submission order; sj_server_poll
- * retires finished ticks and starts queued ones, up to max_running at
- * once, so ticks of different scenes overlap on the device.  A tick replays
- * the scene's captured graph (sj_tick_graph) on the request's own input
- * arrays, then writes per-query counts and pair-set hashes
- * (sj_result_hashes) and the tick counters (sj_tick_counters) into the
- * scene's output slots.  Not thread-safe.
+ * retiring or evicting a scene returns its memory.  Every scene has its own
+ * stream.  Tick requests queue per scene in submission order;
+ * sj_server_poll retires finished ticks and starts queued ones, up to
+ * max_running at once, so ticks of different scenes overlap on the device.
+ * A tick replays the scene's captured graph (sj_tick_graph) on the
+ * request's own input arrays, then writes per-query counts and pair-set
+ * hashes (sj_result_hashes) and the tick counters (sj_tick_counters) into
+ * the scene's output slots.
+ *
+ * Eviction: a scene's results depend only on the last-known positions of
+ * its objects (Definition 1), so an idle scene can leave the device as a
+ * host copy of its positions (with its configuration and current leaf
+ * threshold) and come back later with the same results.  Scenes added with
+ * sj_server_add are admitted on demand when a request of theirs comes up,
+ * and evicted when idle (least recently used first) to make room for
+ * another; sj_server_evict evicts any idle scene explicitly.  A re-admitted
+ * scene builds a new quadtree on its next tick and forgets a cost model set
+ * on it (its tuned threshold is kept).  Not thread-safe.
  * ------------------------------------------------------------------------ */
 typedef struct sj_server sj_server;
 
@@ -437,7 +447,11 @@ typedef struct sj_served {
 
 typedef struct sj_server_stats {
   uint64_t pool_bytes, pool_used;
-  uint32_t scenes, running, queued;
+  uint32_t scenes;      /* registered scenes (resident or evicted) */
+  uint32_t running, queued;
+  uint32_t resident;    /* scenes holding pool memory */
+  uint32_t admissions;  /* scenes made resident so far (re-admissions included) */
+  uint32_t evictions;   /* scenes moved to host memory so far */
 } sj_server_stats;
 
 /* Device bytes a scene takes from the pool (workspace + output slots). */
@@ -452,6 +466,19 @@ int sj_server_destroy(sj_server *server);
  * now; SJ_ENOSPACE otherwise (nothing is reserved; try again later). */
 int sj_server_admit(sj_server *server, const sj_config *cfg, uint32_t max_updates,
                     uint32_t *scene_id);
+
+/* Registers a scene that is made resident when its first request comes up
+ * (evicting idle scenes added this way if the pool is full) and may be
+ * evicted when idle.  SJ_ENOSPACE if it is larger than the whole pool. */
+int sj_server_add(sj_server *server, const sj_config *cfg, uint32_t max_updates,
+                  uint32_t *scene_id);
+
+/* Moves a resident scene with no tick running to host memory (pinned; its
+ * positions, configuration and current threshold) and returns its pool
+ * memory; synchronises its stream.  Its queued requests stay queued and
+ * bring it back.  The result views of its last tick (sj_served, the scene
+ * object) become invalid.  SJ_ESTATE if it is not resident or runs a tick. */
+int sj_server_evict(sj_server *server, uint32_t scene_id);
 
 /* Releases an idle scene (no tick queued or running) and its memory. */
 int sj_server_retire(sj_server *server, uint32_t scene_id);
@@ -473,13 +500,17 @@ int sj_server_submit(sj_server *server, uint32_t scene_id, const uint32_t *d_id,
                      uint32_t flags);
 
 /* Retires finished ticks (at most cap, written to done[0 .. *n_done)) and
- * starts queued ticks in submission order.  Non-blocking. */
+ * starts queued ticks in submission order, admitting scenes that are not
+ * resident (and evicting idle scenes added with sj_server_add, least
+ * recently used first, but none whose tick this call retired).  The outputs
+ * of a retired tick of such a scene stay valid until the next poll.
+ * Non-blocking. */
 int sj_server_poll(sj_server *server, sj_served *done, uint32_t cap, uint32_t *n_done);
 
 int sj_server_info(const sj_server *server, sj_server_stats *out);
 
-/* The scene object of an admitted scene (results of its last retired tick
- * stay readable until its next tick starts). */
+/* The scene object of a resident scene (results of its last retired tick
+ * stay readable until its next tick starts or it is evicted). */
 int sj_server_scene(sj_server *server, uint32_t scene_id, sj_scene **out);
 
 const char *sj_server_last_error(const sj_server *server);

@@ -89,7 +89,8 @@ class SjServed(Structure):
 
 class SjServerStats(Structure):
     _fields_ = [("pool_bytes", c_uint64), ("pool_used", c_uint64), ("scenes", c_uint32),
-                ("running", c_uint32), ("queued", c_uint32)]
+                ("running", c_uint32), ("queued", c_uint32), ("resident", c_uint32),
+                ("admissions", c_uint32), ("evictions", c_uint32)]
 
 
 EXPORTS = {
@@ -126,6 +127,8 @@ EXPORTS = {
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
                                  c_uint64, c_void_p, c_uint32]),
     "sj_server_poll": (c_int, [c_void_p, POINTER(SjServed), c_uint32, POINTER(c_uint32)]),
+    "sj_server_add": (c_int, [c_void_p, POINTER(SjConfig), c_uint32, POINTER(c_uint32)]),
+    "sj_server_evict": (c_int, [c_void_p, c_uint32]),
     "sj_server_info": (c_int, [c_void_p, POINTER(SjServerStats)]),
     "sj_server_scene": (c_int, [c_void_p, c_uint32, POINTER(c_void_p)]),
     "sj_server_last_error": (c_char_p, [c_void_p]),
@@ -543,6 +546,16 @@ class Server:
             return None
         self._check(rc)
         return int(sid.value)
+
+    def add(self, cfg: SjConfig, max_updates: int) -> int:
+        """Scene id of a scene admitted on demand and evicted when idle."""
+        sid = c_uint32()
+        self._check(self._lib.sj_server_add(self.handle, byref(cfg), max_updates, byref(sid)))
+        return int(sid.value)
+
+    def evict(self, sid: int):
+        """Moves an idle resident scene to host memory (sj_server_evict)."""
+        self._check(self._lib.sj_server_evict(self.handle, sid))
 
     def retire(self, sid: int):
         self._check(self._lib.sj_server_retire(self.handle, sid))

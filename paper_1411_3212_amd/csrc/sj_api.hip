@@ -993,6 +993,13 @@ void sj_scene_ctl_from_host(sj_scene *s, const Ctl *h_ctl) {
 
 int sj_scene_status(sj_scene *s) { return status_of(s, s->host_ctl.err); }
 
+int sj_scene_positions_copy(sj_scene *s, void *h_pos, int to_host) {
+  const size_t bytes = (size_t)s->B.N * sizeof(float2);
+  hipError_t e = to_host ? hipMemcpyAsync(h_pos, s->B.pos, bytes, hipMemcpyDeviceToHost, s->stream)
+                         : hipMemcpyAsync(s->B.pos, h_pos, bytes, hipMemcpyHostToDevice, s->stream);
+  return e == hipSuccess ? SJ_OK : hip_fail(s, e, "positions copy");
+}
+
 void sj_set_global_error(const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);

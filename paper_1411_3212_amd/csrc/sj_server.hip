@@ -1,17 +1,28 @@
 // Tick-serving runtime: many scenes, one device, continuous batching.
 //
-// Scenes are admitted while their memory fits in a caller-provided device
-// pool (first-fit allocator, 256-byte blocks, freed blocks coalesce).  Every
-// admitted scene has its own stream, a workspace, fixed input slots and
-// output slots carved from the pool.  Tick requests (device input buffers)
-// queue per scene in arrival order.  sj_server_poll retires finished ticks
-// and starts queued ones: a request starts when its scene has no tick in
-// flight and fewer than `max_running` ticks run; ticks of different scenes
-// overlap on the device.  A tick is: one copy kernel of the inputs into the
-// scene's slots, the scene's captured graph (updates + join), per-query
-// counts and pair-set hashes and the tick counters into the output slots,
-// an asynchronous copy of the control block to pinned host memory (so the
+// A resident scene holds a workspace and two sets of output slots carved
+// from a caller-provided device pool (first-fit allocator, 256-byte blocks,
+// freed blocks coalesce), and has its own stream.  Tick requests (device
+// input buffers, read in place by the tick, so they stay valid until it is
+// retired) queue per scene in arrival order.  sj_server_poll retires
+// finished ticks and starts queued ones: a request starts when its scene has
+// no tick in flight and fewer than `max_running` ticks run; ticks of
+// different scenes overlap on the device.  A tick is: the scene's captured
+// graph (updates + join) on the request's arrays, per-query counts and
+// pair-set hashes and the tick counters into the output slots, an
+// asynchronous copy of the control block to pinned host memory (so the
 // quadtree decision of the next tick is known on the host), an event.
+//
+// Eviction: an idle scene can leave the device.  Its state that results
+// depend on, the last-known position of every object (Definition 1 reads
+// nothing else), is copied to pinned host memory, with its configuration
+// and current leaf threshold; its pool memory is returned.  When a request
+// of a scene that is not resident comes up in arrival order, the poll
+// admits it again (a new workspace, the positions copied back; its next
+// tick builds a quadtree), evicting least recently used idle scenes that
+// the server manages when the pool is full.  A scene that waits for memory
+// holds back the admission of scenes behind it, not the ticks of resident
+// scenes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -94,7 +105,10 @@ struct Request {
 };
 
 struct ServedScene {
-  bool live = false;
+  bool live = false;      // registered (admitted, or added to be admitted on demand)
+  bool resident = false;  // holds pool memory and a scene object
+  bool managed = false;   // the poll may evict it when idle
+  sj_config cfg{};        // as admitted; th_quad follows the scene's threshold
   sj_scene *scene = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -112,6 +126,10 @@ struct ServedScene {
   bool has_result = false;
   Request last{};
   int status = SJ_OK;
+  float2 *snap = nullptr;  // pinned host positions of an evicted scene
+  bool has_snap = false;
+  uint64_t last_use = 0;   // server clock at its last admission or retired tick
+  uint64_t retired_poll = 0;  // the poll that retired its last tick
 };
 
 // Tick record: the 8 tick counters, then the digest of the tick's results:
@@ -151,6 +169,9 @@ struct sj_server {
   PoolAlloc pool;
   uint32_t max_running = 4;
   uint32_t running = 0;
+  uint64_t clock = 0;
+  uint64_t polls = 0;
+  uint32_t admissions = 0, evictions = 0;
   std::vector<ServedScene> scenes;
   std::deque<std::pair<uint32_t, uint64_t>> order;  // (scene, tag) in arrival order
   char err[256] = "";
@@ -183,10 +204,11 @@ int sj_server_destroy(sj_server *s) {
   for (auto &sc : s->scenes) {
     if (!sc.live) continue;
     if (sc.stream) (void)hipStreamSynchronize(sc.stream);
-    sj_scene_destroy(sc.scene);
+    if (sc.resident) sj_scene_destroy(sc.scene);
     if (sc.done) (void)hipEventDestroy(sc.done);
     if (sc.stream) (void)hipStreamDestroy(sc.stream);
     if (sc.h_ctl) (void)hipHostFree(sc.h_ctl);
+    if (sc.snap) (void)hipHostFree(sc.snap);
   }
   delete s;
   return SJ_OK;
@@ -200,44 +222,111 @@ size_t sj_server_scene_bytes(const sj_config *cfg, uint32_t max_updates) {
   return align_up(ws) + 4 * align_up(8 * Q) + 2 * align_up(64);
 }
 
-int sj_server_admit(sj_server *s, const sj_config *cfg, uint32_t max_updates, uint32_t *scene_id) {
-  if (!s || !cfg || !scene_id) return SJ_EINVAL;
-  const size_t need = sj_server_scene_bytes(cfg, max_updates);
+// A registered scene's stream, completion event and pinned control block
+// (kept while it is evicted).
+static int scene_handles(ServedScene &sc) {
+  hipError_t e = hipStreamCreateWithFlags(&sc.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&sc.done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&sc.h_ctl, sizeof(Ctl), hipHostMallocDefault);
+  if (e == hipSuccess) return SJ_OK;
+  if (sc.done) (void)hipEventDestroy(sc.done);
+  if (sc.stream) (void)hipStreamDestroy(sc.stream);
+  sc.done = nullptr;
+  sc.stream = nullptr;
+  return SJ_EDEVICE;
+}
+
+// Pool memory, output slots and a scene object for a registered scene, with
+// the positions of its snapshot copied back (ordered before its next tick
+// on its stream).  SJ_ENOSPACE: the pool has no room now.
+static int make_resident(sj_server *s, ServedScene &sc) {
+  const size_t need = sj_server_scene_bytes(&sc.cfg, sc.max_updates);
   if (!need) return srv_fail(s, SJ_EINVAL, "admit: invalid scene configuration");
   uint8_t *mem = (uint8_t *)s->pool.alloc(need);
-  if (!mem) return srv_fail(s, SJ_ENOSPACE, "admit: the scene does not fit in the pool now");
-  ServedScene sc;
-  sc.mem = mem;
-  sc.mem_bytes = need;
-  sc.max_updates = max_updates;
-  sc.max_queries = cfg->capacity_queries;
-  const size_t ws = align_up(sj_workspace_bytes(cfg));
+  if (!mem) return SJ_ENOSPACE;
+  const size_t ws = align_up(sj_workspace_bytes(&sc.cfg));
   uint8_t *p = mem + ws;
   auto take = [&](size_t bytes) {
     uint8_t *r = p;
     p += align_up(bytes);
     return r;
   };
-  const size_t Q = cfg->capacity_queries;
+  const size_t Q = sc.cfg.capacity_queries;
   for (int b = 0; b < 2; ++b) {
     sc.o_cnt[b] = (uint64_t *)take(8 * Q);
     sc.o_hash[b] = (uint64_t *)take(8 * Q);
     sc.o_counters[b] = (uint64_t *)take(64);
   }
-  hipError_t e = hipStreamCreateWithFlags(&sc.stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&sc.done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&sc.h_ctl, sizeof(Ctl), hipHostMallocDefault);
-  if (e != hipSuccess) {
-    s->pool.release(mem, need);
-    return srv_fail(s, SJ_EDEVICE, "admit: stream/event/pinned allocation failed");
-  }
-  int rc = sj_scene_create(cfg, mem, ws, sc.stream, &sc.scene);
+  int rc = sj_scene_create(&sc.cfg, mem, ws, sc.stream, &sc.scene);
+  if (rc == SJ_OK && sc.has_snap) rc = sj_scene_positions_copy(sc.scene, sc.snap, 0);
   if (rc != SJ_OK) {
-    (void)hipEventDestroy(sc.done);
-    (void)hipStreamDestroy(sc.stream);
-    (void)hipHostFree(sc.h_ctl);
+    srv_fail(s, rc, sc.scene ? sj_last_error(sc.scene) : sj_last_error(nullptr));
+    if (sc.scene) sj_scene_destroy(sc.scene);
+    sc.scene = nullptr;
     s->pool.release(mem, need);
-    return srv_fail(s, rc, sj_last_error(nullptr));
+    return rc;
+  }
+  sc.mem = mem;
+  sc.mem_bytes = need;
+  sc.parity = 0;
+  sc.resident = true;
+  sc.last_use = ++s->clock;
+  s->admissions += 1;
+  return SJ_OK;
+}
+
+// Moves an idle resident scene to host memory: positions, configuration and
+// the threshold of its current quadtree; returns its pool memory.
+static int evict_scene(sj_server *s, ServedScene &sc) {
+  const size_t bytes = (size_t)sc.cfg.capacity_objects * sizeof(float2);
+  if (!sc.snap && hipHostMalloc((void **)&sc.snap, bytes, hipHostMallocDefault) != hipSuccess) {
+    sc.snap = nullptr;
+    return srv_fail(s, SJ_EDEVICE, "evict: pinned snapshot allocation failed");
+  }
+  sj_tick_stats st{};
+  const int rs = sj_stats(sc.scene, &st);  // synchronises the scene's stream
+  if (rs == SJ_EDEVICE) return srv_fail(s, rs, sj_last_error(sc.scene));
+  int rc = sj_scene_positions_copy(sc.scene, sc.snap, 1);
+  if (rc == SJ_OK && hipStreamSynchronize(sc.stream) != hipSuccess) rc = SJ_EDEVICE;
+  if (rc != SJ_OK) return srv_fail(s, rc, "evict: positions copy failed");
+  // keep the threshold (the workspace stays sized for the same smallest one)
+  if (!sc.cfg.th_min) sc.cfg.th_min = sc.cfg.th_quad ? sc.cfg.th_quad : 64u;
+  if (st.th >= sc.cfg.th_min) sc.cfg.th_quad = st.th;
+  sj_scene_destroy(sc.scene);
+  sc.scene = nullptr;
+  s->pool.release(sc.mem, sc.mem_bytes);
+  sc.mem = nullptr;
+  sc.resident = false;
+  sc.has_snap = true;
+  s->evictions += 1;
+  return SJ_OK;
+}
+
+// Registers a scene slot; resident: admit it now (SJ_ENOSPACE if it does
+// not fit), else it is admitted when its first request comes up.
+static int register_scene(sj_server *s, const sj_config *cfg, uint32_t max_updates, bool resident,
+                          uint32_t *scene_id) {
+  if (!s || !cfg || !scene_id) return SJ_EINVAL;
+  const size_t need = sj_server_scene_bytes(cfg, max_updates);
+  if (!need) return srv_fail(s, SJ_EINVAL, "admit: invalid scene configuration");
+  if (need > s->pool.size)
+    return srv_fail(s, SJ_ENOSPACE, "admit: the scene is larger than the whole pool");
+  ServedScene sc;
+  sc.cfg = *cfg;
+  sc.max_updates = max_updates;
+  sc.max_queries = cfg->capacity_queries;
+  sc.managed = !resident;
+  if (scene_handles(sc) != SJ_OK)
+    return srv_fail(s, SJ_EDEVICE, "admit: stream/event/pinned allocation failed");
+  if (resident) {
+    const int rc = make_resident(s, sc);
+    if (rc != SJ_OK) {
+      (void)hipEventDestroy(sc.done);
+      (void)hipStreamDestroy(sc.stream);
+      (void)hipHostFree(sc.h_ctl);
+      return rc == SJ_ENOSPACE ? srv_fail(s, rc, "admit: the scene does not fit in the pool now")
+                               : rc;
+    }
   }
   sc.live = true;
   uint32_t id = 0;
@@ -248,16 +337,35 @@ int sj_server_admit(sj_server *s, const sj_config *cfg, uint32_t max_updates, ui
   return SJ_OK;
 }
 
+int sj_server_admit(sj_server *s, const sj_config *cfg, uint32_t max_updates, uint32_t *scene_id) {
+  return register_scene(s, cfg, max_updates, true, scene_id);
+}
+
+int sj_server_add(sj_server *s, const sj_config *cfg, uint32_t max_updates, uint32_t *scene_id) {
+  return register_scene(s, cfg, max_updates, false, scene_id);
+}
+
+int sj_server_evict(sj_server *s, uint32_t id) {
+  if (!s || id >= s->scenes.size() || !s->scenes[id].live) return SJ_EINVAL;
+  ServedScene &sc = s->scenes[id];
+  if (!sc.resident) return srv_fail(s, SJ_ESTATE, "evict: the scene is not resident");
+  if (sc.running) return srv_fail(s, SJ_ESTATE, "evict: a tick of the scene is running");
+  return evict_scene(s, sc);
+}
+
 int sj_server_retire(sj_server *s, uint32_t id) {
   if (!s || id >= s->scenes.size() || !s->scenes[id].live) return SJ_EINVAL;
   ServedScene &sc = s->scenes[id];
   if (sc.running || !sc.queue.empty()) return srv_fail(s, SJ_ESTATE, "retire: ticks pending");
   (void)hipStreamSynchronize(sc.stream);
-  sj_scene_destroy(sc.scene);
+  if (sc.resident) {
+    sj_scene_destroy(sc.scene);
+    s->pool.release(sc.mem, sc.mem_bytes);
+  }
   (void)hipEventDestroy(sc.done);
   (void)hipStreamDestroy(sc.stream);
   (void)hipHostFree(sc.h_ctl);
-  s->pool.release(sc.mem, sc.mem_bytes);
+  if (sc.snap) (void)hipHostFree(sc.snap);
   sc = ServedScene();
   return SJ_OK;
 }
@@ -314,10 +422,13 @@ static int start_tick(sj_server *s, uint32_t id) {
   return rc;
 }
 
-// Retires finished ticks (up to cap reported) and starts queued ones.
+// Retires finished ticks (up to cap reported) and starts queued ones, in
+// arrival order, admitting scenes that are not resident (and evicting the
+// least recently used idle managed scenes to make room).
 int sj_server_poll(sj_server *s, sj_served *done, uint32_t cap, uint32_t *n_done) {
   if (!s || !n_done) return SJ_EINVAL;
   *n_done = 0;
+  const uint64_t poll = ++s->polls;
   for (uint32_t id = 0; id < s->scenes.size(); ++id) {
     ServedScene &sc = s->scenes[id];
     if (!sc.live || !sc.running) continue;
@@ -326,6 +437,8 @@ int sj_server_poll(sj_server *s, sj_served *done, uint32_t cap, uint32_t *n_done
     if (q == hipErrorNotReady) continue;
     sc.running = false;
     s->running -= 1;
+    sc.last_use = ++s->clock;
+    sc.retired_poll = poll;
     int st = sc.status;
     if (q != hipSuccess) st = SJ_EDEVICE;
     if (st == SJ_OK) {
@@ -343,8 +456,10 @@ int sj_server_poll(sj_server *s, sj_served *done, uint32_t cap, uint32_t *n_done
     sc.parity ^= 1u;
   }
   // start queued requests in arrival order
+  bool blocked = false;  // a scene earlier in the order waits for pool memory
   for (auto it = s->order.begin(); it != s->order.end() && s->running < s->max_running;) {
-    ServedScene &sc = s->scenes[it->first];
+    const uint32_t id = it->first;
+    ServedScene &sc = s->scenes[id];
     if (!sc.live) {
       it = s->order.erase(it);
       continue;
@@ -353,7 +468,35 @@ int sj_server_poll(sj_server *s, sj_served *done, uint32_t cap, uint32_t *n_done
       ++it;
       continue;
     }
-    start_tick(s, it->first);
+    if (!sc.resident) {
+      if (blocked) {
+        ++it;
+        continue;
+      }
+      int rc = make_resident(s, sc);
+      while (rc == SJ_ENOSPACE) {
+        uint32_t victim = UINT32_MAX;
+        for (uint32_t v = 0; v < s->scenes.size(); ++v) {
+          const ServedScene &o = s->scenes[v];
+          // a tick retired by this poll keeps its outputs for the caller
+          if (v == id || !o.live || !o.resident || !o.managed || o.running || !o.queue.empty() ||
+              o.retired_poll == poll)
+            continue;
+          if (victim == UINT32_MAX || o.last_use < s->scenes[victim].last_use) victim = v;
+        }
+        if (victim == UINT32_MAX) break;
+        rc = evict_scene(s, s->scenes[victim]);
+        if (rc != SJ_OK) return rc;
+        rc = make_resident(s, sc);
+      }
+      if (rc == SJ_ENOSPACE) {
+        blocked = true;
+        ++it;
+        continue;
+      }
+      if (rc != SJ_OK) return rc;
+    }
+    start_tick(s, id);
     it = s->order.erase(it);
   }
   return SJ_OK;
@@ -365,19 +508,24 @@ int sj_server_info(const sj_server *s, sj_server_stats *out) {
   out->pool_bytes = s->pool.size;
   out->pool_used = s->pool.used;
   out->running = s->running;
-  uint32_t live = 0, queued = 0;
+  uint32_t live = 0, queued = 0, resident = 0;
   for (const auto &sc : s->scenes) {
     if (!sc.live) continue;
     ++live;
+    resident += sc.resident ? 1u : 0u;
     queued += (uint32_t)sc.queue.size();
   }
   out->scenes = live;
   out->queued = queued;
+  out->resident = resident;
+  out->admissions = s->admissions;
+  out->evictions = s->evictions;
   return SJ_OK;
 }
 
 int sj_server_scene(sj_server *s, uint32_t id, sj_scene **out) {
   if (!s || !out || id >= s->scenes.size() || !s->scenes[id].live) return SJ_EINVAL;
+  if (!s->scenes[id].resident) return srv_fail(s, SJ_ESTATE, "scene: not resident (evicted)");
   *out = s->scenes[id].scene;
   return SJ_OK;
 }

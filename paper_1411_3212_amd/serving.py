@@ -1,11 +1,14 @@
 """Tick serving of many independent scenes on one GPU (continuous batching).
 
 Each scene is a moving-object set with its own tick stream.  Tick requests
-arrive as a Poisson process per scene.  Scenes are admitted into the
-server's device pool while their memory fits (an HBM budget), so a scene
-whose requests arrive while others hold the memory waits, and is admitted
-as soon as a finished scene is retired.  Admitted scenes' ticks run on
-their own streams and overlap on the device (sj_server_*).
+arrive as a Poisson process per scene.  A scene's memory comes from the
+server's device pool (an HBM budget).  With eviction (the default), every
+scene is registered up front and the server admits it when one of its
+requests comes up, evicting idle scenes (their positions to host memory,
+least recently used first) when the pool is full; a scene admitted again
+gives the same results.  Without it, a scene is admitted when it fits and
+keeps its memory until its last request is served.  Resident scenes' ticks
+run on their own streams and overlap on the device (sj_server_*).
 
 The latency of a tick request is its completion time minus its arrival time,
 so it includes the waits for admission and for a running slot as well as
@@ -126,12 +129,14 @@ def poisson_requests(n_scenes: int, n_requests: int, rate_per_scene: float, n_ti
 
 
 def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
-          keep_arrays: bool = False, digest: bool = False) -> dict:
+          keep_arrays: bool = False, digest: bool = False, evict: bool = True) -> dict:
     """Runs the requests in real time through a server.  Returns latencies,
     per-request counters and, with digest (implied by keep_arrays),
     per-request digests (sum of per-query pair-set hashes mod 2^64, pair
     count) and, with keep_arrays, the per-query count and hash arrays.  The
-    digest reads every result, so it is for checking runs."""
+    digest reads every result, so it is for checking runs.  evict: scenes
+    are admitted on demand and evicted when idle (sj_server_add); else each
+    is admitted when it fits and retired after its last request."""
     digest = digest or keep_arrays
     srv = Server(pool_bytes, max_running)
     for s_ in {s for _, s, _ in requests}:
@@ -151,6 +156,10 @@ def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
     admitted_at, retired_at = {}, {}
     nxt, done = 0, 0
     history = torch.zeros((max(n_req, 1), 16), dtype=torch.int64, device="cuda")
+    if evict:  # every scene registered; the server admits and evicts
+        for s_ in sorted(remaining):
+            sid_of[s_] = srv.add(specs[s_].cfg, specs[s_].max_updates)
+            scene_of[sid_of[s_]] = s_
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while done < n_req:
@@ -191,7 +200,7 @@ def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
                 arrays[tag] = (cnt.cpu().numpy().view(np.uint64), hsh.cpu().numpy().view(np.uint64))
             done += 1
             remaining[s] -= 1
-            if remaining[s] == 0:
+            if remaining[s] == 0 and not evict:
                 srv.retire(sid)
                 del sid_of[s]
                 retired_at[s] = time.perf_counter() - t0
@@ -199,6 +208,7 @@ def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
             time.sleep(max(0.0, min(requests[nxt][0] - (time.perf_counter() - t0), 0.001)))
     makespan = time.perf_counter() - t0
     torch.cuda.synchronize()
+    info = srv.info()
     hist = history.cpu().numpy().view(np.uint64)
     ctr = {t: tuple(int(v) for v in hist[t, :8]) for t in range(n_req)}
     dig = {t: (int(hist[t, 8]), int(hist[t, 9])) for t in range(n_req)}
@@ -206,7 +216,8 @@ def serve(specs: list, requests: list, pool_bytes: int, max_running: int, torch,
     lats = np.array([lat[t] for t in range(n_req)]) * 1e3
     pairs = sum(c[0] for c in ctr.values())
     return dict(latency_ms=lats, counters=ctr, digest=dig, arrays=arrays, makespan_s=makespan,
-                pairs=pairs, admitted_at=admitted_at, retired_at=retired_at)
+                pairs=pairs, admitted_at=admitted_at, retired_at=retired_at,
+                admissions=info["admissions"], evictions=info["evictions"])
 
 
 def serve_alone(spec: SceneSpec, tick_seq: list, torch, keep_arrays: bool = False) -> list:
@@ -263,6 +274,8 @@ def main(argv=None) -> int:
     ap.add_argument("--max-running", type=int, default=4)
     ap.add_argument("--digest", action="store_true",
                     help="also hash every tick's result set (a checking run: reads all results)")
+    ap.add_argument("--no-evict", action="store_true",
+                    help="admit a scene when it fits and keep it until its last request")
     args = ap.parse_args(argv)
     import torch
     specs = make_specs(args.scenes, nmin=args.nmin, nmax=args.nmax)
@@ -280,7 +293,8 @@ def main(argv=None) -> int:
     srv_probe = Server(1 << 20)
     need = [srv_probe.scene_bytes(sp.cfg, sp.max_updates) for sp in specs]
     srv_probe.close()
-    r = serve(specs, reqs, pool, args.max_running, torch, digest=args.digest)
+    r = serve(specs, reqs, pool, args.max_running, torch, digest=args.digest,
+              evict=not args.no_evict)
     lat = r["latency_ms"]
     out = {
         "metric": "tick serving: p50/p99 tick latency, ticks/s, result pairs/s",
@@ -292,6 +306,7 @@ def main(argv=None) -> int:
         "ticks_per_s": len(reqs) / r["makespan_s"], "pairs_per_s": r["pairs"] / r["makespan_s"],
         "pool_gib": pool / 2**30, "scene_gib_total": sum(need) / 2**30,
         "max_running": args.max_running, "digest": args.digest, "generation_s": gen_s,
+        "evict": not args.no_evict, "admissions": r["admissions"], "evictions": r["evictions"],
     }
     print(json.dumps(out), flush=True)
     return 0
