@@ -173,7 +173,9 @@ typedef struct sj_results {
   const uint32_t *d_cov_off;   /* [nq + 1] */
   const uint32_t *d_cov_leaf;
   const uint32_t *d_leaf_beg;  /* [n_leaves + 1] */
-  const uint32_t *d_sorted_id; /* [n_present] object ids in Morton order */
+  const uint32_t *d_sorted_id; /* [n_present] object ids grouped by leaf,
+                                  leaves in Morton order (leaf L's objects
+                                  are d_leaf_beg[L] .. d_leaf_beg[L+1]) */
   /* Counters of the tick, from the same read-back (0 for the result
    * counts when the tick's results overflowed): */
   uint32_t n_present;         /* objects with a position (= d_leaf_beg[n_leaves]) */

@@ -25,6 +25,9 @@ computes, with the passage of the paper it follows:
 * ``split`` -- query splitting into intersecting and covering subqueries
   (mapping function g; indexing of queries).
 * ``mix64`` -- SplitMix64's output function, used by the pair-set hash.
+* ``knn`` / ``knn_d2`` -- repeated k-nearest-neighbour queries (the
+  paper's future work, Section "Conclusions"): the k present objects of
+  smallest (binary32 squared distance, id), by brute force.
 * ``ug_col`` / ``ug_cells`` / ``ug_split`` -- the uniform grid of the UG
   method (Definition "MBR partitioning into a uniform grid"; UG index
   creation and query indexing): columns and rows of the frame along its
@@ -89,6 +92,8 @@ def _load():
         "or_ug_cells": (None, [u32, P, P, P, ctypes.c_float, ctypes.c_float, i32, u32, P]),
         "or_ug_split": (None, [u32, P, P, P, P, P, ctypes.c_float, ctypes.c_float, i32, u32,
                                P, P, P, P, P, P, P]),
+        "or_knn": (None, [u32, P, P, P, u32, P, P, P, u32, P, P]),
+        "or_knn_d2": (ctypes.c_float, [ctypes.c_float] * 4),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -331,3 +336,22 @@ def ug_split(live, rects, fr, s: int, count):
     lc = np.zeros(int(oc[-1]), np.uint32)
     lib.or_ug_split(*args, None, None, _p(oi), _p(oc), _p(li), _p(lc))
     return oi, li, oc, lc
+
+
+def knn(st: State, live, qx, qy, k: int):
+    """k nearest present objects of every live query point, ascending by
+    (binary32 squared distance, id): returns (ids[nq, k], d2[nq, k]); empty
+    slots hold id 0xffffffff and d2 = inf."""
+    qx, qy = _f32(qx), _f32(qy)
+    live = np.ascontiguousarray(live, np.uint8)
+    nq = len(qx)
+    ids = np.zeros((nq, max(k, 0)), np.uint32)
+    d2 = np.zeros((nq, max(k, 0)), np.float32)
+    _load().or_knn(st.N, _p(st.px), _p(st.py), _p(st.has), nq, _p(live), _p(qx), _p(qy),
+                   int(k), _p(ids), _p(d2))
+    return ids, d2
+
+
+def knn_d2(px: float, py: float, qx: float, qy: float) -> float:
+    """The binary32 squared distance of the kNN definition for one pair."""
+    return float(_load().or_knn_d2(px, py, qx, qy))

@@ -611,3 +611,75 @@ void or_ug_split(uint32_t nq, const uint8_t *live, const float *xa, const float 
     if (nc) nc[k] = cc;
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* Repeated k-nearest-neighbour queries (the paper's stated future      */
+/* work, Section "Conclusions"; the paper defines no semantics, so this */
+/* is the reading both sides implement).  A query (qid, qx, qy) asks   */
+/* for the k present objects with the smallest key (d2, id), where      */
+/*   dx = fl32(px - qx), dy = fl32(py - qy),                             */
+/*   d2 = fl32(fl32(dx * dx) + fl32(dy * dy)),                           */
+/* evaluated in exactly that order in binary32 (no contraction), ties  */
+/* broken by the smaller id.  Results are in ascending key order; a     */
+/* query with fewer than k present objects gets all of them, the rest   */
+/* of its k slots hold id 0xffffffff and d2 = +inf.  A query superseded */
+/* by a later query of the same object in the tick is answered with    */
+/* all slots empty (as a superseded range query has an empty result).  */
+/* Brute force: every present object is scored, and a sorted list of    */
+/* the k best keys so far is kept by insertion.                          */
+/* ------------------------------------------------------------------ */
+
+static inline float or_d2(float px, float py, float qx, float qy) {
+  volatile float dx = px - qx, dy = py - qy;
+  volatile float xx = dx * dx, yy = dy * dy;
+  return xx + yy;
+}
+
+/* key = (binary32 bits of d2) << 32 | id; d2 >= +0, so the bit pattern   */
+/* orders like the value.                                                 */
+static inline uint64_t or_knn_key(float d2, uint32_t id) {
+  uint32_t b;
+  memcpy(&b, &d2, 4);
+  return ((uint64_t)b << 32) | id;
+}
+
+void or_knn(uint32_t N, const float *px, const float *py, const uint8_t *has,
+            uint32_t nq, const uint8_t *live, const float *qx, const float *qy,
+            uint32_t k, uint32_t *out_id, float *out_d2) {
+  if (k == 0) return;
+#pragma omp parallel
+  {
+    uint64_t *best = (uint64_t *)malloc(sizeof(uint64_t) * k);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t q = 0; q < (int64_t)nq; ++q) {
+      uint32_t nb = 0;
+      if (live[q]) {
+        for (uint32_t j = 0; j < N; ++j) {
+          if (!has[j]) continue;
+          const uint64_t key = or_knn_key(or_d2(px[j], py[j], qx[q], qy[q]), j);
+          if (nb == k && key >= best[k - 1]) continue;
+          uint32_t p = nb < k ? nb++ : k - 1;
+          while (p > 0 && best[p - 1] > key) {
+            best[p] = best[p - 1];
+            --p;
+          }
+          best[p] = key;
+        }
+      }
+      for (uint32_t i = 0; i < k; ++i) {
+        if (i < nb) {
+          const uint32_t b = (uint32_t)(best[i] >> 32);
+          out_id[(uint64_t)q * k + i] = (uint32_t)best[i];
+          memcpy(&out_d2[(uint64_t)q * k + i], &b, 4);
+        } else {
+          out_id[(uint64_t)q * k + i] = 0xffffffffu;
+          out_d2[(uint64_t)q * k + i] = INFINITY;
+        }
+      }
+    }
+    free(best);
+  }
+}
+
+/* The binary32 squared distance of the definition above, one pair. */
+float or_knn_d2(float px, float py, float qx, float qy) { return or_d2(px, py, qx, qy); }
