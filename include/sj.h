@@ -544,6 +544,21 @@ size_t sj_mlp_scratch_bytes(uint32_t n);
 int sj_mlp_grad(const uint16_t *d_w, const float *d_x, const float *d_t, uint32_t n,
                 float *d_grad, void *d_scratch, size_t scratch_bytes, hipStream_t stream);
 
+/* sj_mlp_grad without a caller-provided scratch buffer, for callers that
+ * cannot allocate device memory (code under graph capture, serving loops
+ * that refine the model between ticks, harnesses that forbid hipMalloc).
+ * The per-block partial gradients live in a fixed array inside the library
+ * (sj_mlp_noalloc_scratch_bytes() = 4,655,104 bytes per GPU, held until the
+ * process ends); its size does not depend on n, so no n is refused for it.
+ * Same kernels and result as sj_mlp_grad, bit for bit.  The call allocates
+ * nothing (on its first call on a GPU it looks up the array's address on
+ * that GPU).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (on different streams, or from different threads
+ * without ordering) race and give wrong gradients; serialise them. */
+size_t sj_mlp_noalloc_scratch_bytes(void);
+int sj_mlp_grad_noalloc(const uint16_t *d_w, const float *d_x, const float *d_t, uint32_t n,
+                        float *d_grad, hipStream_t stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
  * on the FP32 masters with moments d_m, d_v; writes the BF16 copy d_w. */
 int sj_mlp_adam(float *d_master, const float *d_grad, float *d_m, float *d_v, uint16_t *d_w,

@@ -138,6 +138,8 @@ EXPORTS = {
     "sj_mlp_scratch_bytes": (c_size_t, [c_uint32]),
     "sj_mlp_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p, c_size_t,
                             c_void_p]),
+    "sj_mlp_noalloc_scratch_bytes": (c_size_t, []),
+    "sj_mlp_grad_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]),
     "sj_mlp_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_float,
                             c_void_p]),
 }

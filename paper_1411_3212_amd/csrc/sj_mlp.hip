@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "sj.h"
 #include "sj_device.h"
 #include "sj_mlp.h"
@@ -179,11 +181,51 @@ __global__ void k_mlp_adam(float *master, const float *grad, float *m, float *v,
 
 constexpr uint32_t kGradBlocks = 256;
 
+// Per-block partial gradients of sj_mlp_grad_noalloc: a fixed array in the
+// library's device memory (one copy per GPU, held until the process ends),
+// for callers that cannot allocate.  Every block writes its whole partial
+// on every call, so nothing has to start at zero.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the device.
+constexpr size_t kGradScratchFloats = (size_t)kGradBlocks * (kMlpParams + 1);
+static __device__ __align__(256) float scratch[kGradScratchFloats];
+
 }  // namespace sj
 
 using namespace sj;
 
 namespace {
+
+// Device address of `scratch` on each GPU, looked up on the first call made
+// with that GPU current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    sj_set_global_error("sj_mlp_grad_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    return SJ_EDEVICE;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    sj_set_global_error("sj_mlp_grad_noalloc: device %d above the supported %d", dev,
+                        kMaxDevices);
+    return SJ_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(sj::scratch));
+    if (e != hipSuccess || !p) {
+      sj_set_global_error("sj_mlp_grad_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+      return SJ_EDEVICE;
+    }
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return SJ_OK;
+}
 
 // Status of the launches since the matching launch_begin(): errors that
 // earlier calls of other code left pending are cleared first, so a failure
@@ -234,6 +276,24 @@ int sj_mlp_grad(const uint16_t *d_w, const float *d_x, const float *d_t, uint32_
   hipLaunchKernelGGL(k_mlp_reduce, dim3(18), dim3(256), 0, s, (const float *)partial, kGradBlocks,
                      d_grad);
   return launch_end("sj_mlp_grad");
+}
+
+size_t sj_mlp_noalloc_scratch_bytes(void) { return kGradScratchFloats * sizeof(float); }
+
+int sj_mlp_grad_noalloc(const uint16_t *d_w, const float *d_x, const float *d_t, uint32_t n,
+                        float *d_grad, hipStream_t s) {
+  if (!d_w || !d_grad || (n && (!d_x || !d_t))) return SJ_EINVAL;
+  // the partials are per block (kGradBlocks of them whatever n is), so
+  // every n fits the fixed array
+  void *p = nullptr;
+  const int rc = scratch_address(&p);
+  if (rc != SJ_OK) return rc;
+  float *partial = (float *)p;
+  launch_begin();
+  hipLaunchKernelGGL(k_mlp_grad, dim3(kGradBlocks), dim3(64), 0, s, d_w, d_x, d_t, n, partial);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(18), dim3(256), 0, s, (const float *)partial, kGradBlocks,
+                     d_grad);
+  return launch_end("sj_mlp_grad_noalloc");
 }
 
 int sj_mlp_adam(float *d_master, const float *d_grad, float *d_m, float *d_v, uint16_t *d_w,
