@@ -16,6 +16,9 @@ the timed window holds at least one rebuild tick per rebuild period; their
 latency is also reported apart.  A separate untimed pass checks that every
 configuration gives the same per-query result sizes and pair-set hashes.
 
+The same ticks then run as k-nearest-neighbour queries (k = 16 by default)
+at the issuers' positions, reported apart under "knn".
+
 Prints one JSON line: result pairs/s (value), ticks/s, p50/p99 tick latency,
 the roofline figure of the dominant kernel (its launch time measured with
 HIP events on the scene's stream inside the timed region), and the CPU
@@ -54,13 +57,14 @@ WORKLOAD_TEXT = {
 
 
 def scene_config(wl: workloads.Workload, th: int = 64, covering: bool = True,
-                 reorder: bool = True) -> dict:
+                 reorder: bool = True, rebuild: str = "auto") -> dict:
     """Capacities sized for a workload (subqueries, covering entries and
-    result ids per tick, with headroom) and the covering / reorder switches."""
+    result ids per tick, with headroom), the covering / reorder switches and
+    the rebuild policy."""
     from paper_1411_3212_amd.serving import scene_capacities
     c = scene_capacities(wl, th, covering)
     c.pop("nq")
-    c.update(covering=covering, reorder=reorder)
+    c.update(covering=covering, reorder=reorder, rebuild=rebuild)
     return c
 
 
@@ -89,6 +93,12 @@ def parse():
                     help="off: every overlapped leaf is tested (no covering leaves)")
     ap.add_argument("--reorder", default="on", choices=["on", "off"],
                     help="off: join tasks in leaf order instead of heaviest first")
+    ap.add_argument("--rebuild", default="auto", choices=["auto", "cost"],
+                    help="quadtree reuse: auto (periodic + occupancy/frame checks) or cost "
+                         "(rent or buy on the device clock)")
+    ap.add_argument("--knn", type=int, default=16,
+                    help="also time the same ticks as k-nearest-neighbour queries at the "
+                         "issuers' positions with this k (0: off)")
     return ap.parse_args()
 
 
@@ -151,7 +161,7 @@ class Run:
         self.label = "learned" if learned else f"fixed {th}"
         self.model = costmodel.load(MODEL) if learned else None
         cfg = scene_config(wl, th if not learned else 64, args.covering == "on",
-                           args.reorder == "on")
+                           args.reorder == "on", args.rebuild)
         self.th = None if learned else th
         kw = {k: v for k, v in cfg.items() if k != "th"}
         if learned:
@@ -249,6 +259,48 @@ class Run:
 
     def close(self):
         self.scene.close()
+
+
+def knn_run(args, wl, ticks, nq, th, torch, W, K):
+    """The same ticks as k-nearest-neighbour queries (k = args.knn) at the
+    issuers' positions, on a scene with threshold th: updates + kNN tick per
+    step (sj_run_knn returns once the outputs are written)."""
+    from paper_1411_3212_amd.binding import Scene
+    k = args.knn
+    kw = {kk: v for kk, v in scene_config(wl, th, rebuild=args.rebuild).items() if kk != "th"}
+    sc = Scene(wl.n, nq, th=th, **kw)
+    steps = []
+    for buf, m, q in ticks[:W + K]:
+        v = views(buf, m, q, torch)
+        qi = v["qid"].long()
+        steps.append((v, v["x"].index_select(0, qi), v["y"].index_select(0, qi)))
+    out_id = torch.empty(nq * k, dtype=torch.int32, device="cuda")
+    out_d2 = torch.empty(nq * k, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    lat, fb, rebuilt = [], [], []
+    for i, (v, qx, qy) in enumerate(steps):
+        if i == W:
+            sc.build_index()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        h0 = time.perf_counter()
+        q = v["qid"].numel()
+        sc.apply_updates(v["ids"], v["x"], v["y"])
+        sc.run_knn(v["qid"], qx, qy, k, out_id[:q * k], out_d2[:q * k])
+        if i >= W:
+            lat.append((time.perf_counter() - h0) * 1e3)
+            s = sc.stats()
+            fb.append(s["knn_fallback"])
+            rebuilt.append(s["rebuilt"])
+    wall = time.perf_counter() - t0
+    sc.close()
+    lat = np.array(lat)
+    return {"k": k, "threshold": th, "queries_per_tick": nq, "ms_per_step": wall * 1e3 / K,
+            "knn_queries_per_s": nq * K / wall, "ticks_per_s": K / wall,
+            "p50_tick_ms": float(np.percentile(lat, 50)),
+            "p99_tick_ms": float(np.percentile(lat, 99)),
+            "rebuild_ticks": int(np.sum(rebuilt)),
+            "fallback_queries_per_tick": float(np.mean(fb))}
 
 
 def verify(args, wl, ticks, nq, configs, torch):
@@ -433,7 +485,8 @@ def main():
                    "threshold": "learned (cost model; tuning amortised)" if learned
                    else int(args.threshold),
                    "covering": args.covering == "on", "reorder": args.reorder == "on",
-                   "rebuild": "auto, period 32, forced on the first timed tick",
+                   "rebuild": ("auto, period 32" if args.rebuild == "auto" else
+                               "cost (rent or buy)") + ", forced on the first timed tick",
                    "launch": args.mode},
         "ticks_per_s": hs["ticks_per_s"],
         "p50_tick_ms": hs["p50_tick_ms"],
@@ -476,6 +529,11 @@ def main():
             "p99_ratio": {k: cmp[configs[0][0]]["p99_tick_ms"] / v["p99_tick_ms"]
                           for k, v in cmp.items() if k != configs[0][0]},
         }
+    if args.knn:
+        try:
+            out["knn"] = knn_run(args, wl, ticks, nq, int(head.th_last), torch, W, K)
+        except Exception as e:  # reported, the range-query line stands
+            out["knn"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_verify and len(configs) > 1:
         same = verify(args, wl, ticks, nq, configs, torch)
         out.setdefault("learned_vs_fixed" if learned else "vs_fixed", {})[

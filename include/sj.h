@@ -108,8 +108,17 @@ enum sj_rebuild {
                             objects or more than 1% of the objects lay
                             outside the index frame */
   SJ_REBUILD_ALWAYS = 1, /* rebuild on every tick */
-  SJ_REBUILD_NEVER = 2   /* rebuild only on the first tick and after
+  SJ_REBUILD_NEVER = 2,  /* rebuild only on the first tick and after
                             sj_build_index */
+  SJ_REBUILD_COST = 3    /* rebuild when keeping the quadtree has cost as
+                            much as a rebuild (rent or buy): after a build,
+                            each kept tick adds its device time above the
+                            fastest kept tick since the build, and the tick
+                            after the sum reaches the build tick's own
+                            excess over that fastest tick rebuilds.  Within
+                            twice the least total excess for excesses that
+                            grow as objects drift.  Also on the first tick
+                            and after sj_build_index. */
 };
 
 typedef struct sj_config {
@@ -210,6 +219,9 @@ typedef struct sj_tick_stats {
                              |intersecting subqueries| * |objects| */
   uint32_t error_bits;    /* latched device error flags of this tick */
   uint32_t tick;          /* ticks run so far */
+  uint32_t knn_fallback;  /* after sj_run_knn: queries answered by the
+                             fallback scan over every object */
+  uint32_t reserved;
 } sj_tick_stats;
 
 /* Phases timed when SJ_PROFILE is set (device time in milliseconds of the
@@ -385,6 +397,35 @@ int sj_timing_log(sj_scene *scene, sj_timing_view *out);
  * only SJ_PH_JOIN_WRITE is timed (the pass runs as a graph of its own
  * between two events); the other entries are 0. */
 int sj_phase_times(sj_scene *scene, float *ms, int n);
+
+/* Largest k of a k-nearest-neighbour query. */
+#define SJ_KNN_MAX 64u
+
+/* Closes the tick like sj_run_tick and answers nq k-nearest-neighbour
+ * queries instead of range queries (the paper leaves repeated kNN queries
+ * over moving objects to future work, Section "Conclusions", proposing to
+ * reuse its pipeline; this is that reuse).  Query i, issued by object
+ * d_qid[i] at point (d_qx[i], d_qy[i]), asks for the k present objects of
+ * smallest key (d2, id), where d2 = fl32(fl32(dx*dx) + fl32(dy*dy)),
+ * dx = fl32(px - qx), dy = fl32(py - qy), each operation rounded to
+ * binary32 on its own; ties go to the smaller id.  Output (device,
+ * caller-owned, row-major nq x k): d_out_id[i*k + j], d_out_d2[i*k + j] is
+ * the (j+1)-th nearest; slots past the present objects hold id 0xffffffff
+ * and d2 = +inf; a query superseded by a later query of the same object in
+ * the tick, or one at a non-finite point (SJ_EDATA), gets only such slots.
+ * How: a candidate square per query from the quadtree (the k-th distance
+ * to the objects of the point's leaf, or the farthest corner of the
+ * smallest enclosing quadrant holding k objects), the tick's query split
+ * and join on those squares, then a per-query selection; a query whose
+ * square cannot be proved to hold its k nearest is answered by a scan over
+ * every object (counted in sj_tick_stats.knn_fallback).  sj_fetch_results
+ * afterwards returns the squares' range results.  1 <= k <= SJ_KNN_MAX,
+ * nq <= capacity_queries; not with SJ_UNIFORM_GRID or SJ_ATOMIC_RESULTS
+ * (SJ_EINVAL).  Synchronises: returns after the outputs are written, with
+ * the tick's status (SJ_EOVERFLOW: outputs not written; grow the
+ * capacities). */
+int sj_run_knn(sj_scene *scene, const uint32_t *d_qid, const float *d_qx, const float *d_qy,
+               uint32_t nq, uint32_t k, uint32_t *d_out_id, float *d_out_d2);
 
 /* Internal arrays for tests and tools (device views, valid until the next
  * call): sorted Morton codes and ids of present objects, leaf table in

@@ -23,7 +23,7 @@ SJ_UNIFORM_GRID, SJ_ATOMIC_RESULTS, SJ_CU_COUNTERS = 64, 128, 256
 CU_SLOTS = 4096
 SJ_SORTED = 1  # sj_expand_results: ascending ids per list
 COST_TERMS = 6  # SJ_COST_TERMS
-REBUILD = {"auto": 0, "always": 1, "never": 2}
+REBUILD = {"auto": 0, "always": 1, "never": 2, "cost": 3}
 PHASES = ["updates", "index", "build", "leaves", "split", "schedule", "join_count", "join_scan",
           "join_write"]
 _NAMES = {0: "SJ_OK", -1: "SJ_EINVAL", -2: "SJ_ENOSPACE", -3: "SJ_EOVERFLOW", -4: "SJ_EDATA",
@@ -61,7 +61,8 @@ class SjTickStats(Structure):
                 ("l_deep", c_uint32), ("th", c_uint32), ("rebuilt", c_uint32),
                 ("n_tasks", c_uint32), ("max_leaf", c_uint32), ("n_isect", c_uint64),
                 ("n_cov", c_uint64), ("n_isect_ids", c_uint64), ("cov_pairs", c_uint64),
-                ("tests", c_uint64), ("error_bits", c_uint32), ("tick", c_uint32)]
+                ("tests", c_uint64), ("error_bits", c_uint32), ("tick", c_uint32),
+                ("knn_fallback", c_uint32), ("reserved", c_uint32)]
 
 
 class SjIndexView(Structure):
@@ -102,6 +103,8 @@ EXPORTS = {
     "sj_build_index": (c_int, [c_void_p, c_uint32]),
     "sj_run_tick": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                             c_uint32]),
+    "sj_run_knn": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_uint32, c_void_p,
+                           c_void_p]),
     "sj_tick_graph": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_uint32]),
     "sj_fetch_results": (c_int, [c_void_p, POINTER(SjResults)]),
@@ -365,6 +368,27 @@ class Scene:
                                      _ptr(yb), nq), self.handle)
         self._keep = [qid, xa, ya, xb, yb]
         self._graph_key = None
+
+    def run_knn(self, qid, qx, qy, k: int, out_id=None, out_d2=None):
+        """Closes the tick with k-nearest-neighbour queries at points (qx,
+        qy); returns (ids int32 [nq, k], d2 float32 [nq, k]), ascending by
+        (d2, id), empty slots id -1 (0xffffffff) and d2 inf.  Synchronises."""
+        import torch
+        nq = qid.numel()
+        qid = self._dev(qid, qid.dtype if qid.dtype in (torch.int32, torch.uint32) else torch.int32)
+        self._dev(qx, torch.float32, nq)
+        self._dev(qy, torch.float32, nq)
+        if out_id is None:
+            out_id = torch.empty((nq, k), dtype=torch.int32, device=self.device)
+        if out_d2 is None:
+            out_d2 = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        self._dev(out_id, torch.int32, nq * k)
+        self._dev(out_d2, torch.float32, nq * k)
+        self._keep = [qid, qx, qy]
+        self._graph_key = None
+        _check(self._lib.sj_run_knn(self.handle, _ptr(qid), _ptr(qx), _ptr(qy), nq, int(k),
+                                    _ptr(out_id), _ptr(out_d2)), self.handle)
+        return out_id, out_d2
 
     def prepare_tick(self, ids, x, y, qid, xa, ya, xb, yb) -> "TickArgs":
         """Checks one tick's input tensors once; tick_graph(prepared) then

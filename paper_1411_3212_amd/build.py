@@ -9,7 +9,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsj.so"
-SOURCES = ["sj_prims.hip", "sj_kernels.hip", "sj_results.hip", "sj_baseline.hip", "sj_api.hip", "sj_server.hip", "sj_mlp.hip", "sj_tune.hip"]
+SOURCES = ["sj_prims.hip", "sj_kernels.hip", "sj_results.hip", "sj_baseline.hip", "sj_knn.hip", "sj_api.hip", "sj_server.hip", "sj_mlp.hip", "sj_tune.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -112,7 +112,7 @@ int derive(const sj_config *cfg, Derived *d, char *msg, size_t msz) {
     snprintf(msg, msz, "split_slots must be at most 4096");
     return SJ_EINVAL;
   }
-  if (cfg->rebuild_policy > SJ_REBUILD_NEVER) {
+  if (cfg->rebuild_policy > SJ_REBUILD_COST) {
     snprintf(msg, msz, "unknown rebuild policy");
     return SJ_EINVAL;
   }
@@ -230,6 +230,8 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.pairs = d.sqb ? c.take<uint2>(d.R) : nullptr;
   b.cu_tests = d.cu ? c.take<uint64_t>(sj::kCuSlots) : nullptr;
   b.tune = c.take<sj::TuneState>(1);
+  b.kq_rect = c.take<float>(4 * Q);
+  b.kq_fb = c.take<uint32_t>(Q);
   b.N = d.N;
   b.Q = d.Q;
   b.LCAP = d.LCAP;
@@ -302,7 +304,7 @@ uint32_t host_decision(const sj_scene *s) {
   const Ctl &c = s->host_ctl;
   const uint32_t policy = s->cfg.rebuild_policy;
   const bool r = s->force_pending || !c.built || policy == SJ_REBUILD_ALWAYS ||
-                 (policy == SJ_REBUILD_AUTO && c.want_rebuild);
+                 ((policy == SJ_REBUILD_AUTO || policy == SJ_REBUILD_COST) && c.want_rebuild);
   return r ? 1u : 0u;
 }
 
@@ -333,10 +335,19 @@ void count_build(sj_scene *s, uint32_t decision, bool tune) {
   }
 }
 
+// A tick of k-nearest-neighbour queries: query points, k, outputs.
+struct KnnArgs {
+  const float *qx, *qy;
+  uint32_t k;
+  uint32_t *out_id;
+  float *out_d2;
+};
+
 // part: 0 the whole tick; 1 up to the result-offset scan; 2 the join write.
-// The tick's query arrays are those last written to the scene's input block.
+// The tick's query arrays are those last written to the scene's input block
+// (for a kNN tick: the candidate squares, written by the radius kernel).
 void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_total, bool events,
-                  int part = 0, bool tune = false) {
+                  int part = 0, bool tune = false, const KnnArgs *knn = nullptr) {
   const hipStream_t st = s->stream;
   const uint32_t flags = s->cfg.flags;
   const uint32_t policy = s->cfg.rebuild_policy;
@@ -358,6 +369,7 @@ void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_tota
   if (decision != 0u && !(flags & SJ_UNIFORM_GRID)) sj::launch_build(s->B, s->l_max, st);
   rec(2);
   sj::launch_leaves(s->B, st);
+  if (knn) sj::launch_knn_radius(s->B, knn->qx, knn->qy, nq, knn->k, st);
   rec(3);
   const uint32_t *qord = sj::launch_split(s->B, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
   rec(4);
@@ -379,6 +391,7 @@ void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_tota
   if (part == 1) return;
   if (!sqb) sj::launch_join_write(s->B, nq, st);
   rec(8);
+  if (knn) sj::launch_knn_select(s->B, knn->qx, knn->qy, nq, knn->k, knn->out_id, knn->out_d2, st);
   rec(9);
   sj::launch_ctl_out(s->B, s->pin_ctl, st);
   s->events_valid = events;
@@ -454,7 +467,7 @@ int sj_scene_create(const sj_config *cfg, void *d_workspace, size_t ws_bytes, hi
       return SJ_EDEVICE;
     }
   }
-  sj::launch_ctl_init(s->B.ctl, d.th, d.ug, d.ug_bits, stream);
+  sj::launch_ctl_init(s->B.ctl, d.th, d.ug, d.ug_bits, cfg->rebuild_policy, stream);
   sj::launch_fill_u32((uint32_t *)s->B.pos, 2ull * d.N, 0x7fc00000u, stream);  // NaN: no position
   sj::launch_fill_u64(s->B.ustamp, d.N, 0ull, stream);
   sj::launch_fill_u64(s->B.qstamp, d.N, 0ull, stream);
@@ -543,6 +556,37 @@ int sj_run_tick(sj_scene *s, const uint32_t *d_qid, const float *d_xa, const flo
   after_tick(s, d_qid, nq);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SJ_OK : hip_fail(s, e, "run_tick launch");
+}
+
+int sj_run_knn(sj_scene *s, const uint32_t *d_qid, const float *d_qx, const float *d_qy,
+               uint32_t nq, uint32_t k, uint32_t *d_out_id, float *d_out_d2) {
+  if (!s) return SJ_EINVAL;
+  if (k < 1u || k > SJ_KNN_MAX) return fail(s, SJ_EINVAL, "run_knn: k must be in 1..64");
+  if (s->cfg.flags & (SJ_UNIFORM_GRID | SJ_ATOMIC_RESULTS))
+    return fail(s, SJ_EINVAL, "run_knn: needs the quadtree and the lock-free join");
+  if (nq > s->B.Q) return fail(s, SJ_EINVAL, "run_knn: nq above capacity_queries");
+  if (nq && (!d_qid || !d_qx || !d_qy || !d_out_id || !d_out_d2 || ((uintptr_t)d_qid & 3u) ||
+             ((uintptr_t)d_qx & 3u) || ((uintptr_t)d_qy & 3u) || ((uintptr_t)d_out_id & 3u) ||
+             ((uintptr_t)d_out_d2 & 3u)))
+    return fail(s, SJ_EINVAL, "run_knn: null or misaligned pointer");
+  const uint32_t decision = host_decision(s);
+  sj::TickIn in{};
+  in.qid = d_qid;
+  const uint64_t Q = s->B.Q;
+  in.xa = s->B.kq_rect;
+  in.ya = s->B.kq_rect + Q;
+  in.xb = s->B.kq_rect + 2 * Q;
+  in.yb = s->B.kq_rect + 3 * Q;
+  sj::launch_tick_in(s->B, in, 2u, s->stream);
+  const KnnArgs a{d_qx, d_qy, k, d_out_id, d_out_d2};
+  enqueue_tick(s, nq, decision, s->upd_pending, s->prof, 0, false, &a);
+  count_build(s, decision, false);
+  after_tick(s, d_qid, nq);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "run_knn launch");
+  const int rc = sync_ctl(s);
+  if (rc != SJ_OK) return rc;
+  return status_of(s, s->host_ctl.err);
 }
 
 // Event record nodes e0 -> (join write kernel node) -> e1 in a captured
@@ -738,6 +782,7 @@ int sj_stats(sj_scene *s, sj_tick_stats *out) {
   out->tests = c.tests;
   out->error_bits = c.err;
   out->tick = c.tick;
+  out->knn_fallback = c.n_knn_fb;
   return s->ticked ? status_of(s, c.err) : SJ_OK;
 }
 

@@ -59,6 +59,7 @@ struct Ctl {
   uint32_t ug_bits;       // bits per axis of the grid cells' Morton codes
   uint32_t sq_skip;       // radix digits of the subqueries' leaf keys (multiple of 8)
   uint32_t max_leaf;
+  uint32_t n_knn_fb;      // kNN queries of the tick listed for the fallback scan
   uint32_t err_upd;       // errors of updates since the last tick
   uint32_t err;           // errors of the current tick (includes err_upd)
   uint32_t go_split;      // subquery/covering capacities respected
@@ -66,6 +67,14 @@ struct Ctl {
   uint32_t n32[2];        // intersecting / covering subqueries as u32
   uint64_t n_isect, n_cov, n_res, cov_pairs, tests;
   uint64_t upd_seq, qry_seq;
+  // rebuild by cost (SJ_REBUILD_COST): device clock (100 MHz) at the start
+  // of the tick; durations of the last build tick and of the fastest kept
+  // tick since; the build's extra cost over it (< 0: not known yet); the
+  // summed excess of the kept ticks over the fastest one
+  uint64_t t_start;
+  uint32_t policy;
+  float d_build, d_base, b_cost, excess;
+  uint32_t pad_cost;
 };
 
 // Input arrays of a tick.  Kernels read them from this block in device

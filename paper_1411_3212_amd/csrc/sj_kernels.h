@@ -54,6 +54,9 @@ struct Bufs {
   uint2 *pairs;                         // appended (query, object) pairs of the baseline
                                         // filter (or null: lock-free join)
   uint64_t *cu_tests;                   // containment tests per CU slot (or null)
+  float *kq_rect;                       // kNN candidate squares: xa, ya, xb, yb arrays of Q
+                                        // (or null: the scene takes no kNN queries)
+  uint32_t *kq_fb;                      // kNN queries left to the fallback scan (Q)
   TuneState *tune;                      // threshold tuner state
   // capacities
   uint32_t N, Q, LCAP, NCAP, FCAP, slots, tcap, TCAP;
@@ -62,7 +65,8 @@ struct Bufs {
 
 // ug_split: columns of the uniform-grid index (0: quadtree), ug_bits its
 // cells' bits per axis.
-void launch_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits, uint32_t policy,
+                     hipStream_t s);
 void launch_request_build(Ctl *ctl, uint32_t th, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
@@ -104,6 +108,14 @@ void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, ui
 // Host handle of the join write kernel (to find its node in a captured graph).
 const void *join_write_kernel();
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s);
+// k-nearest-neighbour queries: the candidate square of every query point
+// (after the leaves of the tick are known, before the query split reads
+// the squares as the tick's rectangles), and the selection of the k
+// nearest among each square's results (after the join write pass).
+void launch_knn_radius(const Bufs &B, const float *qx, const float *qy, uint32_t nq, uint32_t k,
+                       hipStream_t s);
+void launch_knn_select(const Bufs &B, const float *qx, const float *qy, uint32_t nq, uint32_t k,
+                       uint32_t *out_id, float *out_d2, hipStream_t s);
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s);
 void launch_hash(const Bufs &B, uint32_t nq, const uint32_t *qid, uint64_t *cnt, uint64_t *hash,
                  hipStream_t s);

@@ -22,47 +22,11 @@
 // kernels of the pipeline (no same-address atomics from every block).
 #include "sj_device.h"
 #include "sj_kernels.h"
+#include "sj_tree.h"
 
 namespace sj {
 
 constexpr uint32_t kTableScanMax = 1024;  // queries over more table cells start at the root
-// Start-table entry of a leaf: flag, level - 1 (4 bits), leaf index (27 bits).
-constexpr uint32_t kLeafIdxBits = 27;
-constexpr uint32_t kLeafIdxMask = (1u << kLeafIdxBits) - 1u;
-
-// The quadtree as the traversals see it: node table (4 child references,
-// kLeafBit marks a leaf), start table at level tlev, leaf starts and levels.
-struct Tree {
-  const uint4 *nodes;
-  const uint32_t *table;
-  const uint32_t *lstart, *llevel;
-  uint32_t tlev;
-};
-
-// Leaf containing the finest-level code `code`: its start-table cell gives
-// the leaf, or the internal node at level tlev to descend from (one child
-// reference per level, at most kFine - tlev of them).
-__device__ __forceinline__ uint32_t table_entry(const Tree &tr, uint32_t code) {
-  return tr.table[code >> (2u * (kFine - tr.tlev))];
-}
-// The descent from table entry e (split from the table load so that a
-// thread can issue several table loads before it waits for one).
-__device__ __forceinline__ uint32_t leaf_from(const Tree &tr, uint32_t e, uint32_t code) {
-  if (e & kLeafBit) return e & kLeafIdxMask;
-  uint32_t node = e;
-  for (uint32_t k = tr.tlev; k < (uint32_t)kFine; ++k) {
-    const uint32_t q = (code >> (2u * (kFine - k - 1u))) & 3u;
-    const uint4 nd = tr.nodes[node];
-    const uint32_t r = q == 0u ? nd.x : q == 1u ? nd.y : q == 2u ? nd.z : nd.w;
-    if (r & kLeafBit) return r & ~kLeafBit;
-    node = r;
-  }
-  return 0u;  // not reached: every level-16 cell lies in a leaf
-}
-__device__ __forceinline__ uint32_t leaf_of(const Tree &tr, uint32_t code) {
-  return leaf_from(tr, table_entry(tr, code), code);
-}
-
 // ------------------------------------------------------------- utilities --
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -77,11 +41,14 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
-__global__ void k_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits) {
+__global__ void k_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits,
+                           uint32_t policy) {
   Ctl c;
   uint8_t *b = (uint8_t *)&c;
   for (unsigned i = 0; i < sizeof(Ctl); ++i) b[i] = 0;
   c.th_cur = th;
+  c.policy = policy;
+  c.b_cost = -1.0f;
   c.scale = 65536.0f;
   c.ug_split = ug_split;
   c.ug_bits = ug_bits;
@@ -288,8 +255,10 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   else if (decision == 1u)
     r = true;
   else
-    r = ctl->force || !ctl->built || policy == 1u || (policy == 0u && ctl->want_rebuild);
+    r = ctl->force || !ctl->built || policy == 1u ||
+        ((policy == 0u || policy == 3u) && ctl->want_rebuild);
   ctl->rebuild = r ? 1u : 0u;
+  ctl->t_start = __builtin_amdgcn_s_memrealtime();
   if (!r) {
     ctl->since_build += 1;
     // leaf keys are below n_leaves: the radix passes above their width
@@ -1781,10 +1750,35 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
 
 // --------------------------------------------------------------- results --
 
+// Rebuild by cost, at the end of every tick (rent or buy: keeping the
+// quadtree costs the excess of each kept tick over the fastest kept tick
+// since the last build; a build costs its tick's excess over that kept
+// tick; the next tick builds once the summed excess reaches the cost of a
+// build, which spends at most twice the least possible on any sequence of
+// growing excesses).  Durations are device time from the index frame's
+// decision to this kernel.  Results do not depend on when the quadtree is
+// built.
+__device__ void rebuild_by_cost(Ctl *ctl) {
+  const float d = (float)(__builtin_amdgcn_s_memrealtime() - ctl->t_start);
+  if (ctl->rebuild) {
+    ctl->d_build = d;
+    ctl->d_base = 0.0f;
+    ctl->b_cost = -1.0f;
+    ctl->excess = 0.0f;
+  } else {
+    if (ctl->d_base == 0.0f || d < ctl->d_base) ctl->d_base = d;
+    if (ctl->b_cost < 0.0f) ctl->b_cost = fmaxf(ctl->d_build - d, 0.0f);
+    ctl->excess += d - ctl->d_base;
+  }
+  ctl->want_rebuild = !ctl->built || (ctl->b_cost >= 0.0f && ctl->excess >= ctl->b_cost);
+}
+
 // End of a tick: the control block to the host's pinned mirror (one wave,
 // a word per lane), so reading the tick's counters needs no copy command.
-__global__ void k_ctl_out(const Ctl *ctl, Ctl *host) {
+__global__ void k_ctl_out(Ctl *ctl, Ctl *host) {
   static_assert(sizeof(Ctl) % 4 == 0, "word copy");
+  if (threadIdx.x == 0 && ctl->policy == 3u) rebuild_by_cost(ctl);
+  __syncthreads();
   const uint32_t *src = (const uint32_t *)ctl;
   uint32_t *dst = (uint32_t *)host;
   for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) dst[i] = src[i];
@@ -1806,8 +1800,9 @@ __global__ void k_counters(const Ctl *ctl, uint64_t *out) {
 
 #define LAUNCH(k, g, b, s, ...) hipLaunchKernelGGL(k, dim3(g), dim3(b), 0, s, __VA_ARGS__)
 
-void launch_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits, hipStream_t s) {
-  LAUNCH(k_ctl_init, 1, 1, s, ctl, th, ug_split, ug_bits);
+void launch_ctl_init(Ctl *ctl, uint32_t th, uint32_t ug_split, uint32_t ug_bits, uint32_t policy,
+                     hipStream_t s) {
+  LAUNCH(k_ctl_init, 1, 1, s, ctl, th, ug_split, ug_bits, policy);
 }
 void launch_request_build(Ctl *ctl, uint32_t th, hipStream_t s) {
   LAUNCH(k_request_build, 1, 1, s, ctl, th);
@@ -1847,10 +1842,6 @@ void launch_updates(const Bufs &B, uint32_t m, uint64_t seq_off, hipStream_t s) 
          (const uint64_t *)B.ustamp, (const Ctl *)B.ctl, B.pos);
 }
 
-static Tree tree_of(const Bufs &B) {
-  return Tree{(const uint4 *)B.nodes, (const uint32_t *)B.table, (const uint32_t *)B.lstart,
-              (const uint32_t *)B.llevel, 0u};
-}
 
 void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t upd_total,
                   uint32_t nq, uint32_t key_bits, hipStream_t s) {
@@ -1991,7 +1982,7 @@ void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s) {
 const void *join_write_kernel() { return reinterpret_cast<const void *>(&k_join_write); }
 
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s) {
-  LAUNCH(k_ctl_out, 1, kWave, s, (const Ctl *)B.ctl, host);
+  LAUNCH(k_ctl_out, 1, kWave, s, B.ctl, host);
 }
 
 void launch_counters(const Bufs &B, uint64_t *out, hipStream_t s) {

@@ -214,3 +214,12 @@ def make(name: str, **overrides) -> Workload:
             spec[key] = overrides.pop(key)
     params.update(overrides)
     return Workload(name=name, params=params, **spec)
+
+
+def issuer_points(t: Tick):
+    """Points of k-nearest-neighbour queries: each issuer's position in the
+    tick's updates (every generator here updates every object on every tick,
+    in id order)."""
+    if len(t.ids) == 0 or int(t.ids[-1]) != len(t.ids) - 1:
+        raise ValueError("issuer_points needs a tick that updates objects 0..n-1 in order")
+    return t.x[t.qid], t.y[t.qid]
