@@ -150,12 +150,14 @@ typedef struct sj_config {
 
 /* Compressed results of the last tick (Sections "Bitmap decoding" and
  * "Optimizations").  The result of query k (input order of the tick) is a
- * list of runs of object ids:
+ * list of runs of object ids, reached through the query's processing
+ * position p = d_query_pos[k] (the tick processes large batches in a
+ * spatial order; p = k otherwise):
  *   intersecting part, one run per intersecting subquery (the decoded
  *     bitmap of the query against one leaf): for every slot s in
- *     [d_isect_slot_off[k], d_isect_slot_off[k+1]), run r = d_slot_run[s]
+ *     [d_isect_slot_off[p], d_isect_slot_off[p+1]), run r = d_slot_run[s]
  *     is d_isect_id[d_run_off[r] .. d_run_off[r+1]);
- *   covering part: for every c in [d_cov_off[k], d_cov_off[k+1]), leaf
+ *   covering part: for every c in [d_cov_off[p], d_cov_off[p+1]), leaf
  *     L = d_cov_leaf[c] contributes all objects
  *     d_sorted_id[d_leaf_beg[L] .. d_leaf_beg[L+1]).
  * Runs are stored in the join's order (the runs of one leaf's subqueries
@@ -175,11 +177,12 @@ typedef struct sj_results {
   uint64_t n_cov_entries;     /* = d_cov_off[nq] */
   uint64_t total_pairs;       /* sum over queries of |res(q)| */
   uint64_t n_runs;            /* intersecting subqueries = d_isect_slot_off[nq] */
-  const uint32_t *d_isect_slot_off; /* [nq + 1] */
+  const uint32_t *d_query_pos; /* [nq] processing position of query k */
+  const uint32_t *d_isect_slot_off; /* [nq + 1], by processing position */
   const uint32_t *d_slot_run;  /* [n_runs] */
   const uint64_t *d_run_off;   /* [n_runs + 1] */
   const uint32_t *d_isect_id;  /* [n_isect_ids] */
-  const uint32_t *d_cov_off;   /* [nq + 1] */
+  const uint32_t *d_cov_off;   /* [nq + 1], by processing position */
   const uint32_t *d_cov_leaf;
   const uint32_t *d_leaf_beg;  /* [n_leaves + 1] */
   const uint32_t *d_sorted_id; /* [n_present] object ids grouped by leaf,

@@ -48,7 +48,7 @@ class SjConfig(Structure):
 class SjResults(Structure):
     _fields_ = [("nq", c_uint32), ("n_leaves", c_uint32), ("n_isect_ids", c_uint64),
                 ("n_cov_entries", c_uint64), ("total_pairs", c_uint64), ("n_runs", c_uint64),
-                ("d_isect_slot_off", c_void_p), ("d_slot_run", c_void_p), ("d_run_off", c_void_p),
+                ("d_query_pos", c_void_p), ("d_isect_slot_off", c_void_p), ("d_slot_run", c_void_p), ("d_run_off", c_void_p),
                 ("d_isect_id", c_void_p), ("d_cov_off", c_void_p),
                 ("d_cov_leaf", c_void_p), ("d_leaf_beg", c_void_p), ("d_sorted_id", c_void_p),
                 ("n_present", c_uint32), ("n_tasks", c_uint32), ("n_subqueries", c_uint64),
@@ -208,6 +208,7 @@ class Results:
     on first access, so a fetch for the counters builds no tensor)."""
 
     _VIEWS = {  # attribute: (pointer field, length, dtype name)
+        "query_pos": ("d_query_pos", lambda r: r.nq, "int32"),
         "isect_slot_off": ("d_isect_slot_off", lambda r: r.nq + 1, "int32"),
         "slot_run": ("d_slot_run", lambda r: r.n_runs, "int32"),
         "run_off": ("d_run_off", lambda r: r.n_runs + 1, "int64"),

@@ -34,13 +34,13 @@ import numpy as np
 from . import binding, serving, workloads
 from .binding import PHASES, Scene
 
-CAND = (32, 64, 128, 256, 512, 1024)
+CAND = (32, 64, 128, 256, 384, 512, 768, 1024)
 MODEL_PATH = Path(__file__).resolve().parent / "data" / "cost_model.json"
 # tick phases whose time depends on the threshold (the sort of the ticks
 # that keep the tree through its leaf keys; the build is amortised over the
 # rebuild period and left out)
 COST_PHASES = ("index", "leaves", "split", "schedule", "join_count", "join_scan", "join_write")
-TRAIN_SETS = (("hotspot", 20), ("segments", 20))  # 2 x 6 thresholds x 17 logged ticks
+TRAIN_SETS = (("hotspot", 20), ("segments", 20))  # 2 x 8 thresholds x 17 logged ticks
 
 
 def _ptr(t):

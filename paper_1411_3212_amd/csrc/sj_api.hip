@@ -219,6 +219,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.q_nc = c.take<uint32_t>(Q);
   b.q_ioff = c.take<uint32_t>(Q + 1);
   b.q_coff = c.take<uint32_t>(Q + 1);
+  b.qpos = c.take<uint32_t>(Q);
   b.qlist = c.take<uint32_t>(Q * d.slots);
   b.sq = c.take<uint32_t>(d.S);
   b.slot_sq = c.take<uint32_t>(d.S);
@@ -807,6 +808,7 @@ int sj_fetch_results(sj_scene *s, sj_results *out) {
   out->d_run_off = s->B.res_off;
   out->d_isect_id = s->B.res_ids;
   out->d_cov_off = s->B.q_coff;
+  out->d_query_pos = s->B.qpos;
   out->d_cov_leaf = s->B.cov_leaf;
   out->d_leaf_beg = s->B.leaf_beg;
   out->d_sorted_id = s->B.valA;

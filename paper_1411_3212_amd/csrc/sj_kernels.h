@@ -43,7 +43,8 @@ struct Bufs {
   uint32_t *tleaf;                      // tasks in run order: leaf
   // queries and subqueries
   float4 *qrect;                        // rectangles in processing order
-  uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;
+  uint32_t *q_ni, *q_nc, *q_ioff, *q_coff;  // per query in processing order
+  uint32_t *qpos;                       // processing position of query k
   uint32_t *qlist;                      // visited leaves per query (slots each)
   uint32_t *sq;                         // subqueries grouped by leaf: index of the rectangle
   uint32_t *slot_sq;                    // per intersecting slot (query order): its subquery

@@ -783,9 +783,10 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
 // coordinates among the query's cells of that leaf), in cell order, then
 // the internal nodes of the round one after the other, each walked by its
 // lane.  Queries over more than kTableScanMax cells are walked from the
-// root by the group's first lane.  visit(leaf, covering, idx, ri, rc)
-// receives the leaf's index in the query's list and its rank among the
-// intersecting (ri) or covering (rc) entries.  Inactive leaves are skipped.
+// root by the group's first lane.  visit(leaf, covering, idx, ri, rc, cnt)
+// receives the leaf's index in the query's list, its rank among the
+// intersecting (ri) or covering (rc) entries and its object count.
+// Inactive leaves are skipped.
 constexpr uint32_t kSplitGroup = 16;
 constexpr uint32_t kSplitBatch = 4;  // rounds of table cells whose loads go out together
 
@@ -858,7 +859,7 @@ __device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *sta
         }
       }
       const uint64_t ma = ballot(a) & gm, mc = ballot(cv) & gm, mi = ma & ~mc;
-      if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc));
+      if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc), le[j] - lb[j]);
       nl += (uint32_t)__popcll(ma);
       ni += (uint32_t)__popcll(mi);
       nc += (uint32_t)__popcll(mc);
@@ -869,9 +870,10 @@ __device__ __forceinline__ LeafCounts group_leaves(const Tree &tr, uint32_t *sta
         uint32_t dl = 0, di = 0, dc = 0;
         if (lane == bl) {
           auto v = [&](uint32_t lf, bool cov0) {
-            if (leaf_beg[lf + 1] == leaf_beg[lf]) return;
+            const uint32_t cnt = leaf_beg[lf + 1] - leaf_beg[lf];
+            if (cnt == 0u) return;
             const bool cc = cov0 && covering;
-            visit(lf, cc, nl + dl, ni + di, nc + dc);
+            visit(lf, cc, nl + dl, ni + di, nc + dc, cnt);
             ++dl;
             if (cc)
               ++dc;
@@ -907,15 +909,16 @@ __device__ __forceinline__ LeafCounts grid_leaves(uint32_t s, const QBox q,
   for (uint64_t c0 = 0; c0 < ncell; c0 += kSplitGroup) {
     const uint64_t c = c0 + gl;
     bool a = false, cv = false;
-    uint32_t leaf = 0;
+    uint32_t leaf = 0, cnt = 0;
     if (c < ncell) {
       const uint32_t ci = i0 + (uint32_t)(c % w), cj = j0 + (uint32_t)(c / w);
       leaf = morton2(ci, cj);
-      a = leaf_beg[leaf + 1] != leaf_beg[leaf];
+      cnt = leaf_beg[leaf + 1] - leaf_beg[leaf];
+      a = cnt != 0u;
       cv = a && covering && i0 < ci && ci < i1 && j0 < cj && cj < j1;
     }
     const uint64_t ma = ballot(a) & gm, mc = ballot(cv) & gm, mi = ma & ~mc;
-    if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc));
+    if (a) visit(leaf, cv, nl + mbcnt(ma), ni + mbcnt(mi), nc + mbcnt(mc), cnt);
     nl += (uint32_t)__popcll(ma);
     ni += (uint32_t)__popcll(mi);
     nc += (uint32_t)__popcll(mc);
@@ -943,17 +946,23 @@ __global__ void __launch_bounds__(kBlock) k_qorder_keys(Ctl *ctl, const TickIn *
 }
 
 // Count pass, one query per group of kSplitGroup lanes: the numbers of
-// intersecting and covering subqueries per query; the first `slots`
-// entries of a query's list (leaf, covering flag) are kept for the write
-// pass.  The rectangle of the g-th query in processing order is stored at
+// intersecting and covering subqueries per query, and the pairs the
+// covering leaves give (per-block partials added into red's 1,024 slots,
+// cleared before the pass); the first `slots` entries of a query's list
+// (leaf, covering flag) are kept for the write pass.  Per-query arrays are
+// indexed by the processing position g (qpos[k] = g), so the scans hand out
+// slots in processing order: the subqueries of a spatially ordered batch's
+// neighbouring queries get neighbouring slots.  The rectangle of the g-th query in processing order is stored at
 // qrect[g], so that the subqueries of one leaf (queries that lie close
 // together, processed close together in a spatially ordered batch) read
 // nearby rectangles in the join.
 __global__ void __launch_bounds__(kBlock) k_q_count(
     Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, float4 *qrect, uint32_t *q_ni, uint32_t *q_nc, uint32_t *qlist,
-    uint32_t slots, uint32_t covering, const uint32_t *qord) {
+    uint32_t slots, uint32_t covering, const uint32_t *qord, uint32_t *qpos, uint64_t *red) {
   __shared__ uint32_t stack[kFine * kBlock];
+  __shared__ uint64_t lds[kWavesPerBlock];
+  uint64_t covp = 0;
   const uint32_t *__restrict__ qid = tin->qid;
   const float *__restrict__ xa = tin->xa, *__restrict__ ya = tin->ya, *__restrict__ xb = tin->xb,
                             *__restrict__ yb = tin->yb;
@@ -971,9 +980,10 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     const float4 r = make_float4(xa[k], ya[k], xb[k], yb[k]);
     QBox q;
     if (query_box(ctl, k, qid[k], N, qstamp, seq, r, &q, &bad_rect) && tree_ok) {
-      uint32_t *lst = qlist + (uint64_t)k * slots;
-      auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t, uint32_t) {
+      uint32_t *lst = qlist + (uint64_t)g * slots;
+      auto visit = [&](uint32_t leaf, bool c, uint32_t i, uint32_t, uint32_t, uint32_t cnt) {
         if (i < slots) lst[i] = leaf | (c ? kLeafBit : 0u);
+        if (c) covp += cnt;
       };
       const LeafCounts n =
           ug ? grid_leaves(ug, q, leaf_beg, covering, lane, gm, visit)
@@ -983,10 +993,21 @@ __global__ void __launch_bounds__(kBlock) k_q_count(
     }
     if (gl == 0) {
       qrect[g] = r;
-      q_ni[k] = ni;
-      q_nc[k] = nc;
+      q_ni[g] = ni;
+      q_nc[g] = nc;
+      qpos[k] = g;
     }
     flag_error(ctl, kErrQueryRect, bad_rect);
+  }
+  covp = wave_sum(covp);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = covp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kWavesPerBlock; ++w) t += lds[w];
+    if (t) atomicAdd((unsigned long long *)&red[kRedCovPairs * kChunkBlocks +
+                                                (blockIdx.x & (kChunkBlocks - 1))],
+                     (unsigned long long)t);
   }
 }
 
@@ -1023,7 +1044,7 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
   ctl->n32[1] = err ? 0u : (uint32_t)tot[1];
 }
 
-// Write pass, one query per group, in query order: every intersecting
+// Write pass, one query per group, in processing order: every intersecting
 // subquery's leaf at its slot (skey[slot]; sval[slot] = slot, the value the
 // sort by leaf carries; sg[slot] = g, the index of its query's rectangle),
 // covering leaves per query.  A query whose list fit reads it back,
@@ -1036,10 +1057,8 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
     const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, uint32_t slots,
     uint32_t *skey, uint32_t *sval, uint32_t *sg, uint32_t *cov_leaf, uint32_t covering,
-    uint64_t *red, const uint32_t *qord) {
+    const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
-  __shared__ uint64_t lds[kWavesPerBlock];
-  uint64_t covp = 0;
   if (ctl->go_split) {
     const uint32_t *__restrict__ qid = tin->qid;
     const uint64_t seq = ctl->qry_seq;
@@ -1049,14 +1068,12 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
     const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
     for (uint32_t g = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; g < nq; g += ngroups) {
-      const uint32_t k = qord ? qord[g] : g;
-      const uint32_t n = q_ni[k] + q_nc[k];
+      const uint32_t n = q_ni[g] + q_nc[g];
       if (n == 0) continue;
-      const uint32_t wi = q_ioff[k], wc = q_coff[k];
+      const uint32_t wi = q_ioff[g], wc = q_coff[g];
       auto put = [&](uint32_t leaf, bool c, uint32_t ri, uint32_t rc) {
         if (c) {
           cov_leaf[wc + rc] = leaf;
-          covp += leaf_beg[leaf + 1] - leaf_beg[leaf];
         } else {
           skey[wi + ri] = leaf;
           sval[wi + ri] = wi + ri;
@@ -1064,7 +1081,7 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
         }
       };
       if (n <= slots) {
-        const uint32_t *lst = qlist + (uint64_t)k * slots;
+        const uint32_t *lst = qlist + (uint64_t)g * slots;
         uint32_t ri = 0, rc = 0;
         for (uint32_t i0 = 0; i0 < n; i0 += kSplitGroup) {
           const uint32_t i = i0 + gl;
@@ -1077,10 +1094,11 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
           rc += (uint32_t)__popcll(mc);
         }
       } else {
+        const uint32_t k = qord ? qord[g] : g;
         QBox q;
         bool bad_rect;
         query_box(ctl, k, qid[k], N, qstamp, seq, qrect[g], &q, &bad_rect);
-        auto visit = [&](uint32_t leaf, bool c, uint32_t, uint32_t ri, uint32_t rc) {
+        auto visit = [&](uint32_t leaf, bool c, uint32_t, uint32_t ri, uint32_t rc, uint32_t) {
           put(leaf, c, ri, rc);
         };
         if (ug)
@@ -1089,14 +1107,6 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
           group_leaves(tr, stack + threadIdx.x, q, leaf_beg, covering, lane, gm, visit);
       }
     }
-  }
-  covp = wave_sum(covp);
-  if (lane_id() == 0) lds[threadIdx.x / kWave] = covp;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = 0;
-    for (int w = 0; w < kWavesPerBlock; ++w) t += lds[w];
-    red[kRedCovPairs * kChunkBlocks + blockIdx.x] = t;
   }
 }
 
@@ -1910,9 +1920,11 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
                                       B.hist, B.tot, 0, 16, s);
     qord = alt ? B.qord2 : B.qord;
   }
+  LAUNCH(k_fill_u64, 4, kBlock, s, B.red + (uint64_t)kRedCovPairs * kChunkBlocks,
+         (uint64_t)kChunkBlocks, 0ull);
   LAUNCH(k_q_count, grid_for((uint64_t)nq * kSplitGroup, 8192), kBlock, s, B.ctl, tin, nq, B.N,
          (const uint64_t *)B.qstamp, tree_of(B), (const uint32_t *)B.leaf_beg, B.qrect, B.q_ni,
-         B.q_nc, B.qlist, B.slots, covering, qord);
+         B.q_nc, B.qlist, B.slots, covering, qord, B.qpos, B.red);
   ScanJobs jobs{};
   jobs.j[0] = job_u32(B.q_ni, B.q_ioff, nullptr, nq);
   jobs.j[1] = job_u32(B.q_nc, B.q_coff, nullptr, nq);
@@ -1927,7 +1939,7 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
          (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots, skey, sval, B.slot_sq,
-         B.cov_leaf, covering, B.red, qord);
+         B.cov_leaf, covering, qord);
   radix_sort_pairs(skey, sval, k1, v1, &B.ctl->n32[0], B.S, &B.ctl->go_split, B.hist, B.tot, 0,
                    32, s, nullptr, nullptr, &B.ctl->sq_skip);
   LAUNCH(k_sq_final, grid_for(B.S, 4096), kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)skey,

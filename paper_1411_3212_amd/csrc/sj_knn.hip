@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(kBlock) k_knn_radius(
 // at a time (lane i holds segment i's start and length), their elements
 // 64 at a time across segment boundaries.
 struct KnnIn {
-  const uint32_t *q_ioff, *slot_sq, *res_ids, *q_coff, *cov_leaf, *leaf_beg, *sid;
+  const uint32_t *q_ioff, *slot_sq, *res_ids, *q_coff, *cov_leaf, *leaf_beg, *sid, *qpos;
   const uint64_t *res_off;
   const float2 *pos, *sxy;
 };
@@ -268,7 +268,8 @@ __global__ void __launch_bounds__(kBlock) k_knn_select(
       continue;
     }
     uint64_t n = 0;
-    const uint32_t s0 = I.q_ioff[q], s1 = I.q_ioff[q + 1];
+    const uint32_t pq = I.qpos[q];  // the query's processing position: its slots
+    const uint32_t s0 = I.q_ioff[pq], s1 = I.q_ioff[pq + 1];
     for (uint32_t s = s0; s < s1; s += kWave) {
       uint64_t b = 0;
       uint32_t len = 0;
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(kBlock) k_knn_select(
       }
       n += add_segments(I, b, len, true, x, y, k, lane, &best);
     }
-    const uint32_t c0 = I.q_coff[q], c1 = I.q_coff[q + 1];
+    const uint32_t c0 = I.q_coff[pq], c1 = I.q_coff[pq + 1];
     for (uint32_t c = c0; c < c1; c += kWave) {
       uint64_t b = 0;
       uint32_t len = 0;
@@ -351,7 +352,7 @@ void launch_knn_radius(const Bufs &B, const float *qx, const float *qy, uint32_t
 void launch_knn_select(const Bufs &B, const float *qx, const float *qy, uint32_t nq, uint32_t k,
                        uint32_t *out_id, float *out_d2, hipStream_t s) {
   if (!nq) return;
-  KnnIn I{B.q_ioff, B.slot_sq, B.res_ids, B.q_coff, B.cov_leaf, B.leaf_beg, B.valA,
+  KnnIn I{B.q_ioff, B.slot_sq, B.res_ids, B.q_coff, B.cov_leaf, B.leaf_beg, B.valA, B.qpos,
           B.res_off, (const float2 *)B.pos, (const float2 *)B.sxy};
   LAUNCH(k_knn_select, wave_grid(nq), kBlock, s, B.ctl, (const TickIn *)B.tin, qx, qy, nq, B.N,
          (const uint64_t *)B.qstamp, I, (const float *)B.kq_rect, B.Q, k, out_id, out_d2,

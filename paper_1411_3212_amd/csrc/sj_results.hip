@@ -7,13 +7,14 @@
 namespace sj {
 
 
-// The results of query k are runs of ids: for every intersecting slot s in
-// [q_ioff[k], q_ioff[k+1]), the run of subquery i = slot_sq[s],
-// res_ids[res_off[i] .. res_off[i+1]); for every covering leaf L in
-// cov_leaf[q_coff[k] .. q_coff[k+1]), its objects sid[leaf_beg[L] ..
-// leaf_beg[L+1]).  A wave takes a query and walks its runs in that order.
+// The results of query k, at processing position p = qpos[k], are runs of
+// ids: for every intersecting slot s in [q_ioff[p], q_ioff[p+1]), the run of
+// subquery i = slot_sq[s], res_ids[res_off[i] .. res_off[i+1]); for every
+// covering leaf L in cov_leaf[q_coff[p] .. q_coff[p+1]), its objects
+// sid[leaf_beg[L] .. leaf_beg[L+1]).  A wave takes a query and walks its
+// runs in that order.
 struct Runs {
-  const uint32_t *q_ioff, *slot_sq, *res_ids, *q_coff, *cov_leaf, *leaf_beg, *sid;
+  const uint32_t *q_ioff, *slot_sq, *res_ids, *q_coff, *cov_leaf, *leaf_beg, *sid, *qpos;
   const uint64_t *res_off;
   uint32_t isect;  // 0: the intersecting results are appended pairs, not runs
 };
@@ -22,13 +23,14 @@ struct Runs {
 template <typename F>
 __device__ __forceinline__ uint64_t for_each_id(const Runs &R, uint32_t k, uint32_t lane, F f) {
   uint64_t pos = 0;
-  for (uint32_t s = R.isect ? R.q_ioff[k] : 0u; s < (R.isect ? R.q_ioff[k + 1] : 0u); ++s) {
+  const uint32_t p = R.qpos[k];
+  for (uint32_t s = R.isect ? R.q_ioff[p] : 0u; s < (R.isect ? R.q_ioff[p + 1] : 0u); ++s) {
     const uint32_t i = R.slot_sq[s];
     const uint64_t a = R.res_off[i], b = R.res_off[i + 1];
     for (uint64_t j = a + lane; j < b; j += kWave) f(R.res_ids[j], pos + (j - a));
     pos += b - a;
   }
-  for (uint32_t e = R.q_coff[k]; e < R.q_coff[k + 1]; ++e) {
+  for (uint32_t e = R.q_coff[p]; e < R.q_coff[p + 1]; ++e) {
     const uint32_t leaf = R.cov_leaf[e];
     const uint32_t lb = R.leaf_beg[leaf], le = R.leaf_beg[leaf + 1];
     for (uint32_t j = lb + lane; j < le; j += kWave) f(R.sid[j], pos + (j - lb));
@@ -40,11 +42,12 @@ __device__ __forceinline__ uint64_t for_each_id(const Runs &R, uint32_t k, uint3
 // Result size of query k (one thread).
 __device__ __forceinline__ uint64_t result_size(const Runs &R, uint32_t k) {
   uint64_t c = 0;
-  for (uint32_t s = R.isect ? R.q_ioff[k] : 0u; s < (R.isect ? R.q_ioff[k + 1] : 0u); ++s) {
+  const uint32_t p = R.qpos[k];
+  for (uint32_t s = R.isect ? R.q_ioff[p] : 0u; s < (R.isect ? R.q_ioff[p + 1] : 0u); ++s) {
     const uint32_t i = R.slot_sq[s];
     c += R.res_off[i + 1] - R.res_off[i];
   }
-  for (uint32_t e = R.q_coff[k]; e < R.q_coff[k + 1]; ++e)
+  for (uint32_t e = R.q_coff[p]; e < R.q_coff[p + 1]; ++e)
     c += R.leaf_beg[R.cov_leaf[e] + 1] - R.leaf_beg[R.cov_leaf[e]];
   return c;
 }
@@ -159,7 +162,8 @@ static Runs runs_of(const Bufs &B) {
   return Runs{(const uint32_t *)B.q_ioff,  (const uint32_t *)B.slot_sq,
               (const uint32_t *)B.res_ids, (const uint32_t *)B.q_coff,
               (const uint32_t *)B.cov_leaf, (const uint32_t *)B.leaf_beg,
-              (const uint32_t *)B.valA,    (const uint64_t *)B.res_off,
+              (const uint32_t *)B.valA,    (const uint32_t *)B.qpos,
+              (const uint64_t *)B.res_off,
               B.pairs ? 0u : 1u};
 }
 

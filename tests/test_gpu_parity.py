@@ -110,9 +110,11 @@ def test_split_and_work_counters_equal_oracle(th):
     assert s["cov_pairs"] == int(cnt[lc_act].sum())
     co = r.cov_off.cpu().numpy().view(np.uint32)
     cl = r.cov_leaf.cpu().numpy().view(np.uint32)
+    qp = r.query_pos.cpu().numpy().view(np.uint32)
     for k in range(t.nq):
         want = [x for x in lc[oc[k]:oc[k + 1]] if cnt[x] > 0]
-        assert sorted(cl[co[k]:co[k + 1]].tolist()) == want
+        p = qp[k]
+        assert sorted(cl[co[p]:co[p + 1]].tolist()) == want
 
 
 def test_edges_corners_signed_zero_and_degenerate_queries():
@@ -224,7 +226,8 @@ def test_outputs_are_deterministic_and_expand_matches():
         sc = run_scene(wl.n, t, th=16)
         r = sc.fetch()
         outs.append([x.cpu().numpy().tobytes() for x in
-                     (r.isect_slot_off, r.slot_run, r.run_off, r.isect_id, r.cov_off, r.cov_leaf,
+                     (r.query_pos, r.isect_slot_off, r.slot_run, r.run_off, r.isect_id, r.cov_off,
+                      r.cov_leaf,
                       r.leaf_beg, r.sorted_id)])
         off, ids = sc.expand()
         off, ids = off.cpu().numpy(), ids.cpu().numpy()
@@ -421,9 +424,11 @@ def test_graph_ticks_equal_eager_ticks():
         if k % 2 == 1:  # ticks the host has not fetched: device decides
             continue
         re, rg = eager.fetch(), graph.fetch()
-        for a, b in zip((re.isect_slot_off, re.slot_run, re.run_off, re.isect_id, re.cov_off,
+        for a, b in zip((re.query_pos, re.isect_slot_off, re.slot_run, re.run_off, re.isect_id,
+                         re.cov_off,
                          re.cov_leaf, re.leaf_beg),
-                        (rg.isect_slot_off, rg.slot_run, rg.run_off, rg.isect_id, rg.cov_off,
+                        (rg.query_pos, rg.isect_slot_off, rg.slot_run, rg.run_off, rg.isect_id,
+                         rg.cov_off,
                          rg.cov_leaf, rg.leaf_beg)):
             assert torch.equal(a, b)
         cnt, h = gpu_count_hash(graph)

@@ -63,8 +63,10 @@ def test_grid_index_split_and_results_equal_oracle(s):
     r = sc.fetch()
     co = r.cov_off.cpu().numpy().view(np.uint32)
     cl = r.cov_leaf.cpu().numpy().view(np.uint32)
+    qp = r.query_pos.cpu().numpy().view(np.uint32)
     for k in range(t.nq):
-        assert sorted(cl[co[k]:co[k + 1]].tolist()) == sorted(lc[oc[k]:oc[k + 1]].tolist())
+        p = qp[k]
+        assert sorted(cl[co[p]:co[p + 1]].tolist()) == sorted(lc[oc[k]:oc[k + 1]].tolist())
 
 
 @pytest.mark.parametrize("covering,reorder", [(False, True), (True, False)])
