@@ -1671,6 +1671,106 @@ __device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff,
   write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
 }
 
+// Tasks of one object block (at most kJoinRegChunks x 64 objects) produce
+// their ids in address order: the runs of a task's subqueries are adjacent,
+// and each subquery's hits come chunk by chunk.  Such a task stages its ids
+// in the wave's LDS slice and stores them 64 at a time, full and
+// consecutive, instead of one partial store per subquery and chunk.
+constexpr uint32_t kStage = 1024;  // staged ids per wave
+
+// Stores the staged ids [0, fill) at res_ids[gbase ..): every full 64 (all:
+// every one), the rest moved to the front of the slice.
+__device__ __forceinline__ void stage_flush(uint32_t *stage, uint32_t &fill, uint64_t &gbase,
+                                            uint32_t *__restrict__ res_ids, uint32_t lane,
+                                            bool all) {
+  wave_lds_fence();
+  const uint32_t nfull = fill & ~((uint32_t)kWave - 1u);
+  for (uint32_t j = 0; j < nfull; j += (uint32_t)kWave) res_ids[gbase + j + lane] = stage[j + lane];
+  const uint32_t rem = fill - nfull;
+  if (all) {
+    if (lane < rem) res_ids[gbase + nfull + lane] = stage[nfull + lane];
+    gbase += fill;
+    fill = 0;
+    return;
+  }
+  const uint32_t v = lane < rem ? stage[nfull + lane] : 0u;
+  wave_lds_fence();  // every read above is done before the slice is overwritten
+  if (lane < rem) stage[lane] = v;
+  gbase += nfull;
+  fill = rem;
+}
+
+template <uint32_t NCH>
+__device__ __forceinline__ void stage_rounds(const float4 *wrect, uint32_t nk, const float2 *p,
+                                             const uint64_t *h, const uint32_t *id,
+                                             uint32_t *stage, uint32_t &fill, uint64_t &gbase,
+                                             uint32_t *__restrict__ res_ids, uint32_t lane) {
+  for (uint32_t kk = 0; kk < nk; ++kk) {
+    if (fill > kStage - (uint32_t)kWave * NCH) stage_flush(stage, fill, gbase, res_ids, lane, false);
+    const float4 r = wrect[kk];
+#pragma unroll
+    for (uint32_t c = 0; c < NCH; ++c) {
+      const uint64_t m = hits(r, p[c], h[c]);
+      if (__builtin_amdgcn_inverse_ballot_w64(m)) stage[fill + mbcnt(m)] = id[c];
+      fill += (uint32_t)__popcll(m);
+    }
+  }
+}
+
+// A one-block task: loads as write_first, ids staged from the task's first
+// result offset on.
+template <uint32_t NCH>
+__device__ __forceinline__ void write_staged(float4 *wrect, uint32_t nk,
+                                             const float2 *__restrict__ sxy,
+                                             const uint32_t *__restrict__ sid, uint32_t ob,
+                                             uint32_t oe, const float4 *__restrict__ qrect,
+                                             const uint64_t *__restrict__ res_off, uint32_t e,
+                                             uint32_t sb, uint32_t lane, uint32_t *stage,
+                                             uint32_t *__restrict__ res_ids) {
+  float2 p[NCH];
+  uint64_t h[NCH];
+  uint32_t id[NCH];
+  load_chunks<NCH>(sxy, ob, oe, lane, p, h);
+  load_ids<NCH>(sid, ob, oe, lane, id);
+  uint64_t gbase = res_off[sb];
+  if (lane < nk) wrect[lane] = qrect[e];
+  wave_lds_fence();
+  uint32_t fill = 0;
+  stage_rounds<NCH>(wrect, nk, p, h, id, stage, fill, gbase, res_ids, lane);
+  stage_flush(stage, fill, gbase, res_ids, lane, true);
+}
+
+// write_half with staging: a round stages subquery kk's hits (low half)
+// and then kk + 1's (high half).
+__device__ __forceinline__ void write_half_staged(float4 *wrect, uint32_t nk,
+                                                  const float2 *__restrict__ sxy,
+                                                  const uint32_t *__restrict__ sid, uint32_t ob,
+                                                  uint32_t oe, const float4 *__restrict__ qrect,
+                                                  const uint64_t *__restrict__ res_off,
+                                                  uint32_t e, uint32_t sb, uint32_t lane,
+                                                  uint32_t *stage,
+                                                  uint32_t *__restrict__ res_ids) {
+  const uint32_t half = lane >> 5, i = min(ob + (lane & 31u), oe - 1u);
+  const uint64_t h = ballot(ob + (lane & 31u) < oe);
+  const float2 p = sxy[i];
+  const uint32_t id = sid[i];
+  uint64_t gbase = res_off[sb];
+  if (lane < nk) wrect[lane] = qrect[e];
+  wave_lds_fence();
+  uint32_t fill = 0;
+  for (uint32_t kk = 0; kk < nk; kk += 2) {
+    if (fill > kStage - (uint32_t)kWave) stage_flush(stage, fill, gbase, res_ids, lane, false);
+    const float4 rk = wrect[min(kk + half, nk - 1u)];
+    uint64_t m = hits(rk, p, h);
+    if (kk + 1u >= nk) m &= kLowHalf;
+    const uint32_t lo = (uint32_t)__popcll(m & kLowHalf);
+    if (__builtin_amdgcn_inverse_ballot_w64(m))
+      stage[fill + (half ? lo + mbcnt(m & ~kLowHalf) : mbcnt(m & kLowHalf))] = id;
+    fill += (uint32_t)__popcll(m);
+  }
+  stage_flush(stage, fill, gbase, res_ids, lane, true);
+}
+
 // The write pass puts the results of the subqueries in subquery order: task
 // by task, the runs of a task's subqueries are adjacent, so the pass stores
 // its ids as one contiguous stream and reads its offsets in order; a
@@ -1686,6 +1786,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
                                                        uint32_t nq, float *tlog) {
   __shared__ float4 lrect[kBlock];
   __shared__ uint64_t loff[kBlock];
+  __shared__ uint32_t lstage[kWavesPerBlock * kStage];
   const bool go = ctl->go_join != 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->qry_seq += nq;
@@ -1699,6 +1800,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint64_t *woff = loff + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  uint32_t *stage = lstage + (threadIdx.x / kWave) * kStage;
   if (w0 >= nt) return;
   const uint32_t *trec32 = (const uint32_t *)trec;
   uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
@@ -1720,16 +1822,16 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     const bool more = ob + (uint32_t)kWave * kJoinRegChunks < oe;
     wave_lds_fence();
     if (oe - ob <= 32u)
-      write_half(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids);
+      write_half_staged(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage,
+                        res_ids);
     else if (nch <= 1u)
-      write_first<1>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
-                     more);
+      write_staged<1>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
     else if (nch <= 2u)
-      write_first<2>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
-                     more);
+      write_staged<2>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
     else if (nch <= 4u)
-      write_first<4>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
-                     more);
+      write_staged<4>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
+    else if (!more)
+      write_staged<8>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
     else
       write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
                      more);

@@ -208,7 +208,10 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   const int role = pass_role(skip, shift);
   if (role == kPassNone) return;
   const bool gather = GATHER && gather_pass(skip, shift, last_shift);
-  __shared__ uint32_t cnt[kSortItems * kWavesPerBlock * 256];
+  // per (row, wave, digit) counts, then their running offsets (at most a
+  // tile, 2,048): 16 bits each, so that four blocks fit a CU's LDS
+  __shared__ uint16_t cnt[kSortItems * kWavesPerBlock * 256];
+  static_assert(kSortTile <= 65535, "tile offsets fit 16 bits");
   __shared__ uint32_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
   __shared__ uint32_t goff[256], tbase[256], tcnt[256];
@@ -255,15 +258,16 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
         m &= b ? bb : ~bb;
       }
       rank[r] = mbcnt(m);
-      if (valid && rank[r] == 0) cnt[(r * kWavesPerBlock + w) * 256 + dig[r]] = (uint32_t)__popcll(m);
+      if (valid && rank[r] == 0)
+        cnt[(r * kWavesPerBlock + w) * 256 + dig[r]] = (uint16_t)__popcll(m);
     }
     __syncthreads();
     // thread d: exclusive running count of digit d over (sub-tile, wave)
     uint32_t run = 0;
 #pragma unroll
     for (int rw = 0; rw < kSortItems * kWavesPerBlock; ++rw) {
-      uint32_t c = cnt[rw * 256 + tid];
-      cnt[rw * 256 + tid] = run;
+      const uint32_t c = cnt[rw * 256 + tid];
+      cnt[rw * 256 + tid] = (uint16_t)run;
       run += c;
     }
     {
