@@ -1315,6 +1315,23 @@ __global__ void __launch_bounds__(kBlock) k_task_place(Ctl *ctl, const uint32_t 
 // against a chunk are one ballot per rectangle bound: the count pass adds
 // their popcount, the write pass compacts the hits with each lane's rank
 // among them.
+// The containment test on integer keys: the key of a binary32 coordinate
+// orders like the value (IEEE comparison, with -0 equal to +0), so
+// xa <= x <= xb is the unsigned range check key(x) - key(xa) <= key(xb) -
+// key(xa): two compares per subquery and object instead of four, and half
+// the lane masks to combine.
+__device__ __forceinline__ uint32_t ckey(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return u == 0x80000000u ? 0x80000000u : ((u & 0x80000000u) ? ~u : (u | 0x80000000u));
+}
+__device__ __forceinline__ uint2 pos_key(float2 p) { return make_uint2(ckey(p.x), ckey(p.y)); }
+// (key(xa), key(xb) - key(xa), key(ya), key(yb) - key(ya)) of a valid
+// rectangle (xa <= xb, ya <= yb, finite).
+__device__ __forceinline__ uint4 rect_key(float4 r) {
+  const uint32_t xa = ckey(r.x), ya = ckey(r.y);
+  return make_uint4(xa, ckey(r.z) - xa, ya, ckey(r.w) - ya);
+}
+
 constexpr uint32_t kJoinRegChunks = 8;  // object chunks of 64 in registers
 static_assert(kTaskSub <= (uint32_t)kWave, "a task's subqueries fit one wave");
 
@@ -1358,12 +1375,12 @@ __device__ __forceinline__ uint32_t sq_entry(const uint32_t *__restrict__ sq, co
 // which the mask excludes.
 template <uint32_t NCH>
 __device__ __forceinline__ void load_chunks(const float2 *__restrict__ sxy, uint32_t o0,
-                                            uint32_t oe, uint32_t lane, float2 *p, uint64_t *h) {
+                                            uint32_t oe, uint32_t lane, uint2 *p, uint64_t *h) {
 #pragma unroll
   for (uint32_t c = 0; c < NCH; ++c) {
     const uint32_t i = o0 + c * (uint32_t)kWave + lane;
     h[c] = ballot(i < oe);
-    p[c] = sxy[min(i, oe - 1u)];
+    p[c] = pos_key(sxy[min(i, oe - 1u)]);
   }
 }
 
@@ -1376,19 +1393,19 @@ __device__ __forceinline__ void load_ids(const uint32_t *__restrict__ sid, uint3
 
 // Lanes whose object lies in the closed rectangle r: one ballot per bound,
 // so the four comparisons stay lane masks.
-__device__ __forceinline__ uint64_t hits(const float4 r, const float2 p, uint64_t h) {
-  return ballot(r.x <= p.x) & ballot(p.x <= r.z) & ballot(r.y <= p.y) & ballot(p.y <= r.w) & h;
+__device__ __forceinline__ uint64_t hits(const uint4 r, const uint2 p, uint64_t h) {
+  return ballot(p.x - r.x <= r.y) & ballot(p.y - r.z <= r.w) & h;
 }
 
 // Hits of subqueries 0..nk-1 against NCH chunks; lane kk returns subquery
 // kk's.
 template <uint32_t NCH>
-__device__ __forceinline__ uint32_t count_rounds(const float4 *wrect, uint32_t nk,
-                                                 const float2 *p, const uint64_t *h,
+__device__ __forceinline__ uint32_t count_rounds(const uint4 *wrect, uint32_t nk,
+                                                 const uint2 *p, const uint64_t *h,
                                                  uint32_t lane) {
   uint32_t blk = 0;
   for (uint32_t kk = 0; kk < nk; ++kk) {
-    const float4 r = wrect[kk];
+    const uint4 r = wrect[kk];
     uint32_t tot = 0;
 #pragma unroll
     for (uint32_t c = 0; c < NCH; ++c) tot += (uint32_t)__popcll(hits(r, p[c], h[c]));
@@ -1400,16 +1417,16 @@ __device__ __forceinline__ uint32_t count_rounds(const float4 *wrect, uint32_t n
 // First block of a task: its object loads go out with the gathers of the
 // subquery rectangles (lane kk < nk: subquery kk's, returned in *r).
 template <uint32_t NCH>
-__device__ __forceinline__ uint32_t count_first(float4 *wrect, uint32_t nk,
+__device__ __forceinline__ uint32_t count_first(uint4 *wrect, uint32_t nk,
                                                 const float2 *__restrict__ sxy, uint32_t ob,
                                                 uint32_t oe, const float4 *__restrict__ qrect,
                                                 uint32_t e, uint32_t lane, float4 *r) {
-  float2 p[NCH];
+  uint2 p[NCH];
   uint64_t h[NCH];
   load_chunks<NCH>(sxy, ob, oe, lane, p, h);
   if (lane < nk) {
     *r = qrect[e];
-    wrect[lane] = *r;
+    wrect[lane] = rect_key(*r);
   }
   wave_lds_fence();
   return count_rounds<NCH>(wrect, nk, p, h, lane);
@@ -1420,21 +1437,21 @@ __device__ __forceinline__ uint32_t count_first(float4 *wrect, uint32_t nk,
 // low half and kk + 1 on the high half.
 constexpr uint64_t kLowHalf = 0xffffffffull;
 
-__device__ __forceinline__ uint32_t count_half(float4 *wrect, uint32_t nk,
+__device__ __forceinline__ uint32_t count_half(uint4 *wrect, uint32_t nk,
                                                const float2 *__restrict__ sxy, uint32_t ob,
                                                uint32_t oe, const float4 *__restrict__ qrect,
                                                uint32_t e, uint32_t lane, float4 *r) {
   const uint32_t half = lane >> 5, i = ob + (lane & 31u);
   const uint64_t h = ballot(i < oe);
-  const float2 p = sxy[min(i, oe - 1u)];
+  const uint2 p = pos_key(sxy[min(i, oe - 1u)]);
   if (lane < nk) {
     *r = qrect[e];
-    wrect[lane] = *r;
+    wrect[lane] = rect_key(*r);
   }
   wave_lds_fence();
   uint32_t blk = 0;
   for (uint32_t kk = 0; kk < nk; kk += 2) {
-    const float4 rk = wrect[min(kk + half, nk - 1u)];
+    const uint4 rk = wrect[min(kk + half, nk - 1u)];
     uint64_t m = hits(rk, p, h);
     if (kk + 1u >= nk) m &= kLowHalf;  // no second subquery
     const uint32_t lo = (uint32_t)__popcll(m & kLowHalf), hi = (uint32_t)__popcll(m >> 32);
@@ -1445,10 +1462,10 @@ __device__ __forceinline__ uint32_t count_half(float4 *wrect, uint32_t nk,
 
 // A further block of a long leaf.
 template <uint32_t NCH>
-__device__ __forceinline__ uint32_t count_block(const float4 *wrect, uint32_t nk,
+__device__ __forceinline__ uint32_t count_block(const uint4 *wrect, uint32_t nk,
                                                 const float2 *__restrict__ sxy, uint32_t o0,
                                                 uint32_t oe, uint32_t lane) {
-  float2 p[NCH];
+  uint2 p[NCH];
   uint64_t h[NCH];
   load_chunks<NCH>(sxy, o0, oe, lane, p, h);
   return count_rounds<NCH>(wrect, nk, p, h, lane);
@@ -1461,7 +1478,7 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
              const uint32_t *__restrict__ sq, const float4 *__restrict__ qrect,
              const float2 *__restrict__ sxy, uint32_t *sq_cnt, float *tlog, const uint32_t *lstart,
              const uint32_t *llevel, uint64_t *cu_tests) {
-  __shared__ float4 lrect[kBlock];
+  __shared__ uint4 lrect[kBlock];
   if (!ctl->go_split) return;
   const uint32_t nt = ctl->n_run;
   const uint32_t lane = lane_id();
@@ -1469,7 +1486,7 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (w0 >= nt) return;
-  float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  uint4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   const uint32_t *trec32 = (const uint32_t *)trec;
   uint4 rec = rec_read(rec_load(trec32, w0, nt, lane), w0, nt);
   uint4 rn = rec_read(rec_load(trec32, w0 + nwaves, nt, lane), w0 + nwaves, nt);
@@ -1586,12 +1603,12 @@ __global__ void __launch_bounds__(kChunkBlocks) k_join_top(Ctl *ctl, ScanJobs jo
 // Subqueries 0..nk-1 against NCH chunks: each hit goes to its subquery's
 // next free result slot (woff, advanced in LDS when more objects follow).
 template <uint32_t NCH>
-__device__ __forceinline__ void write_rounds(const float4 *wrect, uint64_t *woff, uint32_t nk,
-                                             const float2 *p, const uint64_t *h,
+__device__ __forceinline__ void write_rounds(const uint4 *wrect, uint64_t *woff, uint32_t nk,
+                                             const uint2 *p, const uint64_t *h,
                                              const uint32_t *id, uint32_t *__restrict__ res_ids,
                                              bool more) {
   for (uint32_t kk = 0; kk < nk; ++kk) {
-    const float4 r = wrect[kk];
+    const uint4 r = wrect[kk];
     uint64_t base = woff[kk];
 #pragma unroll
     for (uint32_t c = 0; c < NCH; ++c) {
@@ -1606,14 +1623,14 @@ __device__ __forceinline__ void write_rounds(const float4 *wrect, uint64_t *woff
 // First block of a task: object loads and the gathers of the subqueries'
 // rectangles and result offsets go out together.
 template <uint32_t NCH>
-__device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint32_t nk,
+__device__ __forceinline__ void write_first(uint4 *wrect, uint64_t *woff, uint32_t nk,
                                             const float2 *__restrict__ sxy,
                                             const uint32_t *__restrict__ sid, uint32_t ob,
                                             uint32_t oe, const float4 *__restrict__ qrect,
                                             const uint64_t *__restrict__ res_off, uint32_t e,
                                             uint32_t sb, uint32_t lane,
                                             uint32_t *__restrict__ res_ids, bool more) {
-  float2 p[NCH];
+  uint2 p[NCH];
   uint64_t h[NCH];
   uint32_t id[NCH];
   load_chunks<NCH>(sxy, ob, oe, lane, p, h);
@@ -1621,7 +1638,7 @@ __device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint3
   if (lane < nk) {
     const float4 r = qrect[e];
     woff[lane] = res_off[sb + lane];
-    wrect[lane] = r;
+    wrect[lane] = rect_key(r);
   }
   wave_lds_fence();
   write_rounds<NCH>(wrect, woff, nk, p, h, id, res_ids, more);
@@ -1629,7 +1646,7 @@ __device__ __forceinline__ void write_first(float4 *wrect, uint64_t *woff, uint3
 
 // Decoding side of count_half: a round writes the hits of subquery kk
 // (low half) and kk + 1 (high half), each lane ranked within its half.
-__device__ __forceinline__ void write_half(float4 *wrect, uint64_t *woff, uint32_t nk,
+__device__ __forceinline__ void write_half(uint4 *wrect, uint64_t *woff, uint32_t nk,
                                            const float2 *__restrict__ sxy,
                                            const uint32_t *__restrict__ sid, uint32_t ob,
                                            uint32_t oe, const float4 *__restrict__ qrect,
@@ -1638,18 +1655,18 @@ __device__ __forceinline__ void write_half(float4 *wrect, uint64_t *woff, uint32
                                            uint32_t *__restrict__ res_ids) {
   const uint32_t half = lane >> 5, i = min(ob + (lane & 31u), oe - 1u);
   const uint64_t h = ballot(ob + (lane & 31u) < oe);
-  const float2 p = sxy[i];
+  const uint2 p = pos_key(sxy[i]);
   const uint32_t id = sid[i];
   if (lane < nk) {
     const float4 r = qrect[e];
     woff[lane] = res_off[sb + lane];
-    wrect[lane] = r;
+    wrect[lane] = rect_key(r);
   }
   wave_lds_fence();
   const uint64_t mine = half ? ~kLowHalf : kLowHalf;
   for (uint32_t kk = 0; kk < nk; kk += 2) {
     const uint32_t k = min(kk + half, nk - 1u);
-    const float4 rk = wrect[k];
+    const uint4 rk = wrect[k];
     const uint64_t base = woff[k];
     uint64_t m = hits(rk, p, h);
     if (kk + 1u >= nk) m &= kLowHalf;
@@ -1658,12 +1675,12 @@ __device__ __forceinline__ void write_half(float4 *wrect, uint64_t *woff, uint32
 }
 
 template <uint32_t NCH>
-__device__ __forceinline__ void write_block(const float4 *wrect, uint64_t *woff, uint32_t nk,
+__device__ __forceinline__ void write_block(const uint4 *wrect, uint64_t *woff, uint32_t nk,
                                             const float2 *__restrict__ sxy,
                                             const uint32_t *__restrict__ sid, uint32_t o0,
                                             uint32_t oe, uint32_t lane,
                                             uint32_t *__restrict__ res_ids, bool more) {
-  float2 p[NCH];
+  uint2 p[NCH];
   uint64_t h[NCH];
   uint32_t id[NCH];
   load_chunks<NCH>(sxy, o0, oe, lane, p, h);
@@ -1701,13 +1718,13 @@ __device__ __forceinline__ void stage_flush(uint32_t *stage, uint32_t &fill, uin
 }
 
 template <uint32_t NCH>
-__device__ __forceinline__ void stage_rounds(const float4 *wrect, uint32_t nk, const float2 *p,
+__device__ __forceinline__ void stage_rounds(const uint4 *wrect, uint32_t nk, const uint2 *p,
                                              const uint64_t *h, const uint32_t *id,
                                              uint32_t *stage, uint32_t &fill, uint64_t &gbase,
                                              uint32_t *__restrict__ res_ids, uint32_t lane) {
   for (uint32_t kk = 0; kk < nk; ++kk) {
     if (fill > kStage - (uint32_t)kWave * NCH) stage_flush(stage, fill, gbase, res_ids, lane, false);
-    const float4 r = wrect[kk];
+    const uint4 r = wrect[kk];
 #pragma unroll
     for (uint32_t c = 0; c < NCH; ++c) {
       const uint64_t m = hits(r, p[c], h[c]);
@@ -1720,20 +1737,20 @@ __device__ __forceinline__ void stage_rounds(const float4 *wrect, uint32_t nk, c
 // A one-block task: loads as write_first, ids staged from the task's first
 // result offset on.
 template <uint32_t NCH>
-__device__ __forceinline__ void write_staged(float4 *wrect, uint32_t nk,
+__device__ __forceinline__ void write_staged(uint4 *wrect, uint32_t nk,
                                              const float2 *__restrict__ sxy,
                                              const uint32_t *__restrict__ sid, uint32_t ob,
                                              uint32_t oe, const float4 *__restrict__ qrect,
                                              const uint64_t *__restrict__ res_off, uint32_t e,
                                              uint32_t sb, uint32_t lane, uint32_t *stage,
                                              uint32_t *__restrict__ res_ids) {
-  float2 p[NCH];
+  uint2 p[NCH];
   uint64_t h[NCH];
   uint32_t id[NCH];
   load_chunks<NCH>(sxy, ob, oe, lane, p, h);
   load_ids<NCH>(sid, ob, oe, lane, id);
   uint64_t gbase = res_off[sb];
-  if (lane < nk) wrect[lane] = qrect[e];
+  if (lane < nk) wrect[lane] = rect_key(qrect[e]);
   wave_lds_fence();
   uint32_t fill = 0;
   stage_rounds<NCH>(wrect, nk, p, h, id, stage, fill, gbase, res_ids, lane);
@@ -1742,7 +1759,7 @@ __device__ __forceinline__ void write_staged(float4 *wrect, uint32_t nk,
 
 // write_half with staging: a round stages subquery kk's hits (low half)
 // and then kk + 1's (high half).
-__device__ __forceinline__ void write_half_staged(float4 *wrect, uint32_t nk,
+__device__ __forceinline__ void write_half_staged(uint4 *wrect, uint32_t nk,
                                                   const float2 *__restrict__ sxy,
                                                   const uint32_t *__restrict__ sid, uint32_t ob,
                                                   uint32_t oe, const float4 *__restrict__ qrect,
@@ -1752,15 +1769,15 @@ __device__ __forceinline__ void write_half_staged(float4 *wrect, uint32_t nk,
                                                   uint32_t *__restrict__ res_ids) {
   const uint32_t half = lane >> 5, i = min(ob + (lane & 31u), oe - 1u);
   const uint64_t h = ballot(ob + (lane & 31u) < oe);
-  const float2 p = sxy[i];
+  const uint2 p = pos_key(sxy[i]);
   const uint32_t id = sid[i];
   uint64_t gbase = res_off[sb];
-  if (lane < nk) wrect[lane] = qrect[e];
+  if (lane < nk) wrect[lane] = rect_key(qrect[e]);
   wave_lds_fence();
   uint32_t fill = 0;
   for (uint32_t kk = 0; kk < nk; kk += 2) {
     if (fill > kStage - (uint32_t)kWave) stage_flush(stage, fill, gbase, res_ids, lane, false);
-    const float4 rk = wrect[min(kk + half, nk - 1u)];
+    const uint4 rk = wrect[min(kk + half, nk - 1u)];
     uint64_t m = hits(rk, p, h);
     if (kk + 1u >= nk) m &= kLowHalf;
     const uint32_t lo = (uint32_t)__popcll(m & kLowHalf);
@@ -1784,7 +1801,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
                                                        const uint64_t *__restrict__ res_off,
                                                        uint32_t *__restrict__ res_ids,
                                                        uint32_t nq, float *tlog) {
-  __shared__ float4 lrect[kBlock];
+  __shared__ uint4 lrect[kBlock];
   __shared__ uint64_t loff[kBlock];
   __shared__ uint32_t lstage[kWavesPerBlock * kStage];
   const bool go = ctl->go_join != 0;
@@ -1798,7 +1815,7 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
   const uint32_t nwaves = gridDim.x * kWavesPerBlock;
   const uint32_t w0 =
       __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
-  float4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  uint4 *wrect = lrect + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint64_t *woff = loff + (threadIdx.x & ~(uint32_t)(kWave - 1));
   uint32_t *stage = lstage + (threadIdx.x / kWave) * kStage;
   if (w0 >= nt) return;
