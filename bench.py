@@ -211,24 +211,38 @@ class Run:
         return self
 
     def tuning_ms(self, ticks, W):
-        """Extra time of a tick whose build tunes the threshold, against a
-        tick that builds without tuning (eager ticks, the best of two each):
-        the model is installed again so that the next build tunes."""
+        """Extra time of ticks whose build tunes the threshold, against ticks
+        that build without tuning (eager ticks on the same inputs): a tuning
+        in steady state (builds are forced until the scene's next tuning,
+        which tries the candidates near the current threshold), and the
+        scene's first tuning (every candidate; the model is installed again
+        so that the next build tunes)."""
         from paper_1411_3212_amd import costmodel
         torch, sc = self.torch, self.scene
         buf, m, q = ticks[W]
-        tuned, plain = [], []
-        for _ in range(2):
-            costmodel.install(sc, self.model, torch)
-            for out in (tuned, plain):
-                sc.build_index()
-                torch.cuda.synchronize()
-                h0 = time.perf_counter()
-                self.tick(None, buf, m, q, mode="eager")
-                sc.fetch()
-                out.append((time.perf_counter() - h0) * 1e3)
+
+        def build_tick():
+            sc.build_index()
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            self.tick(None, buf, m, q, mode="eager")
+            sc.fetch()
+            return (time.perf_counter() - h0) * 1e3
+
+        plain, steady = [], None
+        n0 = sc.tune_info()["n_tunes"]
+        for _ in range(24):
+            dt = build_tick()
+            if sc.tune_info()["n_tunes"] > n0:
+                steady = dt
+                break
+            plain.append(dt)
+        base = float(np.median(plain)) if plain else build_tick()
+        costmodel.install(sc, self.model, torch)
+        first = build_tick()
         info = sc.tune_info()
-        return max(0.0, min(tuned) - min(plain)), info
+        steady_ms = max(0.0, steady - base) if steady is not None else max(0.0, first - base)
+        return steady_ms, max(0.0, first - base), info
 
     def phase_sample(self, ticks, start, n):
         """Per-phase device times of n further eager ticks."""
@@ -448,7 +462,8 @@ def main():
         if head is None:
             head = run
             phases = run.phase_sample(ticks, W + K, n_extra)
-            tune_ms, tune_info = run.tuning_ms(ticks, W) if lrn else (0.0, None)
+            tune_ms, tune_first_ms, tune_info = run.tuning_ms(ticks, W) if lrn else \
+                (0.0, 0.0, None)
         runs[label] = run
         if run is not head:
             run.close()
@@ -508,6 +523,7 @@ def main():
     }
     if learned:
         out["tuning"] = {"tuned_tick_extra_ms": tune_ms, "amortised_ms_per_tick": amort,
+                         "first_tuning_extra_ms": tune_first_ms,
                          "ticks_between_tunings": period * tune_every,
                          "chosen": tune_info["chosen"],
                          "predicted_cost": dict(zip(map(str, tune_info["cand"]),

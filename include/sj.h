@@ -344,7 +344,8 @@ int sj_stats(sj_scene *scene, sj_tick_stats *out);
  * host decides when a call that synchronises, such as sj_fetch_results or
  * sj_stats, has read the scene's state after the previous tick), the first
  * such build and then every tune_every-th, first builds and splits at every
- * candidate threshold, predicts
+ * candidate threshold (on the first tuning; later tunings try the
+ * candidates within a factor of two of the current threshold), predicts
  *   cost = coef[0] * sum over active leaves c of exp(MLP(f_c))
  *        + coef[1] |Q_I| + coef[2] |Q_C| + coef[3] * leaves
  *        + coef[4] * max over active leaves c of exp(MLP(f'_c))
@@ -361,8 +362,9 @@ int sj_stats(sj_scene *scene, sj_tick_stats *out);
  * join task.
  * Results do not depend on it.
  * d_w: sj_mlp_param_count() BF16 parameters (device, copied); cand: n_cand
- * (1..8) thresholds, each >= th_min.  Synchronises the scene's stream.
- * Errors: SJ_EINVAL (null pointers, bad n_cand or a candidate below th_min). */
+ * (1..8) ascending thresholds, each >= th_min.  Synchronises the scene's
+ * stream.  Errors: SJ_EINVAL (null pointers, bad n_cand, candidates not
+ * ascending or below th_min). */
 #define SJ_COST_TERMS 6
 int sj_set_cost_model(sj_scene *scene, const uint16_t *d_w, const float coef[SJ_COST_TERMS],
                       const uint32_t *cand, uint32_t n_cand);

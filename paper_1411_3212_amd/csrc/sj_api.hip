@@ -23,6 +23,7 @@ struct GraphSlot {
   bool valid;
   bool split;            // exec2 is launched after exec, between the timing events
   uint32_t m, nq, key_bits;
+  uint32_t t_lo, t_hi;   // candidates a tuning tick tries
 };
 
 struct sj_scene {
@@ -51,7 +52,8 @@ struct sj_scene {
   Ctl host_ctl;
   Ctl *pin_ctl = nullptr;  // pinned landing buffer of its copies from the device
   bool cm_set;          // a cost model is installed (sj_set_cost_model)
-  uint32_t n_cand;      // its candidate thresholds
+  uint32_t n_cand;      // its candidate thresholds (ascending)
+  uint32_t cand[8];
   uint32_t tune_every;  // host-decided builds between two tunings
   uint32_t since_tune;  // host-decided builds since the last tuning
   bool tuned;           // a tuning has been enqueued
@@ -326,6 +328,25 @@ bool want_tune(const sj_scene *s, uint32_t decision) {
          (!s->tuned || s->since_tune + 1u >= s->tune_every);
 }
 
+// Candidates [lo, hi) a tuning build tries: all of them the first time;
+// afterwards those within a factor of two of the current threshold (the
+// best threshold moves with the distribution, which drifts between two
+// tunings; the small thresholds, whose trial splits cost the most, are
+// tried again only when the choice comes close to them).
+void tune_window(const sj_scene *s, uint32_t *lo, uint32_t *hi) {
+  *lo = 0;
+  *hi = s->n_cand;
+  if (!s->tuned) return;
+  const uint64_t th = s->host_ctl.th_cur;
+  uint32_t a = 0, b = s->n_cand;
+  while (a < s->n_cand && 2ull * s->cand[a] < th) ++a;
+  while (b > a && s->cand[b - 1] > 2ull * th) --b;
+  if (a < b) {
+    *lo = a;
+    *hi = b;
+  }
+}
+
 void count_build(sj_scene *s, uint32_t decision, bool tune) {
   if (decision != 1u) return;
   if (tune) {
@@ -365,8 +386,11 @@ void enqueue_tick(sj_scene *s, uint32_t nq, uint32_t decision, uint64_t upd_tota
   rec(0);
   sj::launch_index(s->B, decision, policy, upd_total, nq, key_bits(s, decision), st);
   rec(1);
-  if (tune)
-    sj::launch_tune(s->B, s->n_cand, s->l_max, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  if (tune) {
+    uint32_t lo, hi;
+    tune_window(s, &lo, &hi);
+    sj::launch_tune(s->B, lo, hi, s->l_max, nq, (flags & SJ_COVERING) ? 1u : 0u, st);
+  }
   if (decision != 0u && !(flags & SJ_UNIFORM_GRID)) sj::launch_build(s->B, s->l_max, st);
   rec(2);
   sj::launch_leaves(s->B, st);
@@ -649,7 +673,10 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
   const bool tune = want_tune(s, decision);
   GraphSlot &g = s->graphs[tune ? 3u : decision];
   const uint32_t kb = key_bits(s, decision);
-  if (!(g.valid && g.m == m && g.nq == nq && g.key_bits == kb)) {
+  uint32_t t_lo = 0, t_hi = 0;
+  if (tune) tune_window(s, &t_lo, &t_hi);
+  if (!(g.valid && g.m == m && g.nq == nq && g.key_bits == kb && g.t_lo == t_lo &&
+        g.t_hi == t_hi)) {
     if (g.valid) {
       (void)hipGraphExecDestroy(g.exec);
       if (g.split) (void)hipGraphExecDestroy(g.exec2);
@@ -735,6 +762,8 @@ int sj_tick_graph(sj_scene *s, const uint32_t *d_id, const float *d_x, const flo
     g.m = m;
     g.nq = nq;
     g.key_bits = kb;
+    g.t_lo = t_lo;
+    g.t_hi = t_hi;
   }
   // the graph reads this tick's arrays from the scene's input block
   const sj::TickIn in{d_id, d_x, d_y, d_qid, d_xa, d_ya, d_xb, d_yb};
@@ -925,9 +954,12 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[SJ_COST
   if (n_cand == 0 || n_cand > (uint32_t)sj::kMaxCand)
     return fail(s, SJ_EINVAL, "set_cost_model: n_cand must be in 1..8");
   const uint32_t th_min = s->cfg.th_min ? s->cfg.th_min : s->th;
-  for (uint32_t c = 0; c < n_cand; ++c)
+  for (uint32_t c = 0; c < n_cand; ++c) {
     if (cand[c] < th_min || cand[c] == 0)
       return fail(s, SJ_EINVAL, "set_cost_model: candidate below th_min");
+    if (c && cand[c] <= cand[c - 1])
+      return fail(s, SJ_EINVAL, "set_cost_model: candidates must be ascending");
+  }
   struct {
     float coef[SJ_COST_TERMS];
     uint32_t n_cand;
@@ -948,6 +980,7 @@ int sj_set_cost_model(sj_scene *s, const uint16_t *d_w, const float coef[SJ_COST
   if (e != hipSuccess) return hip_fail(s, e, "set_cost_model copy");
   s->cm_set = true;
   s->n_cand = n_cand;
+  for (uint32_t c = 0; c < n_cand; ++c) s->cand[c] = cand[c];
   s->tuned = false;
   s->since_tune = 0;
   for (GraphSlot &g : s->graphs) {  // captured with the previous model state

@@ -104,8 +104,9 @@ void launch_pairs_scatter(const Bufs &B, const uint64_t *off, uint32_t *cursor, 
 void launch_join_write(const Bufs &B, uint32_t nq, hipStream_t s);
 // Trial builds and splits at every candidate threshold, cost prediction,
 // and the choice of the threshold that the tick's build then uses.
-void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, uint32_t covering,
-                 hipStream_t s);
+// The candidates [c_lo, c_hi) are tried; the others keep an infinite cost.
+void launch_tune(const Bufs &B, uint32_t c_lo, uint32_t c_hi, uint32_t l_max, uint32_t nq,
+                 uint32_t covering, hipStream_t s);
 // Host handle of the join write kernel (to find its node in a captured graph).
 const void *join_write_kernel();
 void launch_ctl_out(const Bufs &B, Ctl *host, hipStream_t s);

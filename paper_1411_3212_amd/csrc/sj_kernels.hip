@@ -1114,28 +1114,22 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 // order): position p of the grouped subqueries holds slot s = sval[p];
 // sq[p] = the index of its query's rectangle (sg[s]), slot_sq[s] = p (sg
 // and slot_sq share memory: a slot is read, then written, by the one
-// thread of its position), and every leaf's first position (leaf_sqoff,
-// with the leaves in between empty ones included).
+// thread of its position).  Every leaf's first position (leaf_sqoff, empty
+// leaves included) is a binary search in the sorted keys, one thread per
+// leaf, so a run of empty leaves costs no thread a serial loop.
 __global__ void __launch_bounds__(kBlock) k_sq_final(const Ctl *ctl, const uint32_t *skey,
                                                      const uint32_t *sval, uint32_t *sq,
                                                      uint32_t *slot_sq, uint32_t *leaf_sqoff) {
   if (!ctl->go_split) return;
   const uint32_t n = ctl->n32[0], nl = ctl->n_leaves;
   const uint32_t stride = gridDim.x * kBlock, t0 = blockIdx.x * kBlock + threadIdx.x;
-  if (n == 0) {
-    for (uint32_t t = t0; t <= nl; t += stride) leaf_sqoff[t] = 0u;
-    return;
-  }
   for (uint32_t p = t0; p < n; p += stride) {
-    const uint32_t key = skey[p], s = sval[p];
-    const uint32_t lo = p ? skey[p - 1] + 1u : 0u;
+    const uint32_t s = sval[p];
     const uint32_t g = slot_sq[s];
     slot_sq[s] = p;
     sq[p] = g;
-    for (uint32_t t = lo; t <= key; ++t) leaf_sqoff[t] = p;
-    if (p == n - 1u)
-      for (uint32_t t = key + 1u; t <= nl; ++t) leaf_sqoff[t] = n;
   }
+  for (uint32_t t = t0; t <= nl; t += stride) leaf_sqoff[t] = lower_bound_u32(skey, 0u, n, t);
 }
 
 // -------------------------------------------------------------- schedule --

@@ -91,6 +91,34 @@ __device__ __forceinline__ uint64_t knn_key(float d2, uint32_t id) {
   return ((uint64_t)__float_as_uint(d2) << 32) | id;
 }
 
+// The same for 32-bit keys (the radius needs the k-th distance only).
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v, uint32_t lane) {
+#pragma unroll
+  for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
+#pragma unroll
+    for (uint32_t j = size >> 1; j > 0; j >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)v, (int)j, kWave);
+      const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
+      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  return v;
+}
+__device__ __forceinline__ uint32_t topk_add32(uint32_t best, uint32_t key, uint32_t k,
+                                               uint32_t lane) {
+  const uint32_t kth = (uint32_t)__shfl((int)best, (int)(k - 1u), kWave);
+  if (!ballot(key < kth)) return best;
+  const uint32_t b = wave_sort_u32(key, lane);
+  const uint32_t r = (uint32_t)__shfl((int)b, (int)((uint32_t)kWave - 1u - lane), kWave);
+  uint32_t c = r < best ? r : best;
+#pragma unroll
+  for (uint32_t j = (uint32_t)kWave >> 1; j > 0; j >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)c, (int)j, kWave);
+    c = (lane & j) == 0 ? (o < c ? o : c) : (o > c ? o : c);
+  }
+  return c;
+}
+
 // Adds a batch (one key per lane, kNoKey for none) to the wave's list when
 // one of its keys is below the k-th of the list.
 __device__ __forceinline__ uint64_t topk_add(uint64_t best, uint64_t key, uint32_t k,
@@ -160,14 +188,15 @@ __global__ void __launch_bounds__(kBlock) k_knn_radius(
         lq = l;
       }
       if (oe - ob >= k && oe - ob <= kKnnScanMax) {
-        // the k-th smallest distance to the quadrant's objects
-        uint64_t best = kNoKey;
+        // the k-th smallest distance to the quadrant's objects (binary32
+        // bits of d2 >= 0 order like the values)
+        uint32_t best = 0xffffffffu;
         for (uint32_t i0 = ob; i0 < oe; i0 += kWave) {
           const uint32_t i = i0 + lane;
-          const uint64_t key = i < oe ? knn_key(knn_d2(sxy[i], x, y), i) : kNoKey;
-          best = topk_add(best, key, k, lane);
+          const uint32_t key = i < oe ? __float_as_uint(knn_d2(sxy[i], x, y)) : 0xffffffffu;
+          best = topk_add32(best, key, k, lane);
         }
-        const float d2k = __uint_as_float((uint32_t)(shfl_u64(best, (int)(k - 1u)) >> 32));
+        const float d2k = __uint_as_float((uint32_t)__shfl((int)best, (int)(k - 1u), kWave));
         h = sqrt((double)d2k) * (1.0 + 1.0 / 1024.0);
       } else if (oe - ob >= k) {
         // a large quadrant: its farthest corner from the point

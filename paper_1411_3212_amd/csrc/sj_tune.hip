@@ -42,9 +42,14 @@ __device__ void reset_build(Ctl *ctl, const TuneState *ts, uint4 *front0, uint32
   front0[0] = make_uint4(0u, 0u, ctl->n_present, 0u);
 }
 
+// Candidates that this tuning does not try keep an infinite cost.
 __global__ void k_tune_begin(Ctl *ctl, TuneState *ts) {
   ts->err_saved = ctl->err;
   ts->th_before = ctl->th_cur;
+  for (int c = 0; c < kMaxCand; ++c) {
+    ts->cost[c] = INFINITY;
+    ts->msum[c] = ts->mmax[c] = 0.0f;
+  }
 }
 
 __global__ void k_tune_set(Ctl *ctl, const TuneState *ts, uint32_t c, uint4 *front0) {
@@ -276,10 +281,10 @@ void launch_schedule_mlp(const Bufs &B, hipStream_t s) {
          (const uint32_t *)B.xbase, B.TCAP, B.tkey, B.tkhist);
 }
 
-void launch_tune(const Bufs &B, uint32_t n_cand, uint32_t l_max, uint32_t nq, uint32_t covering,
-                 hipStream_t s) {
+void launch_tune(const Bufs &B, uint32_t c_lo, uint32_t c_hi, uint32_t l_max, uint32_t nq,
+                 uint32_t covering, hipStream_t s) {
   LAUNCH(k_tune_begin, 1, 1, s, B.ctl, B.tune);
-  for (uint32_t c = 0; c < n_cand; ++c) {
+  for (uint32_t c = c_lo; c < c_hi; ++c) {
     LAUNCH(k_tune_set, 1, 1, s, B.ctl, (const TuneState *)B.tune, c, B.front[0]);
     launch_build(B, l_max, s);
     launch_leaves(B, s);
