@@ -1340,6 +1340,24 @@ __device__ __forceinline__ uint32_t chunk_count(uint32_t o0, uint32_t oe) {
   return min(kJoinRegChunks, (oe - o0 + (uint32_t)kWave - 1u) / (uint32_t)kWave);
 }
 
+// Calls f with the chunk count n (1..kJoinRegChunks) as a constant, so a
+// block's rounds test exactly its chunks.
+template <uint32_t N> struct Chunks { static constexpr uint32_t value = N; };
+template <typename F>
+__device__ __forceinline__ auto by_chunks(uint32_t n, F f) {
+  switch (n) {
+    case 1: return f(Chunks<1>{});
+    case 2: return f(Chunks<2>{});
+    case 3: return f(Chunks<3>{});
+    case 4: return f(Chunks<4>{});
+    case 5: return f(Chunks<5>{});
+    case 6: return f(Chunks<6>{});
+    case 7: return f(Chunks<7>{});
+    default: return f(Chunks<8>{});
+  }
+}
+static_assert(kJoinRegChunks == 8, "by_chunks covers 1..8 chunks");
+
 // Task records are read one task ahead with lane l holding component
 // l & 3, so the load stays in flight until the components are read out.
 // The loads made ahead are issued on every path, at an in-range index, so
@@ -1507,20 +1525,17 @@ k_join_count(const Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uin
     uint32_t cnt = 0;
     wave_lds_fence();
     if (ob < oe) {
-      const uint32_t nch = chunk_count(ob, oe);
-      cnt = oe - ob <= 32u ? count_half(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
-            : nch <= 1u ? count_first<1>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
-            : nch <= 2u ? count_first<2>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
-            : nch <= 4u ? count_first<4>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r)
-                        : count_first<8>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r);
+      if (oe - ob <= 32u)
+        cnt = count_half(wrect, nk, sxy, ob, oe, qrect, e, lane, &r);
+      else
+        cnt = by_chunks(chunk_count(ob, oe), [&](auto N) {
+          return count_first<decltype(N)::value>(wrect, nk, sxy, ob, oe, qrect, e, lane, &r);
+        });
       for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
-           o0 += (uint32_t)kWave * kJoinRegChunks) {
-        const uint32_t nc2 = chunk_count(o0, oe);
-        cnt += nc2 <= 1u   ? count_block<1>(wrect, nk, sxy, o0, oe, lane)
-               : nc2 <= 2u ? count_block<2>(wrect, nk, sxy, o0, oe, lane)
-               : nc2 <= 4u ? count_block<4>(wrect, nk, sxy, o0, oe, lane)
-                           : count_block<8>(wrect, nk, sxy, o0, oe, lane);
-      }
+           o0 += (uint32_t)kWave * kJoinRegChunks)
+        cnt += by_chunks(chunk_count(o0, oe), [&](auto N) {
+          return count_block<decltype(N)::value>(wrect, nk, sxy, o0, oe, lane);
+        });
     } else if (tlog && lane < nk) {
       r = qrect[e];
     }
@@ -1835,31 +1850,22 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
     if (oe - ob <= 32u)
       write_half_staged(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage,
                         res_ids);
-    else if (nch <= 1u)
-      write_staged<1>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
-    else if (nch <= 2u)
-      write_staged<2>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
-    else if (nch <= 4u)
-      write_staged<4>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
     else if (!more)
-      write_staged<8>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, stage, res_ids);
+      by_chunks(nch, [&](auto N) {
+        write_staged<decltype(N)::value>(wrect, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane,
+                                         stage, res_ids);
+      });
     else
       write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
                      more);
     rn = rec_read(recv, t + 2u * nwaves, nt);
     for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
          o0 += (uint32_t)kWave * kJoinRegChunks) {
-      const uint32_t nc2 = chunk_count(o0, oe);
       const bool more2 = o0 + (uint32_t)kWave * kJoinRegChunks < oe;
       wave_lds_fence();
-      if (nc2 <= 1u)
-        write_block<1>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-      else if (nc2 <= 2u)
-        write_block<2>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-      else if (nc2 <= 4u)
-        write_block<4>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
-      else
-        write_block<8>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+      by_chunks(chunk_count(o0, oe), [&](auto N) {
+        write_block<decltype(N)::value>(wrect, woff, nk, sxy, sid, o0, oe, lane, res_ids, more2);
+      });
     }
     if (tlog && lane == 0)
       atomicAdd(&tlog[(uint64_t)leaf * 8 + 5], (float)(__builtin_amdgcn_s_memrealtime() - clk0));
