@@ -788,7 +788,7 @@ __device__ __forceinline__ bool query_box(const Ctl *ctl, uint32_t k, uint32_t o
 // intersecting (ri) or covering (rc) entries and its object count.
 // Inactive leaves are skipped.
 constexpr uint32_t kSplitGroup = 16;
-constexpr uint32_t kSplitBatch = 4;  // rounds of table cells whose loads go out together
+constexpr uint32_t kSplitBatch = 2;  // rounds of table cells whose loads go out together
 
 struct LeafCounts {
   uint32_t n, ni, nc;
@@ -1114,21 +1114,33 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 // order): position p of the grouped subqueries holds slot s = sval[p];
 // sq[p] = the index of its query's rectangle (sg[s]), slot_sq[s] = p (sg
 // and slot_sq share memory: a slot is read, then written, by the one
-// thread of its position).  Every leaf's first position (leaf_sqoff, empty
-// leaves included) is a binary search in the sorted keys, one thread per
-// leaf, so a run of empty leaves costs no thread a serial loop.
+// thread of its position).  The slots of neighbouring positions belong to
+// queries near the same leaves, so each XCD (work-groups go to the XCDs in
+// turn) takes one contiguous eighth of the positions and sweeps it with
+// all its work-groups together: the slots in flight then lie in a narrow
+// window that the XCD's L2 holds, and in lines that no other XCD writes.
+// Every leaf's first position (leaf_sqoff, empty leaves included) is a
+// binary search in the sorted keys, one thread per leaf, so a run of
+// empty leaves costs no thread a serial loop.
+constexpr uint32_t kXcds = 8;  // XCDs of the GPU, which take work-groups in turn
+
 __global__ void __launch_bounds__(kBlock) k_sq_final(const Ctl *ctl, const uint32_t *skey,
                                                      const uint32_t *sval, uint32_t *sq,
                                                      uint32_t *slot_sq, uint32_t *leaf_sqoff) {
   if (!ctl->go_split) return;
   const uint32_t n = ctl->n32[0], nl = ctl->n_leaves;
-  const uint32_t stride = gridDim.x * kBlock, t0 = blockIdx.x * kBlock + threadIdx.x;
-  for (uint32_t p = t0; p < n; p += stride) {
+  const uint32_t per_x = gridDim.x / kXcds;  // the grid is a multiple of kXcds
+  const uint32_t x = blockIdx.x % kXcds, bx = blockIdx.x / kXcds;
+  const uint32_t span = (n + kXcds - 1u) / kXcds;
+  const uint32_t x1 = (uint32_t)min((uint64_t)(x + 1u) * span, (uint64_t)n);
+  for (uint64_t p = (uint64_t)x * span + bx * kBlock + threadIdx.x; p < x1;
+       p += (uint64_t)per_x * kBlock) {
     const uint32_t s = sval[p];
     const uint32_t g = slot_sq[s];
-    slot_sq[s] = p;
+    slot_sq[s] = (uint32_t)p;
     sq[p] = g;
   }
+  const uint32_t stride = gridDim.x * kBlock, t0 = blockIdx.x * kBlock + threadIdx.x;
   for (uint32_t t = t0; t <= nl; t += stride) leaf_sqoff[t] = lower_bound_u32(skey, 0u, n, t);
 }
 
@@ -2061,7 +2073,8 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
          B.cov_leaf, covering, qord);
   radix_sort_pairs(skey, sval, k1, v1, &B.ctl->n32[0], B.S, &B.ctl->go_split, B.hist, B.tot, 0,
                    32, s, nullptr, nullptr, &B.ctl->sq_skip);
-  LAUNCH(k_sq_final, grid_for(B.S, 4096), kBlock, s, (const Ctl *)B.ctl, (const uint32_t *)skey,
+  LAUNCH(k_sq_final, (grid_for(B.S, 4096) + kXcds - 1u) / kXcds * kXcds, kBlock, s,
+         (const Ctl *)B.ctl, (const uint32_t *)skey,
          (const uint32_t *)sval, B.sq, B.slot_sq, B.leaf_sqoff);
   return qord;
 }
