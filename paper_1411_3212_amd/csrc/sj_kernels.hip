@@ -1338,7 +1338,7 @@ __device__ __forceinline__ uint4 rect_key(float4 r) {
   return make_uint4(xa, ckey(r.z) - xa, ya, ckey(r.w) - ya);
 }
 
-constexpr uint32_t kJoinRegChunks = 8;  // object chunks of 64 in registers
+constexpr uint32_t kJoinRegChunks = 12;  // object chunks of 64 in registers
 static_assert(kTaskSub <= (uint32_t)kWave, "a task's subqueries fit one wave");
 
 // Orders a wave's LDS stores before its later loads of other lanes' slots
@@ -1365,10 +1365,14 @@ __device__ __forceinline__ auto by_chunks(uint32_t n, F f) {
     case 5: return f(Chunks<5>{});
     case 6: return f(Chunks<6>{});
     case 7: return f(Chunks<7>{});
-    default: return f(Chunks<8>{});
+    case 8: return f(Chunks<8>{});
+    case 9: return f(Chunks<9>{});
+    case 10: return f(Chunks<10>{});
+    case 11: return f(Chunks<11>{});
+    default: return f(Chunks<12>{});
   }
 }
-static_assert(kJoinRegChunks == 8, "by_chunks covers 1..8 chunks");
+static_assert(kJoinRegChunks == 12, "by_chunks covers 1..12 chunks");
 
 // Task records are read one task ahead with lane l holding component
 // l & 3, so the load stays in flight until the components are read out.
@@ -1868,8 +1872,8 @@ __global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *tr
                                          stage, res_ids);
       });
     else
-      write_first<8>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane, res_ids,
-                     more);
+      write_first<kJoinRegChunks>(wrect, woff, nk, sxy, sid, ob, oe, qrect, res_off, e, sb, lane,
+                                  res_ids, more);
     rn = rec_read(recv, t + 2u * nwaves, nt);
     for (uint32_t o0 = ob + (uint32_t)kWave * kJoinRegChunks; o0 < oe;
          o0 += (uint32_t)kWave * kJoinRegChunks) {
