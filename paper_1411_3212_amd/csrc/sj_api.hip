@@ -186,6 +186,7 @@ size_t carve(const Derived &d, uint8_t *base, Bufs *B) {
   b.keyB = c.take<uint32_t>(N);
   b.valB = c.take<uint32_t>(N);
   b.sxy = c.take<float2>(N);
+  b.sxy2 = c.take<float2>(N);
   b.blk = c.take<uint32_t>(sj::kChunkBlocks);
   b.red = c.take<uint64_t>((uint64_t)sj::kRedSlots * sj::kChunkBlocks);
   b.part = c.take<uint64_t>((uint64_t)sj::kMaxScanJobs * sj::kChunkBlocks);

@@ -247,6 +247,27 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, uint32_t want
   return base + inc - want;
 }
 
+// Work-groups go to the GPU's XCDs in turn, and each XCD has its own L2.
+// A sweep gives XCD x the x-th contiguous eighth of n items and walks it
+// with all of that XCD's work-groups together (unit u of `per_block` units
+// in a block takes items first, first + stride, ... below end), so items
+// processed at the same time are neighbours held by one L2.  The grid must
+// be a multiple of kXcds.
+constexpr uint32_t kXcds = 8;
+
+struct Sweep {
+  uint32_t first, end, stride;
+};
+
+__device__ __forceinline__ Sweep xcd_sweep(uint32_t n, uint32_t per_block, uint32_t u) {
+  const uint32_t x = blockIdx.x % kXcds, bx = blockIdx.x / kXcds, per_x = gridDim.x / kXcds;
+  const uint32_t span = (n + kXcds - 1u) / kXcds;
+  const uint64_t lo = (uint64_t)x * span;
+  const uint32_t end = (uint32_t)min(lo + span, (uint64_t)n);
+  const uint64_t first = lo + (uint64_t)bx * per_block + u;
+  return Sweep{(uint32_t)min(first, (uint64_t)end), end, per_x * per_block};
+}
+
 __device__ __forceinline__ void flag_error(Ctl *ctl, uint32_t bits, bool cond) {
   uint64_t m = ballot(cond);
   if (m && lane_id() == (uint32_t)(__ffsll((unsigned long long)m) - 1)) atomicOr(&ctl->err, bits);

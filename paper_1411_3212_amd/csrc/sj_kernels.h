@@ -22,6 +22,7 @@ struct Bufs {
   uint64_t *ustamp, *qstamp;
   uint32_t *keyA, *valA, *keyB, *valB;  // sorted (code, id) end in A
   float2 *sxy;                          // positions in sorted order
+  float2 *sxy2;                         // the sort's other buffer of positions
   uint32_t *blk;                        // per-block present counts/offsets
   uint64_t *red;                        // per-block partials (kRedSlots)
   uint64_t *part;                       // scan partials (kMaxScanJobs)

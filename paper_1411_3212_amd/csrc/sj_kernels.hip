@@ -302,16 +302,18 @@ __global__ void __launch_bounds__(kChunkBlocks) k_decide(Ctl *ctl, uint32_t *blk
   }
 }
 
-// Sort keys of present objects, compacted in id order: their Morton codes
-// when the tick builds the quadtree, else the index of the leaf holding
-// them (the leaves are in Morton order, so grouping by leaf is what the
-// join needs, and leaf indices take fewer radix digits than codes).  Then
+// Sort keys of present objects, compacted in id order with their ids and
+// positions (which the sort carries along): their Morton codes when the
+// tick builds the quadtree, else the index of the leaf holding them (the
+// leaves are in Morton order, so grouping by leaf is what the join needs,
+// and leaf indices take fewer radix digits than codes).  Then
 // the sequence stamps of the tick's queries (the latest query of an object
 // is the one answered).
 __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N, Tree tr,
                                                    Ctl *ctl, const uint32_t *blk, uint32_t *keys,
-                                                   uint32_t *vals, const TickIn *tin,
-                                                   uint32_t nq, uint64_t *qstamp) {
+                                                   uint32_t *vals, float2 *cpos,
+                                                   const TickIn *tin, uint32_t nq,
+                                                   uint64_t *qstamp) {
   // A tile is kMortonRows rows of kBlock ids: every row's loads and table
   // lookups are issued before the first is waited for, and one block scan
   // ranks all rows (one 16-bit field per row).
@@ -357,6 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_morton(const float2 *pos, uint32_t N
         const uint32_t r = base + (uint32_t)((ex >> (16u * j)) & 0xffffu);
         keys[r] = key[j];
         vals[r] = (uint32_t)(t0 + j * kBlock + threadIdx.x);
+        cpos[r] = p[j];
       }
       base += (uint32_t)((tot >> (16u * j)) & 0xffffu);
     }
@@ -1066,8 +1069,9 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     tr.tlev = ctl->tlev;
     const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
     const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
-    const uint32_t ngroups = gridDim.x * (kBlock / kSplitGroup);
-    for (uint32_t g = (blockIdx.x * kBlock + threadIdx.x) / kSplitGroup; g < nq; g += ngroups) {
+    // one XCD's queries write neighbouring slots (grid: kChunkBlocks)
+    const Sweep sw = xcd_sweep(nq, kBlock / kSplitGroup, threadIdx.x / kSplitGroup);
+    for (uint32_t g = sw.first; g < sw.end; g += sw.stride) {
       const uint32_t n = q_ni[g] + q_nc[g];
       if (n == 0) continue;
       const uint32_t wi = q_ioff[g], wc = q_coff[g];
@@ -1122,22 +1126,16 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
 // Every leaf's first position (leaf_sqoff, empty leaves included) is a
 // binary search in the sorted keys, one thread per leaf, so a run of
 // empty leaves costs no thread a serial loop.
-constexpr uint32_t kXcds = 8;  // XCDs of the GPU, which take work-groups in turn
-
 __global__ void __launch_bounds__(kBlock) k_sq_final(const Ctl *ctl, const uint32_t *skey,
                                                      const uint32_t *sval, uint32_t *sq,
                                                      uint32_t *slot_sq, uint32_t *leaf_sqoff) {
   if (!ctl->go_split) return;
   const uint32_t n = ctl->n32[0], nl = ctl->n_leaves;
-  const uint32_t per_x = gridDim.x / kXcds;  // the grid is a multiple of kXcds
-  const uint32_t x = blockIdx.x % kXcds, bx = blockIdx.x / kXcds;
-  const uint32_t span = (n + kXcds - 1u) / kXcds;
-  const uint32_t x1 = (uint32_t)min((uint64_t)(x + 1u) * span, (uint64_t)n);
-  for (uint64_t p = (uint64_t)x * span + bx * kBlock + threadIdx.x; p < x1;
-       p += (uint64_t)per_x * kBlock) {
+  const Sweep sw = xcd_sweep(n, kBlock, threadIdx.x);  // the grid is a multiple of kXcds
+  for (uint32_t p = sw.first; p < sw.end; p += sw.stride) {
     const uint32_t s = sval[p];
     const uint32_t g = slot_sq[s];
-    slot_sq[s] = (uint32_t)p;
+    slot_sq[s] = p;
     sq[p] = g;
   }
   const uint32_t stride = gridDim.x * kBlock, t0 = blockIdx.x * kBlock + threadIdx.x;
@@ -2001,19 +1999,19 @@ void launch_index(const Bufs &B, uint32_t decision, uint32_t policy, uint64_t up
     const bool odd = passes & 1;
     LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
            (const uint32_t *)B.blk, odd ? B.keyB : B.keyA, odd ? B.valB : B.valA,
-           (const TickIn *)B.tin, nq, B.qstamp);
+           odd ? B.sxy2 : B.sxy, (const TickIn *)B.tin, nq, B.qstamp);
     if (odd)
       radix_sort_pairs(B.keyB, B.valB, B.keyA, B.valA, &B.ctl->n_present, B.N, nullptr, B.hist,
-                       B.tot, 0, 8 * passes, s, B.pos, B.sxy);
+                       B.tot, 0, 8 * passes, s, B.sxy2, B.sxy);
     else
       radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, B.N, nullptr, B.hist,
-                       B.tot, 0, 8 * passes, s, B.pos, B.sxy);
+                       B.tot, 0, 8 * passes, s, B.sxy, B.sxy2);
     return;
   }
   LAUNCH(k_morton, kChunkBlocks, kBlock, s, (const float2 *)B.pos, B.N, tree_of(B), B.ctl,
-         (const uint32_t *)B.blk, B.keyA, B.valA, (const TickIn *)B.tin, nq, B.qstamp);
+         (const uint32_t *)B.blk, B.keyA, B.valA, B.sxy, (const TickIn *)B.tin, nq, B.qstamp);
   radix_sort_pairs(B.keyA, B.valA, B.keyB, B.valB, &B.ctl->n_present, B.N, nullptr, B.hist,
-                   B.tot, 0, 32, s, B.pos, B.sxy, &B.ctl->sort_skip);
+                   B.tot, 0, 32, s, B.sxy, B.sxy2, &B.ctl->sort_skip);
 }
 
 void launch_build(const Bufs &B, uint32_t l_max, hipStream_t s) {
@@ -2070,6 +2068,7 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
   // indices in slot_sq; the sort by leaf ping-pongs through res_off's
   // memory and ends where it started
   uint32_t *skey = B.sq_cnt, *sval = B.sq, *k1 = (uint32_t *)B.res_off, *v1 = k1 + B.S;
+  static_assert(kChunkBlocks % kXcds == 0, "k_q_write sweeps per XCD");
   LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,

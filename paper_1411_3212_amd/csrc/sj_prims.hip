@@ -8,6 +8,8 @@
 #include "sj_device.h"
 #include "sj_host.h"
 
+#include <utility>
+
 namespace sj {
 
 __device__ __forceinline__ bool gated(const uint32_t *gate) { return gate && *gate == 0u; }
@@ -15,19 +17,13 @@ __device__ __forceinline__ bool gated(const uint32_t *gate) { return gate && *ga
 // Role of a radix pass when the keys fit in *skip bits (a multiple of 8,
 // at least 8): the passes below sort; the passes above have a zero digit
 // for every key and are identities.  Identities run in pairs as nothing (the
-// data returns to the same buffer), and one left over runs as a copy.  The
-// positions are gathered by the last pass that writes.
+// data returns to the same buffer), and one left over runs as a copy.
 enum : int { kPassSort = 0, kPassCopy = 1, kPassNone = 2 };
 __device__ __forceinline__ int pass_role(const uint32_t *skip, int shift) {
   if (!skip) return kPassSort;
   const uint32_t np = *skip / 8u, p = (uint32_t)shift / 8u;
   if (p < np) return kPassSort;
   return (p == np && (np & 1u)) ? kPassCopy : kPassNone;
-}
-__device__ __forceinline__ bool gather_pass(const uint32_t *skip, int shift, int last_shift) {
-  if (!skip) return shift == last_shift;
-  const uint32_t np = *skip / 8u;
-  return (uint32_t)shift / 8u == ((np & 1u) ? np : np - 1u);
 }
 
 // ---------------------------------------------------------------- scans --
@@ -149,8 +145,9 @@ ScanJob job_u64(const uint32_t *in, uint64_t *out, const uint32_t *n_dev, uint32
 //  scatter: every block ranks its keys tile by tile (wave ballots give the
 //           rank among equal digits of a wave), places the tile in LDS in
 //           digit order and writes each digit's run contiguously to its
-//           global offset.  The last pass can also gather the positions of
-//           the sorted values (sorted SoA of the objects).
+//           global offset.  A float2 per pair can travel with it (the
+//           objects' positions: sorted with their ids, they need no gather
+//           by id, which would read one random line per object).
 // Passes above the device value *skip only copy or do nothing (pass_role).
 
 __global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t *keys, const uint32_t *n_dev,
@@ -193,25 +190,27 @@ __global__ void __launch_bounds__(kChunkBlocks) k_rs_hscan(uint32_t *hist, const
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
-template <bool GATHER>
+template <bool CARRY>
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restrict__ kin,
                                                        const uint32_t *__restrict__ vin,
                                                        uint32_t *__restrict__ kout,
                                                        uint32_t *__restrict__ vout,
                                                        const uint32_t *n_dev, const uint32_t *gate,
                                                        const uint32_t *skip, int shift,
-                                                       int last_shift, const uint32_t *hist,
-                                                       const uint32_t *tot,
-                                                       const float2 *__restrict__ gpos,
-                                                       float2 *__restrict__ gout) {
+                                                       const uint32_t *hist, const uint32_t *tot,
+                                                       const float2 *__restrict__ cin,
+                                                       float2 *__restrict__ cout) {
   if (gated(gate)) return;
   const int role = pass_role(skip, shift);
   if (role == kPassNone) return;
-  const bool gather = GATHER && gather_pass(skip, shift, last_shift);
   // per (row, wave, digit) counts, then their running offsets (at most a
-  // tile, 2,048): 16 bits each, so that four blocks fit a CU's LDS
-  __shared__ uint16_t cnt[kSortItems * kWavesPerBlock * 256];
+  // tile, 2,048): 16 bits each, so that four blocks fit a CU's LDS; once
+  // the tile's places are known the same memory stages the carried float2s
+  constexpr int kCnt = kSortItems * kWavesPerBlock * 256;
   static_assert(kSortTile <= 65535, "tile offsets fit 16 bits");
+  static_assert(kCnt * sizeof(uint16_t) >= kSortTile * sizeof(float2), "carry fits the counts");
+  __shared__ __align__(16) uint16_t cnt[kCnt];
+  float2 *sc = reinterpret_cast<float2 *>(cnt);
   __shared__ uint32_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
   __shared__ uint32_t goff[256], tbase[256], tcnt[256];
@@ -224,10 +223,9 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   if (b0 >= b1) return;  // uniform per block: no barrier is skipped by part of it
   if (role == kPassCopy) {
     for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
-      const uint32_t v = vin[i];
       kout[i] = kin[i];
-      vout[i] = v;
-      if (gather) gout[i] = gpos[v];
+      vout[i] = vin[i];
+      if (CARRY) cout[i] = cin[i];
     }
     return;
   }
@@ -240,15 +238,17 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   __syncthreads();
   for (uint64_t t0 = b0; t0 < b1; t0 += kSortTile) {
     const uint32_t tile_n = (uint32_t)((b1 - t0) < (uint64_t)kSortTile ? (b1 - t0) : kSortTile);
-    for (int i = tid; i < kSortItems * kWavesPerBlock * 256; i += kBlock) cnt[i] = 0;
+    for (int i = tid; i < kCnt; i += kBlock) cnt[i] = 0;
     __syncthreads();
     uint32_t key[kSortItems], val[kSortItems], dig[kSortItems], rank[kSortItems];
+    float2 car[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       const uint32_t li = r * kBlock + tid;
       const bool valid = li < tile_n;
       key[r] = valid ? kin[t0 + li] : 0u;
       val[r] = valid ? vin[t0 + li] : 0u;
+      if (CARRY) car[r] = valid ? cin[t0 + li] : make_float2(0.f, 0.f);
       dig[r] = (key[r] >> shift) & 255u;
       uint64_t m = ballot(valid);
 #pragma unroll
@@ -277,39 +277,38 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       tcnt[tid] = run;
     }
     __syncthreads();
+    uint32_t pos[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+      pos[r] = tbase[dig[r]] + cnt[(r * kWavesPerBlock + w) * 256 + dig[r]] + rank[r];
+    if (CARRY) __syncthreads();  // every count is read before the carry overwrites them
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-      const uint32_t li = r * kBlock + tid;
-      if (li < tile_n) {
-        const uint32_t pos = tbase[dig[r]] + cnt[(r * kWavesPerBlock + w) * 256 + dig[r]] + rank[r];
-        sk[pos] = key[r];
-        sv[pos] = val[r];
+      if (r * kBlock + tid < tile_n) {
+        sk[pos[r]] = key[r];
+        sv[pos[r]] = val[r];
+        if (CARRY) sc[pos[r]] = car[r];
       }
     }
     __syncthreads();
-    // every item's destination first, then all position gathers (issued
-    // together, at a valid id for items past the tile), then the stores
+    // every item's destination first, then the stores
     uint32_t gdst[kSortItems];
-    float2 gp[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       const uint32_t i = r * kBlock + tid;
       const bool valid = i < tile_n;
       key[r] = valid ? sk[i] : 0u;
       val[r] = valid ? sv[i] : 0u;
+      if (CARRY) car[r] = valid ? sc[i] : make_float2(0.f, 0.f);
       const uint32_t d = (key[r] >> shift) & 255u;
       gdst[r] = valid ? goff[d] + (i - tbase[d]) : 0u;
-    }
-    if (gather) {
-#pragma unroll
-      for (int r = 0; r < kSortItems; ++r) gp[r] = gpos[val[r]];
     }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       if (r * kBlock + tid < tile_n) {
         kout[gdst[r]] = key[r];
         vout[gdst[r]] = val[r];
-        if (gather) gout[gdst[r]] = gp[r];
+        if (CARRY) cout[gdst[r]] = car[r];
       }
     }
     __syncthreads();
@@ -321,36 +320,31 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, uint64_t n_cap, const uint32_t *gate,
                       uint32_t *hist, uint32_t *tot, int bit_begin, int bit_end, hipStream_t s,
-                      const float2 *gpos, float2 *gout, const uint32_t *skip) {
+                      float2 *c0, float2 *c1, const uint32_t *skip) {
   // about one tile per block when the count reaches its bound
   uint64_t g = (n_cap + kSortTile - 1) / kSortTile;
   const unsigned nblk = (unsigned)(g < 1 ? 1 : (g > kChunkBlocks ? kChunkBlocks : g));
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  float2 *ci = c0, *co = c1;
   bool in_alt = false;
-  const int last_shift = bit_end - 8;
   for (int shift = bit_begin; shift < bit_end; shift += 8) {
-    // with a device key width any pass may be the one that gathers
-    const bool may_gather = gout && (skip || shift == last_shift);
     hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, s, (const uint32_t *)ki,
                        n_dev, gate, skip, shift, hist);
     hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, skip, shift,
                        tot, nblk);
-    if (may_gather)
+    if (ci)
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nblk), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot, gpos,
-                         gout);
+                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
+                         (const float2 *)ci, co);
     else
       hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nblk), dim3(kBlock), 0, s,
                          (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, last_shift, (const uint32_t *)hist, (const uint32_t *)tot,
+                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
                          (const float2 *)nullptr, (float2 *)nullptr);
-    uint32_t *t = ki;
-    ki = ko;
-    ko = t;
-    t = vi;
-    vi = vo;
-    vo = t;
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+    std::swap(ci, co);
     in_alt = !in_alt;
   }
   // with a key width the writing passes are even in number: back in k0
