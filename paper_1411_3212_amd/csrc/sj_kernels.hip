@@ -1396,17 +1396,18 @@ __device__ __forceinline__ uint32_t sq_entry(const uint32_t *__restrict__ sq, co
   return sq[rec.x < rec.y ? min(rec.x + lane, rec.y - 1u) : 0u];
 }
 
-// Chunk c of a block at o0: lane l holds object o0 + 64 c + l when it is
-// below oe (mask h[c]); the other lanes hold a copy of the last object,
-// which the mask excludes.
+// Chunk c of a block at o0 with exactly NCH chunks: lane l holds object
+// o0 + 64 c + l when it is below oe (mask h[c]); the other lanes hold a copy
+// of the last object, which the mask excludes.  Every chunk but the last
+// is full, so its mask is a constant the tests fold away.
 template <uint32_t NCH>
 __device__ __forceinline__ void load_chunks(const float2 *__restrict__ sxy, uint32_t o0,
                                             uint32_t oe, uint32_t lane, uint2 *p, uint64_t *h) {
 #pragma unroll
   for (uint32_t c = 0; c < NCH; ++c) {
     const uint32_t i = o0 + c * (uint32_t)kWave + lane;
-    h[c] = ballot(i < oe);
-    p[c] = pos_key(sxy[min(i, oe - 1u)]);
+    h[c] = c + 1u < NCH ? ~0ull : ballot(i < oe);
+    p[c] = pos_key(sxy[c + 1u < NCH ? i : min(i, oe - 1u)]);
   }
 }
 
@@ -1414,7 +1415,10 @@ template <uint32_t NCH>
 __device__ __forceinline__ void load_ids(const uint32_t *__restrict__ sid, uint32_t o0,
                                          uint32_t oe, uint32_t lane, uint32_t *id) {
 #pragma unroll
-  for (uint32_t c = 0; c < NCH; ++c) id[c] = sid[min(o0 + c * (uint32_t)kWave + lane, oe - 1u)];
+  for (uint32_t c = 0; c < NCH; ++c) {
+    const uint32_t i = o0 + c * (uint32_t)kWave + lane;
+    id[c] = sid[c + 1u < NCH ? i : min(i, oe - 1u)];
+  }
 }
 
 // Lanes whose object lies in the closed rectangle r: one ballot per bound,
