@@ -163,10 +163,11 @@ __device__ __forceinline__ uint32_t compact16(uint32_t x) {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Number of set bits of m below the calling lane.
-__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+// Number of set bits of m below the calling lane, plus acc (the count
+// instructions add it for free).
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m, uint32_t acc = 0u) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }

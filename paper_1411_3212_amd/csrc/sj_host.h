@@ -30,13 +30,14 @@ void mscan_down(const ScanJobs &jobs, int njobs, const uint64_t *part, const uin
 // are set, a float2 per pair travels with it, between c0 and c1 like the
 // values.  skip (device, optional; then bit_end - bit_begin = 32): the keys
 // fit in *skip bits, the passes above have nothing to sort and the result
-// is in (k0, v0).  hist: 256 * kChunkBlocks u32, tot: 256 u32.  Skipped
-// when *gate == 0.
+// is in (k0, v0).  iota: the values are the pairs' input positions (v0 is
+// not read, only written).  hist: 256 * kChunkBlocks u32, tot: 256 u32.
+// Skipped when *gate == 0.
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, uint64_t n_cap, const uint32_t *gate,
                       uint32_t *hist, uint32_t *tot, int bit_begin, int bit_end, hipStream_t s,
                       float2 *c0 = nullptr, float2 *c1 = nullptr,
-                      const uint32_t *skip = nullptr);
+                      const uint32_t *skip = nullptr, bool iota = false);
 
 inline unsigned grid_for(uint64_t n, unsigned cap = 2048) {
   uint64_t g = (n + 255) / 256;

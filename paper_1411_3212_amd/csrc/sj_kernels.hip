@@ -1048,18 +1048,18 @@ __global__ void __launch_bounds__(kChunkBlocks) k_split_top(Ctl *ctl, ScanJobs j
 }
 
 // Write pass, one query per group, in processing order: every intersecting
-// subquery's leaf at its slot (skey[slot]; sval[slot] = slot, the value the
-// sort by leaf carries; sg[slot] = g, the index of its query's rectangle),
-// covering leaves per query.  A query whose list fit reads it back,
-// kSplitGroup entries at a time; a longer one enumerates its leaves again
-// in the same order.  A stable sort by leaf then groups the subqueries
+// subquery's leaf at its slot (skey[slot]; the sort by leaf carries the
+// slot itself as the value, made by its first pass; sg[slot] = g, the
+// index of its query's rectangle), covering leaves per query.  A query
+// whose list fit reads it back, kSplitGroup entries at a time; a longer
+// one enumerates its leaves again in the same order.  A stable sort by leaf then groups the subqueries
 // (k_sq_final), in slot order inside a leaf, so the grouping and the
 // results' layout are the same on every run.
 __global__ void __launch_bounds__(kBlock) k_q_write(
     Ctl *ctl, const TickIn *tin, uint32_t nq, uint32_t N, const uint64_t *qstamp, Tree tr,
     const uint32_t *leaf_beg, const float4 *qrect, const uint32_t *q_ioff, const uint32_t *q_coff,
     const uint32_t *q_ni, const uint32_t *q_nc, const uint32_t *qlist, uint32_t slots,
-    uint32_t *skey, uint32_t *sval, uint32_t *sg, uint32_t *cov_leaf, uint32_t covering,
+    uint32_t *skey, uint32_t *sg, uint32_t *cov_leaf, uint32_t covering,
     const uint32_t *qord) {
   __shared__ uint32_t stack[kFine * kBlock];
   if (ctl->go_split) {
@@ -1080,7 +1080,6 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
           cov_leaf[wc + rc] = leaf;
         } else {
           skey[wi + ri] = leaf;
-          sval[wi + ri] = wi + ri;
           sg[wi + ri] = g;
         }
       };
@@ -1755,7 +1754,7 @@ __device__ __forceinline__ void stage_rounds(const uint4 *wrect, uint32_t nk, co
 #pragma unroll
     for (uint32_t c = 0; c < NCH; ++c) {
       const uint64_t m = hits(r, p[c], h[c]);
-      if (__builtin_amdgcn_inverse_ballot_w64(m)) stage[fill + mbcnt(m)] = id[c];
+      if (__builtin_amdgcn_inverse_ballot_w64(m)) stage[mbcnt(m, fill)] = id[c];
       fill += (uint32_t)__popcll(m);
     }
   }
@@ -2068,18 +2067,18 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
   mscan_reduce(jobs, 2, B.part, nullptr, s);
   LAUNCH(k_split_top, 1, kChunkBlocks, s, B.ctl, jobs, B.part, B.S, B.C);
   mscan_down(jobs, 2, (const uint64_t *)B.part, nullptr, s);
-  // subqueries in slot order: leaf keys in sq_cnt, slots in sq, rectangle
-  // indices in slot_sq; the sort by leaf ping-pongs through res_off's
-  // memory and ends where it started
+  // subqueries in slot order: leaf keys in sq_cnt, rectangle indices in
+  // slot_sq; the sort by leaf makes the slots as its values, ping-pongs
+  // through res_off's memory and ends where it started (values in sq)
   uint32_t *skey = B.sq_cnt, *sval = B.sq, *k1 = (uint32_t *)B.res_off, *v1 = k1 + B.S;
   static_assert(kChunkBlocks % kXcds == 0, "k_q_write sweeps per XCD");
   LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
-         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots, skey, sval, B.slot_sq,
+         (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots, skey, B.slot_sq,
          B.cov_leaf, covering, qord);
   radix_sort_pairs(skey, sval, k1, v1, &B.ctl->n32[0], B.S, &B.ctl->go_split, B.hist, B.tot, 0,
-                   32, s, nullptr, nullptr, &B.ctl->sq_skip);
+                   32, s, nullptr, nullptr, &B.ctl->sq_skip, true);
   LAUNCH(k_sq_final, (grid_for(B.S, 4096) + kXcds - 1u) / kXcds * kXcds, kBlock, s,
          (const Ctl *)B.ctl, (const uint32_t *)skey,
          (const uint32_t *)sval, B.sq, B.slot_sq, B.leaf_sqoff);

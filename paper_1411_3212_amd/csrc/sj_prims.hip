@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
   if (role == kPassCopy) {
     for (uint64_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
       kout[i] = kin[i];
-      vout[i] = vin[i];
+      vout[i] = vin ? vin[i] : (uint32_t)i;
       if (CARRY) cout[i] = cin[i];
     }
     return;
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
       const uint32_t li = r * kBlock + tid;
       const bool valid = li < tile_n;
       key[r] = valid ? kin[t0 + li] : 0u;
-      val[r] = valid ? vin[t0 + li] : 0u;
+      val[r] = !valid ? 0u : vin ? vin[t0 + li] : (uint32_t)(t0 + li);
       if (CARRY) car[r] = valid ? cin[t0 + li] : make_float2(0.f, 0.f);
       dig[r] = (key[r] >> shift) & 255u;
       uint64_t m = ballot(valid);
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
 bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                       const uint32_t *n_dev, uint64_t n_cap, const uint32_t *gate,
                       uint32_t *hist, uint32_t *tot, int bit_begin, int bit_end, hipStream_t s,
-                      float2 *c0, float2 *c1, const uint32_t *skip) {
+                      float2 *c0, float2 *c1, const uint32_t *skip, bool iota) {
   // about one tile per block when the count reaches its bound
   uint64_t g = (n_cap + kSortTile - 1) / kSortTile;
   const unsigned nblk = (unsigned)(g < 1 ? 1 : (g > kChunkBlocks ? kChunkBlocks : g));
@@ -332,15 +332,16 @@ bool radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                        n_dev, gate, skip, shift, hist);
     hipLaunchKernelGGL(k_rs_hscan, dim3(256), dim3(kChunkBlocks), 0, s, hist, gate, skip, shift,
                        tot, nblk);
+    // the first pass makes the values when they are the input positions
+    const uint32_t *vr = iota && shift == bit_begin ? nullptr : vi;
     if (ci)
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nblk), dim3(kBlock), 0, s,
-                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
-                         (const float2 *)ci, co);
+                         (const uint32_t *)ki, vr, ko, vo, n_dev, gate, skip, shift,
+                         (const uint32_t *)hist, (const uint32_t *)tot, (const float2 *)ci, co);
     else
       hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nblk), dim3(kBlock), 0, s,
-                         (const uint32_t *)ki, (const uint32_t *)vi, ko, vo, n_dev, gate, skip,
-                         shift, (const uint32_t *)hist, (const uint32_t *)tot,
+                         (const uint32_t *)ki, vr, ko, vo, n_dev, gate, skip, shift,
+                         (const uint32_t *)hist, (const uint32_t *)tot,
                          (const float2 *)nullptr, (float2 *)nullptr);
     std::swap(ki, ko);
     std::swap(vi, vo);
