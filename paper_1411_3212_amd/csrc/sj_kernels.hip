@@ -1817,16 +1817,15 @@ __device__ __forceinline__ void write_half_staged(uint4 *wrect, uint32_t nk,
 // The write pass puts the results of the subqueries in subquery order: task
 // by task, the runs of a task's subqueries are adjacent, so the pass stores
 // its ids as one contiguous stream and reads its offsets in order; a
-// query's results are its slots' runs (slot_sq).
-__global__ void __launch_bounds__(kBlock) k_join_write(Ctl *ctl, const uint4 *trec,
-                                                       const uint32_t *tleaf,
-                                                       const uint32_t *__restrict__ sq,
-                                                       const float4 *__restrict__ qrect,
-                                                       const float2 *__restrict__ sxy,
-                                                       const uint32_t *__restrict__ sid,
-                                                       const uint64_t *__restrict__ res_off,
-                                                       uint32_t *__restrict__ res_ids,
-                                                       uint32_t nq, float *tlog) {
+// query's results are its slots' runs (slot_sq).  Six waves per SIMD (at
+// most 80 registers; twelve register chunks need 92 otherwise, five waves):
+// the compiler keeps two registers in scratch, and the extra wave per SIMD
+// hides more of the stores' latency.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
+k_join_write(Ctl *ctl, const uint4 *trec, const uint32_t *tleaf, const uint32_t *__restrict__ sq,
+             const float4 *__restrict__ qrect, const float2 *__restrict__ sxy,
+             const uint32_t *__restrict__ sid, const uint64_t *__restrict__ res_off,
+             uint32_t *__restrict__ res_ids, uint32_t nq, float *tlog) {
   __shared__ uint4 lrect[kBlock];
   __shared__ uint64_t loff[kBlock];
   __shared__ uint32_t lstage[kWavesPerBlock * kStage];
