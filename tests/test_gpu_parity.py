@@ -138,6 +138,31 @@ def test_edges_corners_signed_zero_and_degenerate_queries():
         assert sc.fetch().to_lists() == want
 
 
+@pytest.mark.parametrize("n", [32, 33, 64, 65, 511, 512, 513, 767, 768, 769, 1536, 1537, 2000])
+def test_leaf_sizes_around_the_register_blocks(n):
+    """One leaf of n objects (the threshold above n) queried by 150 random
+    rectangles, so that a task holds 64 subqueries and a leaf several tasks:
+    the half-wave rounds (at most 32 objects), every chunk count of a
+    one-block task (up to 12 chunks, 768 objects) and the multi-block tasks
+    beyond, each with a full and a partial last chunk."""
+    rng = np.random.default_rng(n)
+    x = rng.random(n).astype(F32)
+    y = rng.random(n).astype(F32)
+    nq = 150
+    c = rng.random((nq, 2))
+    h = rng.uniform(0.02, 0.6, (nq, 2))
+    rects = tuple(a.astype(F32) for a in (c[:, 0] - h[:, 0], c[:, 1] - h[:, 1],
+                                           c[:, 0] + h[:, 0], c[:, 1] + h[:, 1]))
+    t = T(ids=range(n), x=x, y=y, qid=rng.integers(0, n, nq), rects=rects)
+    st = oracle.State(n)
+    oracle_apply(st, t)
+    want = oracle_lists(st, t)
+    say(f"leaf sizes n={n}")
+    sc = run_scene(n, t, th=1_000_000, capacity_subqueries=4 * nq, capacity_results=n * nq)
+    assert sc.stats()["n_leaves"] == 1
+    assert sc.fetch().to_lists() == want
+
+
 def test_absent_objects_superseded_queries_and_empty_scenes():
     # objects 0..9, only the even ones have a position; queries by object 3
     # twice (only the last is answered) and by absent object 5
