@@ -140,26 +140,29 @@ def test_edges_corners_signed_zero_and_degenerate_queries():
 
 @pytest.mark.parametrize("n", [32, 33, 64, 65, 511, 512, 513, 767, 768, 769, 1536, 1537, 2000])
 def test_leaf_sizes_around_the_register_blocks(n):
-    """One leaf of n objects (the threshold above n) queried by 150 random
-    rectangles, so that a task holds 64 subqueries and a leaf several tasks:
-    the half-wave rounds (at most 32 objects), every chunk count of a
-    one-block task (up to 12 chunks, 768 objects) and the multi-block tasks
-    beyond, each with a full and a partial last chunk."""
+    """A leaf of n objects (a cluster in the lower-left level-1 quadrant, one
+    more object in the opposite corner, the threshold above n) queried by
+    150 random rectangles, so that a task holds 64 subqueries and the leaf
+    several tasks: the half-wave rounds (at most 32 objects), every chunk
+    count of a one-block task (up to 12 chunks, 768 objects) and the
+    multi-block tasks beyond, each with a full and a partial last chunk."""
     rng = np.random.default_rng(n)
-    x = rng.random(n).astype(F32)
-    y = rng.random(n).astype(F32)
+    x = np.append(rng.uniform(0.1, 0.3, n), 0.9).astype(F32)
+    y = np.append(rng.uniform(0.1, 0.3, n), 0.9).astype(F32)
     nq = 150
-    c = rng.random((nq, 2))
-    h = rng.uniform(0.02, 0.6, (nq, 2))
+    c = rng.uniform(0.1, 0.3, (nq, 2))
+    h = rng.uniform(0.005, 0.12, (nq, 2))
     rects = tuple(a.astype(F32) for a in (c[:, 0] - h[:, 0], c[:, 1] - h[:, 1],
                                            c[:, 0] + h[:, 0], c[:, 1] + h[:, 1]))
-    t = T(ids=range(n), x=x, y=y, qid=rng.integers(0, n, nq), rects=rects)
-    st = oracle.State(n)
+    t = T(ids=range(n + 1), x=x, y=y, qid=rng.integers(0, n, nq), rects=rects)
+    st = oracle.State(n + 1)
     oracle_apply(st, t)
+    codes, _ = oracle.sorted_codes(st, oracle.frame(st))
+    assert int(oracle.quadtree(codes, 1_000_000, 16).count.max()) == n  # the construction
     want = oracle_lists(st, t)
     say(f"leaf sizes n={n}")
-    sc = run_scene(n, t, th=1_000_000, capacity_subqueries=4 * nq, capacity_results=n * nq)
-    assert sc.stats()["n_leaves"] == 1
+    sc = run_scene(n + 1, t, th=1_000_000, capacity_subqueries=4 * nq,
+                   capacity_results=(n + 1) * nq)
     assert sc.fetch().to_lists() == want
 
 
