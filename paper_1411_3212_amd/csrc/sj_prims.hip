@@ -236,19 +236,43 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t *__restric
     goff[tid] = base + hist[tid * kChunkBlocks + blockIdx.x];
   }
   __syncthreads();
+  // without a carried payload, a tile's inputs are loaded while the
+  // previous tile is placed and stored, so that waiting for them does not
+  // also wait for those stores (with one, the registers for it would cost
+  // half the waves)
+  constexpr bool kAhead = !CARRY;
+  uint32_t nkey[kSortItems], nval[kSortItems];
+  float2 ncar[kSortItems];
+  auto load_tile = [&](uint64_t t0) {
+    const uint32_t tn = (uint32_t)((b1 - t0) < (uint64_t)kSortTile ? (b1 - t0) : kSortTile);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const uint32_t li = r * kBlock + tid;
+      const bool valid = li < tn;
+      nkey[r] = valid ? kin[t0 + li] : 0u;
+      nval[r] = !valid ? 0u : vin ? vin[t0 + li] : (uint32_t)(t0 + li);
+      if (CARRY) ncar[r] = valid ? cin[t0 + li] : make_float2(0.f, 0.f);
+    }
+  };
+  if (kAhead) load_tile(b0);
   for (uint64_t t0 = b0; t0 < b1; t0 += kSortTile) {
     const uint32_t tile_n = (uint32_t)((b1 - t0) < (uint64_t)kSortTile ? (b1 - t0) : kSortTile);
     for (int i = tid; i < kCnt; i += kBlock) cnt[i] = 0;
     __syncthreads();
     uint32_t key[kSortItems], val[kSortItems], dig[kSortItems], rank[kSortItems];
     float2 car[kSortItems];
+    if (!kAhead) load_tile(t0);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      key[r] = nkey[r];
+      val[r] = nval[r];
+      if (CARRY) car[r] = ncar[r];
+    }
+    if (kAhead && t0 + kSortTile < b1) load_tile(t0 + kSortTile);
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       const uint32_t li = r * kBlock + tid;
       const bool valid = li < tile_n;
-      key[r] = valid ? kin[t0 + li] : 0u;
-      val[r] = !valid ? 0u : vin ? vin[t0 + li] : (uint32_t)(t0 + li);
-      if (CARRY) car[r] = valid ? cin[t0 + li] : make_float2(0.f, 0.f);
       dig[r] = (key[r] >> shift) & 255u;
       uint64_t m = ballot(valid);
 #pragma unroll
