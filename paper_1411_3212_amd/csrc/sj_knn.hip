@@ -10,10 +10,14 @@
 //              holds its k nearest objects.  The smallest quadrant holding
 //              the point with at least k objects (its leaf, or an ancestor:
 //              a run of whole leaves in Morton order, one range of the
-//              sorted objects) gives the half side: the k-th smallest
-//              distance to its objects (an upper bound of the k-th nearest
-//              distance over all objects), or for a quadrant of more than
-//              kKnnScanMax objects the distance to its farthest corner.
+//              sorted objects) gives the half side: a distance within
+//              which k of its objects lie (an upper bound of the k-th
+//              nearest distance over all objects): every lane keeps the
+//              smallest distance of the objects it scans, and the k-th
+//              smallest of those 64 minima belongs to k distinct objects
+//              (k <= 64, and at least k lanes scan one); for a quadrant of
+//              more than kKnnScanMax objects, the distance to its farthest
+//              corner.
 //   range      the tick's split, schedule and join on those squares:
 //              candidates as runs of ids and covering leaves.
 //   select     per query, one wave: the k smallest keys among the
@@ -38,7 +42,7 @@ namespace sj {
 
 constexpr uint64_t kNoKey = ~0ull;  // an empty slot (above every real key)
 // Quadrants of at most this many objects bound a query's k-th distance by
-// their own k-th distance; larger ones by their farthest corner.
+// their objects' distances; larger ones by their farthest corner.
 constexpr uint32_t kKnnScanMax = 4096;
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
@@ -91,7 +95,8 @@ __device__ __forceinline__ uint64_t knn_key(float d2, uint32_t id) {
   return ((uint64_t)__float_as_uint(d2) << 32) | id;
 }
 
-// The same for 32-bit keys (the radius needs the k-th distance only).
+// The same for 32-bit keys, ascending across the lanes (the radius needs
+// distances only).
 __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v, uint32_t lane) {
 #pragma unroll
   for (uint32_t size = 2; size <= (uint32_t)kWave; size <<= 1) {
@@ -103,20 +108,6 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t v, uint32_t lane) {
     }
   }
   return v;
-}
-__device__ __forceinline__ uint32_t topk_add32(uint32_t best, uint32_t key, uint32_t k,
-                                               uint32_t lane) {
-  const uint32_t kth = (uint32_t)__shfl((int)best, (int)(k - 1u), kWave);
-  if (!ballot(key < kth)) return best;
-  const uint32_t b = wave_sort_u32(key, lane);
-  const uint32_t r = (uint32_t)__shfl((int)b, (int)((uint32_t)kWave - 1u - lane), kWave);
-  uint32_t c = r < best ? r : best;
-#pragma unroll
-  for (uint32_t j = (uint32_t)kWave >> 1; j > 0; j >>= 1) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)c, (int)j, kWave);
-    c = (lane & j) == 0 ? (o < c ? o : c) : (o > c ? o : c);
-  }
-  return c;
 }
 
 // Adds a batch (one key per lane, kNoKey for none) to the wave's list when
@@ -188,15 +179,16 @@ __global__ void __launch_bounds__(kBlock) k_knn_radius(
         lq = l;
       }
       if (oe - ob >= k && oe - ob <= kKnnScanMax) {
-        // the k-th smallest distance to the quadrant's objects (binary32
-        // bits of d2 >= 0 order like the values)
-        uint32_t best = 0xffffffffu;
+        // the k-th smallest of the lanes' smallest distances (binary32 bits
+        // of d2 >= 0 order like the values; a lane without objects keeps
+        // the largest key)
+        uint32_t m = 0xffffffffu;
         for (uint32_t i0 = ob; i0 < oe; i0 += kWave) {
           const uint32_t i = i0 + lane;
-          const uint32_t key = i < oe ? __float_as_uint(knn_d2(sxy[i], x, y)) : 0xffffffffu;
-          best = topk_add32(best, key, k, lane);
+          if (i < oe) m = min(m, __float_as_uint(knn_d2(sxy[i], x, y)));
         }
-        const float d2k = __uint_as_float((uint32_t)__shfl((int)best, (int)(k - 1u), kWave));
+        const uint32_t srt = wave_sort_u32(m, lane);
+        const float d2k = __uint_as_float((uint32_t)__shfl((int)srt, (int)(k - 1u), kWave));
         h = sqrt((double)d2k) * (1.0 + 1.0 / 1024.0);
       } else if (oe - ob >= k) {
         // a large quadrant: its farthest corner from the point
