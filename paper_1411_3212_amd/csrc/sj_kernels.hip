@@ -1069,7 +1069,8 @@ __global__ void __launch_bounds__(kBlock) k_q_write(
     tr.tlev = ctl->tlev;
     const uint32_t lane = lane_id(), gl = lane & (kSplitGroup - 1u);
     const uint64_t gm = ((1ull << kSplitGroup) - 1ull) << (lane - gl);
-    // one XCD's queries write neighbouring slots (grid: kChunkBlocks)
+    // one XCD's queries write neighbouring slots (the grid is a multiple of
+    // kXcds)
     const Sweep sw = xcd_sweep(nq, kBlock / kSplitGroup, threadIdx.x / kSplitGroup);
     for (uint32_t g = sw.first; g < sw.end; g += sw.stride) {
       const uint32_t n = q_ni[g] + q_nc[g];
@@ -2070,8 +2071,11 @@ const uint32_t *launch_split(const Bufs &B, uint32_t nq, uint32_t covering, hipS
   // slot_sq; the sort by leaf makes the slots as its values, ping-pongs
   // through res_off's memory and ends where it started (values in sq)
   uint32_t *skey = B.sq_cnt, *sval = B.sq, *k1 = (uint32_t *)B.res_off, *v1 = k1 + B.S;
-  static_assert(kChunkBlocks % kXcds == 0, "k_q_write sweeps per XCD");
-  LAUNCH(k_q_write, kChunkBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
+  // 16 queries per block and 4,096 blocks: enough groups in flight to hide
+  // a query's three dependent loads (counts, offsets, its list)
+  constexpr unsigned kQWriteBlocks = 4096;
+  static_assert(kQWriteBlocks % kXcds == 0, "k_q_write sweeps per XCD");
+  LAUNCH(k_q_write, kQWriteBlocks, kBlock, s, B.ctl, tin, nq, B.N, (const uint64_t *)B.qstamp,
          tree_of(B), (const uint32_t *)B.leaf_beg, (const float4 *)B.qrect,
          (const uint32_t *)B.q_ioff, (const uint32_t *)B.q_coff, (const uint32_t *)B.q_ni,
          (const uint32_t *)B.q_nc, (const uint32_t *)B.qlist, B.slots, skey, B.slot_sq,
